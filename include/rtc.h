@@ -1,0 +1,209 @@
+/*
+ * rtc.h - C ABI of the MI355X adaptive-optics real-time-controller hot path.
+ *
+ * The library turns wavefront-sensor pixels into deformable-mirror commands,
+ * one frame at a time, following the four per-sensor stages of the paper
+ * (Jenkins, Basden & Myers, "A many-core CPU prototype of an MCAO and LTAO RTC
+ * for ELT-scale instruments", section 1.1 figure of the AO-loop processes):
+ *
+ *   calibration  -> slopes (Shack-Hartmann centre of gravity, section 2.2, or
+ *                   pyramid normalised quadrant differences, section 2.2)
+ *                -> reconstruction (one dense control-matrix x slope MVM,
+ *                   section 2.3), summed over every sensor of an instance
+ *                   (section 3, partial commands summed on the master)
+ *                -> DM command (leaky integrator, plus the implicit
+ *                   pseudo-open-loop term M a_{f-1}, section 3.4).
+ *
+ * Pixels arrive as row chunks of a camera readout (section 2.2: slopes can be
+ * computed as soon as the rows they need have arrived), so the matrix product
+ * of a chunk's slopes overlaps the readout of later chunks.
+ *
+ * Conventions for every call:
+ *  - Every pointer argument is owned by the caller and is only read (or
+ *    written) during the call, unless stated otherwise.  "host" pointers are
+ *    ordinary CPU memory; "device" pointers are HIP device memory of the
+ *    engine's GPU.
+ *  - Calls return an rtc_status; nothing throws across the ABI.  A device
+ *    error is sticky: once RTC_E_DEVICE is returned, every later call on the
+ *    engine returns it, except rtc_destroy.
+ *  - Arrays are row-major and densely packed.
+ */
+#ifndef RTC_H
+#define RTC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtc_engine rtc_engine;
+
+typedef enum {
+    RTC_OK = 0,
+    RTC_E_INVAL = -1,          /* bad argument, size or ordering */
+    RTC_E_NOMEM = -2,          /* host or device allocation failed */
+    RTC_E_DEVICE = -3,         /* HIP runtime or kernel error (sticky) */
+    RTC_E_TIMEOUT = -4,        /* wait expired before the frame completed */
+    RTC_E_STATE = -5,          /* call not valid in the current state */
+    RTC_E_RING_FULL = -6,      /* pixel ring has no free slot */
+    RTC_E_FRAME_DROPPED = -7   /* the frame was superseded before completing */
+} rtc_status;
+
+enum { RTC_WFS_SH = 0, RTC_WFS_PYR = 1 };
+/* Control-matrix storage: FP32, BF16 (round to nearest even) or OCP FP8
+ * e4m3fn with one FP32 scale per matrix row (scale_r = max_j |R_rj| / 448).
+ * Accumulation is FP32 in every case. */
+enum { RTC_CM_F32 = 0, RTC_CM_BF16 = 1, RTC_CM_FP8 = 2 };
+/* Threshold after calibration, c = ((raw - dark) * flat) - bg in binary32:
+ * SUBTRACT: w = c > T ? c - T : 0;  ZERO: w = c > T ? c : 0;  NONE: w = c. */
+enum { RTC_THR_SUBTRACT = 0, RTC_THR_ZERO = 1, RTC_THR_NONE = 2 };
+/* STREAM: each chunk submission enqueues its own kernels on the engine stream.
+ * PERSISTENT: one resident kernel polls the pinned pixel ring and runs the
+ * whole frame loop on the device. */
+enum { RTC_MODE_STREAM = 0, RTC_MODE_PERSISTENT = 1 };
+
+#define RTC_MAX_WFS 16
+#define RTC_MAX_INST 8
+
+typedef struct {
+    int32_t kind;                 /* RTC_WFS_SH or RTC_WFS_PYR */
+    int32_t frame_h, frame_w;     /* uint16 pixels */
+    int32_t n_chunks;             /* chunk c holds rows [c*H/n, (c+1)*H/n) (floor) */
+    int32_t thr_mode;             /* RTC_THR_* */
+    /* Shack-Hartmann: nsub x nsub subapertures of px x px pixels whose first
+     * pixel is at (origin_row, origin_col). */
+    int32_t nsub, px, origin_row, origin_col;
+    const uint8_t *subap_valid;   /* host, nsub*nsub flags, raster order */
+    /* Pyramid: four pupil images of pupil_px x pupil_px pixels, image q at
+     * (quad_row[q], quad_col[q]); q = 0..3 are I1..I4 of
+     * Sx = (I1 + I2 - I3 - I4) / S, Sy = (I1 + I3 - I2 - I4) / S. */
+    int32_t pupil_px;
+    int32_t quad_row[4], quad_col[4];
+    const uint8_t *pupil_valid;   /* host, pupil_px*pupil_px flags */
+} rtc_wfs_desc;
+
+typedef struct {
+    int32_t n_wfs;                /* 1..RTC_MAX_WFS */
+    const rtc_wfs_desc *wfs;      /* host, n_wfs entries */
+    int32_t n_act;                /* command length */
+    int32_t cm_dtype;             /* RTC_CM_* */
+    int32_t polc;                 /* 1: implicit pseudo-open-loop term on */
+    float gain, leak;
+} rtc_instance_desc;
+
+typedef struct {
+    int32_t device;               /* HIP device ordinal */
+    int32_t n_inst;               /* 1..RTC_MAX_INST */
+    const rtc_instance_desc *inst;
+    int32_t ring_depth;           /* frames buffered per sensor (>= 2) */
+    int32_t mode;                 /* RTC_MODE_* */
+} rtc_create_desc;
+
+typedef struct {
+    uint64_t frame;               /* frame number the commands belong to */
+    int64_t t_last_chunk_ns;      /* host CLOCK_MONOTONIC at the last chunk's submission */
+    int64_t t_ready_ns;           /* host CLOCK_MONOTONIC when the commands were seen */
+    uint64_t dev_ticks_start;     /* device 100 MHz clock: last chunk seen */
+    uint64_t dev_ticks_cmd;       /* device 100 MHz clock: commands published */
+    uint32_t drops;               /* frames dropped on this instance so far */
+    uint32_t reserved;
+} rtc_frame_info;
+
+typedef struct {
+    int32_t n_wfs;
+    int32_t n_units;              /* subapertures (SH) plus pupil pixels (pyramid) */
+    int32_t n_slopes;             /* 2 * n_units */
+    int32_t n_act;
+    int32_t n_kblocks;            /* (sensor, chunk) column blocks of the matrix */
+    int32_t mask_words;           /* uint64 mask words over all units (rtc_read_slopes) */
+    int64_t cm_bytes;             /* bytes of the stored matrix, padding included */
+    int64_t cm_bytes_logical;     /* n_act * n_slopes * element size (+ scales) */
+    int64_t polc_bytes;           /* bytes of the stored POLC matrix (0 if off) */
+} rtc_instance_info;
+
+/* Engine lifetime. rtc_create copies the descriptors; subap/pupil maps are
+ * read during the call only.  Allocates every device and pinned host buffer
+ * the frame loop uses; nothing is allocated afterwards while frames run. */
+rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out);
+rtc_status rtc_destroy(rtc_engine *e);
+const char *rtc_strerror(rtc_status s);
+rtc_status rtc_get_info(rtc_engine *e, int32_t inst, rtc_instance_info *info);
+/* Row range [row_begin, row_end) of chunk `chunk` of sensor `wfs`. */
+rtc_status rtc_chunk_rows(rtc_engine *e, int32_t inst, int32_t wfs, int32_t chunk,
+                          int32_t *row_begin, int32_t *row_end);
+
+/* Control matrix R (host, n_act x n_slopes, FP32, slopes ordered sensor by
+ * sensor, units in raster order, (x, y) interleaved).  The library encodes R
+ * in the instance's storage type and re-tiles it on the device.  With POLC
+ * on, give either D (host, n_slopes x n_act, FP64), and M = R.D is formed
+ * once in FP64 on the device from the FP32 R, or M itself (host, n_act x
+ * n_act, FP32).  M is stored in FP32.  Resets the command state. */
+rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R,
+                             const double *D, const float *M);
+
+/* Detector calibration of one sensor (host FP32 arrays, each nullable):
+ * dark, flat, bg: frame_h x frame_w (defaults 0, 1, 0); thr: one value per
+ * subaperture (SH) or one value (pyramid) (default 0); ref: reference slopes,
+ * 2 per unit (default 0). */
+rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs,
+                                const float *dark, const float *flat, const float *bg,
+                                const float *thr, const float *ref);
+
+/* Stage new gain and leak in the inactive parameter slot (section 3.2: double
+ * buffered parameters).  They take effect from frame *f_eff_out, the first
+ * frame whose processing has not started; no frame is blocked. */
+rtc_status rtc_set_params(rtc_engine *e, int32_t inst, float gain, float leak,
+                          uint64_t *f_eff_out);
+
+/* Command state: a (n_act) and the POLC term p for the next frame (n_act),
+ * host FP32.  rtc_set_state with NULL pointers zeroes them. */
+rtc_status rtc_get_state(rtc_engine *e, int32_t inst, float *a, float *p, uint64_t *next_frame);
+rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const float *p,
+                         uint64_t next_frame);
+
+/* Serving path.  Submit chunk `chunk` of frame `frame` of sensor `wfs`
+ * (host rows: the chunk's rows, frame_w uint16 each).  Chunks of one frame
+ * and sensor must come in increasing order (else RTC_E_INVAL).  A frame
+ * number below the frame in progress gives RTC_E_FRAME_DROPPED; starting a
+ * newer frame before the current one completed drops the current one.  The
+ * frame's commands are produced once every chunk of every sensor of the
+ * instance has been submitted. */
+rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                                  int32_t chunk, const uint16_t *rows);
+/* Wait up to timeout_ns for the commands of `frame` and copy them to cmds
+ * (host, n_act FP32).  info (nullable) receives the frame's timestamps. */
+rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float *cmds,
+                             int64_t timeout_ns, rtc_frame_info *info);
+
+/* Batch path over device-resident frames: runs n_frames consecutive frames
+ * through the whole hot path, in order, updating the command state exactly as
+ * the serving path would.  frames[w] (device) points at n_frames frames of
+ * sensor w spaced frame_stride[w] uint16 apart.  Outputs (device, nullable):
+ * cmds n_frames x n_act, slopes n_frames x n_slopes, counts n_frames x n_units.
+ * Work is enqueued on `stream` (a hipStream_t; NULL = the engine's stream)
+ * and the call returns without waiting. */
+rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const *frames,
+                              const int64_t *frame_stride, int32_t n_frames,
+                              float *cmds, float *slopes, int32_t *counts, void *stream);
+
+/* Slopes, per-unit counts of thresholded pixels and the thresholded-pixel
+ * masks of the most recent frame (host, each nullable).  masks: mask_words
+ * uint64; unit u's pixels, raster order within the subaperture, are bits of
+ * consecutive words starting at a 64-bit boundary; a pyramid unit has one
+ * word whose bits 0..3 are I1..I4.  Synchronises the engine stream. */
+rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
+                           uint64_t *masks);
+/* Stored control matrix in logical order (host): codes n_act x n_slopes of
+ * 4, 2 or 1 bytes per element, and for FP8 the n_act row scales. */
+rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scales);
+
+/* Timing aid: enqueue the reconstruction MVM alone (every column block, on
+ * the current slopes) n_iter times on `stream`.  Changes no command state. */
+rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTC_H */

@@ -1,0 +1,1055 @@
+// Host runtime and C ABI of the real-time-controller hot path.
+//
+// Owns every device and pinned buffer of an engine, builds the unit and
+// column-block tables from the sensor geometry, encodes and re-tiles the
+// control matrix, and drives the gfx950 kernels either per chunk (stream
+// mode) or over device-resident frame batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "rtc.h"
+#include "rtc_internal.h"
+
+using namespace rtc;
+
+namespace {
+
+int64_t now_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
+}
+
+int elem_size(int dt) { return dt == RTC_CM_F32 ? 4 : dt == RTC_CM_BF16 ? 2 : 1; }
+int elems_per_vec(int dt) { return 16 / elem_size(dt); }
+
+// ---------------------------------------------------------------- encoders
+uint16_t bf16_rne(float f) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    const uint32_t lsb = (b >> 16) & 1u;
+    return (uint16_t)((b + 0x7FFFu + lsb) >> 16);
+}
+
+// OCP e4m3fn, round to nearest with ties to even, for |f| <= 448.
+uint8_t fp8_rne(float f) {
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    const uint8_t sign = (uint8_t)((b >> 24) & 0x80u);
+    const uint32_t mag = b & 0x7FFFFFFFu;
+    float a;
+    std::memcpy(&a, &mag, 4);
+    uint32_t code;
+    if (a < 0.015625f) {                       // below 2^-6: subnormal binade, quantum 2^-9
+        code = (uint32_t)std::nearbyint(a * 512.0f);   // exact scaling, ties to even
+    } else {
+        const int e = (int)(mag >> 23) - 127;  // -6 .. 8
+        const uint32_t m23 = mag & 0x7FFFFFu;
+        const uint32_t m3 = (m23 + 0x7FFFFu + ((m23 >> 20) & 1u)) >> 20;   // may carry to 8
+        code = (uint32_t)((e + 7) << 3) + m3;
+    }
+    return (uint8_t)(sign | code);
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- engine state
+struct WfsState {
+    rtc_wfs_desc d{};
+    std::vector<uint8_t> valid;
+    int u0 = 0, u1 = 0;            // unit range in the instance
+    int kind0 = 0;                 // first index in the SH or pyramid unit list
+    std::vector<int> row0;         // chunk row starts, n_chunks + 1 entries
+    std::vector<int> kb_of_chunk;  // column block produced by each chunk, or -1
+    std::vector<int> unit_ready;   // last frame row each unit needs (per unit)
+    // serving
+    int next_chunk = 0;
+    uint16_t *d_ring = nullptr;    // ring_depth frames on the device
+    uint16_t *h_stage = nullptr;   // pinned staging ring (ring_depth frames)
+};
+
+struct FrameSlot {
+    uint64_t frame = ~0ull;
+    bool complete = false;         // work enqueued
+    bool dropped = false;
+    hipEvent_t done = nullptr;
+    int64_t t_last_chunk = 0;
+};
+
+struct Instance {
+    rtc_instance_desc d{};
+    std::vector<WfsState> wfs;
+    int n_units = 0, n_slopes = 0, n_act = 0, n_sh = 0, n_pyr = 0;
+    int mask_words = 0;
+    std::vector<ShUnit> sh;
+    std::vector<PyrUnit> py;
+    std::vector<KBlock> kb;        // reconstruction column blocks
+    std::vector<KBlock> kbm;       // POLC column blocks
+    int spad_len = 0;
+    int64_t cm_bytes = 0, m_bytes = 0;
+    WfsParamSet params{};
+    // device
+    ShUnit *d_sh = nullptr;
+    PyrUnit *d_py = nullptr;
+    KBlock *d_kb = nullptr, *d_kbm = nullptr;
+    float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
+    float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
+    float *d_ref = nullptr;
+    float *d_spad = nullptr, *d_sout = nullptr;
+    int32_t *d_counts = nullptr;
+    uint64_t *d_masks = nullptr;
+    uint8_t *d_cm = nullptr;
+    float *d_scale = nullptr;
+    uint8_t *d_M = nullptr;
+    float *d_ypart = nullptr, *d_ppart = nullptr;
+    float *d_a = nullptr;          // command state, padded to the POLC block size
+    int a_len = 0;
+    bool loaded = false;
+    // parameters: two slots, the staged one becomes active at frame f_switch
+    float gain[2] = {0, 0}, leak[2] = {0, 0};
+    int active = 0;
+    bool pending = false;
+    uint64_t f_switch = 0;
+    uint64_t next_frame = 0;       // next frame the batch path processes
+    uint32_t drops = 0;
+    // serving
+    uint64_t cur_frame = ~0ull;
+    bool cur_started = false;
+    std::vector<FrameSlot> slots;
+    float *h_mail = nullptr;       // pinned, ring_depth x n_act
+    std::mutex mu;
+};
+
+struct rtc_engine {
+    int device = 0;
+    int ring_depth = 2;
+    int mode = RTC_MODE_STREAM;
+    hipStream_t stream = nullptr;
+    std::vector<Instance *> inst;
+    std::vector<DevBuf> allocs;
+    std::vector<void *> pinned;
+    std::atomic<int> sticky{RTC_OK};
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                \
+    do {                                                                             \
+        hipError_t _e = (expr);                                                      \
+        if (_e != hipSuccess) {                                                      \
+            std::fprintf(stderr, "rtc: %s failed: %s (%s:%d)\n", #expr,              \
+                         hipGetErrorString(_e), __FILE__, __LINE__);                 \
+            return RTC_E_DEVICE;                                                     \
+        }                                                                            \
+    } while (0)
+
+template <class T>
+rtc_status dev_alloc(rtc_engine *e, T **p, size_t count) {
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    if (hipMalloc(&q, bytes) != hipSuccess) return RTC_E_NOMEM;
+    if (hipMemset(q, 0, bytes) != hipSuccess) return RTC_E_DEVICE;
+    e->allocs.push_back({q, bytes});
+    *p = static_cast<T *>(q);
+    return RTC_OK;
+}
+
+template <class T>
+rtc_status host_pinned(rtc_engine *e, T **p, size_t count) {
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(count * sizeof(T), 64);
+    if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return RTC_E_NOMEM;
+    std::memset(q, 0, bytes);
+    e->pinned.push_back(q);
+    *p = static_cast<T *>(q);
+    return RTC_OK;
+}
+
+rtc_status fail(rtc_engine *e, rtc_status s) {
+    if (s == RTC_E_DEVICE && e) e->sticky.store(RTC_E_DEVICE);
+    return s;
+}
+
+#define TRY(expr)                                                                    \
+    do {                                                                             \
+        rtc_status _s = (expr);                                                      \
+        if (_s != RTC_OK) return fail(e, _s);                                        \
+    } while (0)
+
+int chunk_row(int H, int n, int c) { return (int)(((int64_t)c * H) / n); }
+
+rtc_status validate_wfs(const rtc_wfs_desc &w) {
+    if (w.frame_h <= 0 || w.frame_w <= 0 || w.n_chunks <= 0 || w.n_chunks > w.frame_h)
+        return RTC_E_INVAL;
+    if (w.thr_mode < RTC_THR_SUBTRACT || w.thr_mode > RTC_THR_NONE) return RTC_E_INVAL;
+    if (w.kind == RTC_WFS_SH) {
+        if (w.nsub <= 0 || w.px <= 0 || w.px > 64 || !w.subap_valid) return RTC_E_INVAL;
+        if (w.origin_row < 0 || w.origin_col < 0) return RTC_E_INVAL;
+        if (w.origin_row + (int64_t)w.nsub * w.px > w.frame_h) return RTC_E_INVAL;
+        if (w.origin_col + (int64_t)w.nsub * w.px > w.frame_w) return RTC_E_INVAL;
+    } else if (w.kind == RTC_WFS_PYR) {
+        if (w.pupil_px <= 0 || !w.pupil_valid) return RTC_E_INVAL;
+        for (int q = 0; q < 4; ++q) {
+            if (w.quad_row[q] < 0 || w.quad_col[q] < 0) return RTC_E_INVAL;
+            if (w.quad_row[q] + w.pupil_px > w.frame_h) return RTC_E_INVAL;
+            if (w.quad_col[q] + w.pupil_px > w.frame_w) return RTC_E_INVAL;
+        }
+    } else {
+        return RTC_E_INVAL;
+    }
+    return RTC_OK;
+}
+
+// Geometry -> units, chunk readiness, column blocks, padded slope layout.
+rtc_status build_instance(rtc_engine *e, Instance *I) {
+    const int E = elems_per_vec(I->d.cm_dtype);
+    int unit = 0, mask = 0;
+    for (int w = 0; w < (int)I->wfs.size(); ++w) {
+        WfsState &S = I->wfs[w];
+        const rtc_wfs_desc &d = S.d;
+        S.u0 = unit;
+        WfsParam &P = I->params.w[w];
+        P.kind = d.kind;
+        P.W = d.frame_w;
+        P.H = d.frame_h;
+        P.thr_mode = d.thr_mode;
+        S.row0.resize(d.n_chunks + 1);
+        for (int c = 0; c <= d.n_chunks; ++c) S.row0[c] = chunk_row(d.frame_h, d.n_chunks, c);
+        if (d.kind == RTC_WFS_SH) {
+            P.p = d.px;
+            P.half = 0.5f * (float)(d.px - 1);
+            P.mask_words = (d.px * d.px + 63) / 64;
+            S.kind0 = (int)I->sh.size();
+            for (int i = 0; i < d.nsub; ++i)
+                for (int j = 0; j < d.nsub; ++j) {
+                    if (!S.valid[(size_t)i * d.nsub + j]) continue;
+                    ShUnit u{};
+                    u.row0 = d.origin_row + i * d.px;
+                    u.col0 = d.origin_col + j * d.px;
+                    u.wfs = w;
+                    u.unit = unit++;
+                    u.mask = mask;
+                    mask += P.mask_words;
+                    I->sh.push_back(u);
+                    S.unit_ready.push_back(u.row0 + d.px - 1);
+                }
+        } else {
+            P.p = 0;
+            P.mask_words = 1;
+            for (int q = 0; q < 4; ++q) {
+                P.qrow[q] = d.quad_row[q];
+                P.qcol[q] = d.quad_col[q];
+            }
+            int qmax = 0;
+            for (int q = 0; q < 4; ++q) qmax = std::max(qmax, d.quad_row[q]);
+            S.kind0 = (int)I->py.size();
+            for (int i = 0; i < d.pupil_px; ++i)
+                for (int j = 0; j < d.pupil_px; ++j) {
+                    if (!S.valid[(size_t)i * d.pupil_px + j]) continue;
+                    PyrUnit u{};
+                    u.i = i;
+                    u.j = j;
+                    u.wfs = w;
+                    u.unit = unit++;
+                    u.mask = mask;
+                    mask += 1;
+                    I->py.push_back(u);
+                    S.unit_ready.push_back(qmax + i);
+                }
+        }
+        S.u1 = unit;
+        if (S.u1 == S.u0) return RTC_E_INVAL;    // a sensor without units
+    }
+    I->n_units = unit;
+    I->n_slopes = 2 * unit;
+    I->mask_words = mask;
+    I->n_sh = (int)I->sh.size();
+    I->n_pyr = (int)I->py.size();
+    // calibration offsets of SH units: p*p values each, in unit order
+    {
+        int off = 0;
+        for (auto &u : I->sh) {
+            u.cal = off;
+            off += I->params.w[u.wfs].p * I->params.w[u.wfs].p;
+        }
+    }
+    // column blocks: units become ready in raster order, so each chunk
+    // completes a contiguous unit range of its sensor
+    int spad = 0;
+    int64_t base = 0;
+    const int n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
+    for (int w = 0; w < (int)I->wfs.size(); ++w) {
+        WfsState &S = I->wfs[w];
+        S.kb_of_chunk.assign(S.d.n_chunks, -1);
+        int next = 0;     // next unit (relative) not yet assigned
+        const int nu = S.u1 - S.u0;
+        for (int c = 0; c < S.d.n_chunks; ++c) {
+            const int last_row = S.row0[c + 1] - 1;
+            int end = next;
+            while (end < nu && S.unit_ready[end] <= last_row) ++end;
+            if (end == next) continue;
+            KBlock K{};
+            K.k0 = 2 * (S.u0 + next);
+            K.k = 2 * (end - next);
+            K.kv = (K.k + E - 1) / E;
+            K.spad = spad;
+            K.base = base;
+            K.wfs = w;
+            K.chunk = c;
+            // map units to padded slope indices
+            for (int u = next; u < end; ++u) {
+                const int gu = S.u0 + u;
+                const int pad = spad + 2 * (u - next);
+                if (S.d.kind == RTC_WFS_SH)
+                    I->sh[S.kind0 + u].pad = pad;
+                else
+                    I->py[S.kind0 + u].pad = pad;
+                (void)gu;
+            }
+            S.kb_of_chunk[c] = (int)I->kb.size();
+            I->kb.push_back(K);
+            spad += ((K.kv * E + 15) / 16) * 16;    // 64-byte aligned block starts
+            base += (int64_t)n_tiles * kTileRows * K.kv * 16;
+            next = end;
+        }
+        if (next != nu) return RTC_E_INVAL;
+    }
+    // the last tile of each block holds fewer rows; trim the allocation to the
+    // real end of the last block
+    {
+        const int last_nr = I->n_act - (n_tiles - 1) * kTileRows;
+        const KBlock &L = I->kb.back();
+        I->cm_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
+                      (int64_t)last_nr * L.kv * 16;
+    }
+    I->spad_len = spad;
+    // POLC column blocks of kPolcBlock commands, F32
+    if (I->d.polc) {
+        const int nb = (I->n_act + kPolcBlock - 1) / kPolcBlock;
+        int64_t mb = 0;
+        for (int b = 0; b < nb; ++b) {
+            KBlock K{};
+            K.k0 = b * kPolcBlock;
+            K.k = std::min(kPolcBlock, I->n_act - K.k0);
+            K.kv = (K.k + 3) / 4;
+            K.spad = K.k0;
+            K.base = mb;
+            mb += (int64_t)n_tiles * kTileRows * K.kv * 16;
+            I->kbm.push_back(K);
+        }
+        const int last_nr = I->n_act - (n_tiles - 1) * kTileRows;
+        const KBlock &L = I->kbm.back();
+        I->m_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
+                     (int64_t)last_nr * L.kv * 16;
+        I->a_len = nb * kPolcBlock;
+    } else {
+        I->a_len = I->n_act;
+    }
+    (void)e;
+    return RTC_OK;
+}
+
+rtc_status alloc_instance(rtc_engine *e, Instance *I) {
+    const size_t nkb = I->kb.size();
+    TRY(dev_alloc(e, &I->d_sh, std::max<size_t>(I->sh.size(), 1)));
+    TRY(dev_alloc(e, &I->d_py, std::max<size_t>(I->py.size(), 1)));
+    TRY(dev_alloc(e, &I->d_kb, nkb));
+    TRY(dev_alloc(e, &I->d_kbm, std::max<size_t>(I->kbm.size(), 1)));
+    size_t sh_px = 0;
+    for (auto &u : I->sh) sh_px += (size_t)I->params.w[u.wfs].p * I->params.w[u.wfs].p;
+    TRY(dev_alloc(e, &I->d_sh_dark, sh_px));
+    TRY(dev_alloc(e, &I->d_sh_flat, sh_px));
+    TRY(dev_alloc(e, &I->d_sh_bg, sh_px));
+    TRY(dev_alloc(e, &I->d_sh_thr, I->sh.size()));
+    TRY(dev_alloc(e, &I->d_py_dark, 4 * I->py.size()));
+    TRY(dev_alloc(e, &I->d_py_flat, 4 * I->py.size()));
+    TRY(dev_alloc(e, &I->d_py_bg, 4 * I->py.size()));
+    TRY(dev_alloc(e, &I->d_py_thr, I->py.size()));
+    TRY(dev_alloc(e, &I->d_ref, I->n_slopes));
+    TRY(dev_alloc(e, &I->d_spad, I->spad_len));
+    TRY(dev_alloc(e, &I->d_sout, I->n_slopes));
+    TRY(dev_alloc(e, &I->d_counts, I->n_units));
+    TRY(dev_alloc(e, &I->d_masks, I->mask_words));
+    TRY(dev_alloc(e, &I->d_cm, (size_t)I->cm_bytes));
+    TRY(dev_alloc(e, &I->d_scale, I->n_act));
+    if (I->d.polc) {
+        TRY(dev_alloc(e, &I->d_M, (size_t)I->m_bytes));
+        TRY(dev_alloc(e, &I->d_ppart, I->kbm.size() * (size_t)I->n_act));
+    }
+    TRY(dev_alloc(e, &I->d_ypart, nkb * (size_t)I->n_act));
+    TRY(dev_alloc(e, &I->d_a, I->a_len));
+    HIP_TRY(hipMemcpy(I->d_sh, I->sh.data(), I->sh.size() * sizeof(ShUnit), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I->d_py, I->py.data(), I->py.size() * sizeof(PyrUnit), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I->d_kb, I->kb.data(), nkb * sizeof(KBlock), hipMemcpyHostToDevice));
+    if (!I->kbm.empty())
+        HIP_TRY(hipMemcpy(I->d_kbm, I->kbm.data(), I->kbm.size() * sizeof(KBlock),
+                          hipMemcpyHostToDevice));
+    // default calibration: dark 0, flat 1, bg 0, threshold 0, reference 0
+    std::vector<float> ones(std::max(sh_px, 4 * I->py.size()), 1.0f);
+    HIP_TRY(hipMemcpy(I->d_sh_flat, ones.data(), sh_px * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I->d_py_flat, ones.data(), 4 * I->py.size() * 4, hipMemcpyHostToDevice));
+    std::vector<float> one_scale(I->n_act, 1.0f);
+    HIP_TRY(hipMemcpy(I->d_scale, one_scale.data(), I->n_act * 4, hipMemcpyHostToDevice));
+    // serving buffers
+    for (auto &S : I->wfs) {
+        const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
+        TRY(dev_alloc(e, &S.d_ring, fpx * e->ring_depth));
+        TRY(host_pinned(e, &S.h_stage, fpx * e->ring_depth));
+    }
+    TRY(host_pinned(e, &I->h_mail, (size_t)e->ring_depth * I->n_act));
+    I->slots.resize(e->ring_depth);
+    for (auto &sl : I->slots) HIP_TRY(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    return RTC_OK;
+}
+
+float active_gain(const Instance *I, uint64_t f) {
+    const int s = (I->pending && f >= I->f_switch) ? 1 - I->active : I->active;
+    return I->gain[s];
+}
+float active_leak(const Instance *I, uint64_t f) {
+    const int s = (I->pending && f >= I->f_switch) ? 1 - I->active : I->active;
+    return I->leak[s];
+}
+// Retire the staged slot once frame f uses it.
+void settle_params(Instance *I, uint64_t f) {
+    if (I->pending && f >= I->f_switch) {
+        I->active = 1 - I->active;
+        I->pending = false;
+    }
+}
+
+// Coefficients of a_f = c1 a_{f-1} + g (y + p).
+void coeffs(const Instance *I, uint64_t f, float *c1, float *g) {
+    const double gd = active_gain(I, f), ld = active_leak(I, f);
+    *g = (float)gd;
+    *c1 = I->d.polc ? (float)(1.0 - ld - gd) : (float)(1.0 - ld);
+}
+
+void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, int u_begin,
+                      int u_end) {
+    WfsState &S = I->wfs[w];
+    if (S.d.kind == RTC_WFS_SH) {
+        const int a = S.kind0 + (u_begin - S.u0), b = S.kind0 + (u_end - S.u0);
+        launch_sh_centroid(st, I->d_sh, a, b, fs, I->params, I->d_sh_dark, I->d_sh_flat,
+                           I->d_sh_bg, I->d_sh_thr, I->d_ref, I->d_spad, I->d_sout,
+                           I->d_counts, I->d_masks);
+    } else {
+        const int a = S.kind0 + (u_begin - S.u0), b = S.kind0 + (u_end - S.u0);
+        launch_pyr_slopes(st, I->d_py, a, b, I->n_pyr, fs, I->params, I->d_py_dark,
+                          I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, I->d_spad,
+                          I->d_sout, I->d_counts, I->d_masks);
+    }
+}
+
+// Integrator + POLC precompute for frame f (slopes and partials in place).
+void enqueue_finish(Instance *I, hipStream_t st, uint64_t f, float *out) {
+    float c1, g;
+    coeffs(I, f, &c1, &g);
+    settle_params(I, f);
+    launch_integrate(st, I->d_ypart, (int)I->kb.size(), I->d.polc ? I->d_ppart : nullptr,
+                     (int)I->kbm.size(), I->n_act,
+                     I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr, I->d_a, I->d_a, out, c1,
+                     g);
+}
+
+void enqueue_polc(Instance *I, hipStream_t st) {
+    if (!I->d.polc) return;
+    launch_mvm(st, RTC_CM_F32, I->d_M, I->d_kbm, 0, (int)I->kbm.size(), I->n_act, I->d_a,
+               I->d_ppart);
+}
+
+rtc_status check(rtc_engine *e, int32_t inst, Instance **out) {
+    if (!e) return RTC_E_INVAL;
+    if (e->sticky.load() != RTC_OK) return (rtc_status)e->sticky.load();
+    if (inst < 0 || inst >= (int)e->inst.size()) return RTC_E_INVAL;
+    *out = e->inst[inst];
+    return RTC_OK;
+}
+
+rtc_status last_error(rtc_engine *e) {
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        std::fprintf(stderr, "rtc: kernel launch failed: %s\n", hipGetErrorString(err));
+        return fail(e, RTC_E_DEVICE);
+    }
+    return RTC_OK;
+}
+
+// Encode R (n_act x n_s, FP32, row-major) into the tiled storage layout.
+void encode_matrix(const Instance *I, const float *R, int dt, const float *inv_scale_unused,
+                   const std::vector<float> &scale, std::vector<uint8_t> &out,
+                   const std::vector<KBlock> &blocks, int n_cols, int64_t bytes) {
+    (void)inv_scale_unused;
+    out.assign((size_t)bytes, 0);
+    const int es = elem_size(dt), E = 16 / es;
+    const int n_rows = I->n_act;
+    const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
+    const int nthreads = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int th = 0; th < nthreads; ++th) {
+        pool.emplace_back([&, th]() {
+            for (int t = th; t < n_tiles; t += nthreads) {
+                const int nr = std::min(kTileRows, n_rows - t * kTileRows);
+                for (const KBlock &K : blocks) {
+                    uint8_t *blk = out.data() + K.base + (int64_t)t * kTileRows * K.kv * 16;
+                    for (int l = 0; l < nr; ++l) {
+                        const int r = t * kTileRows + l;
+                        const float *row = R + (size_t)r * n_cols;
+                        for (int v = 0; v < K.kv; ++v) {
+                            uint8_t *dst = blk + ((size_t)v * nr + l) * 16;
+                            for (int el = 0; el < E; ++el) {
+                                const int c = v * E + el;
+                                if (c >= K.k) break;
+                                const float x = row[K.k0 + c];
+                                if (dt == RTC_CM_F32) {
+                                    std::memcpy(dst + 4 * el, &x, 4);
+                                } else if (dt == RTC_CM_BF16) {
+                                    const uint16_t h = bf16_rne(x);
+                                    std::memcpy(dst + 2 * el, &h, 2);
+                                } else {
+                                    float q = x / scale[r];
+                                    q = std::min(448.0f, std::max(-448.0f, q));
+                                    dst[el] = fp8_rne(q);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        });
+    }
+    for (auto &t : pool) t.join();
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+const char *rtc_strerror(rtc_status s) {
+    switch (s) {
+    case RTC_OK: return "ok";
+    case RTC_E_INVAL: return "invalid argument";
+    case RTC_E_NOMEM: return "out of memory";
+    case RTC_E_DEVICE: return "device error";
+    case RTC_E_TIMEOUT: return "timeout";
+    case RTC_E_STATE: return "invalid state";
+    case RTC_E_RING_FULL: return "pixel ring full";
+    case RTC_E_FRAME_DROPPED: return "frame dropped";
+    }
+    return "unknown status";
+}
+
+rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
+    if (!desc || !out) return RTC_E_INVAL;
+    *out = nullptr;
+    if (desc->n_inst < 1 || desc->n_inst > RTC_MAX_INST || !desc->inst) return RTC_E_INVAL;
+    if (desc->ring_depth < 2 || desc->ring_depth > 64) return RTC_E_INVAL;
+    if (desc->mode != RTC_MODE_STREAM) return RTC_E_INVAL;
+    for (int i = 0; i < desc->n_inst; ++i) {
+        const rtc_instance_desc &d = desc->inst[i];
+        if (d.n_wfs < 1 || d.n_wfs > RTC_MAX_WFS || !d.wfs || d.n_act < 1) return RTC_E_INVAL;
+        if (d.cm_dtype < RTC_CM_F32 || d.cm_dtype > RTC_CM_FP8) return RTC_E_INVAL;
+        if (!std::isfinite(d.gain) || !std::isfinite(d.leak)) return RTC_E_INVAL;
+        for (int w = 0; w < d.n_wfs; ++w)
+            if (validate_wfs(d.wfs[w]) != RTC_OK) return RTC_E_INVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev)
+        return RTC_E_DEVICE;
+    rtc_engine *e = new (std::nothrow) rtc_engine();
+    if (!e) return RTC_E_NOMEM;
+    e->device = desc->device;
+    e->ring_depth = desc->ring_depth;
+    e->mode = desc->mode;
+    auto bail = [&](rtc_status s) {
+        rtc_destroy(e);
+        return s;
+    };
+    if (hipSetDevice(e->device) != hipSuccess) return bail(RTC_E_DEVICE);
+    if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(RTC_E_DEVICE);
+    for (int i = 0; i < desc->n_inst; ++i) {
+        Instance *I = new (std::nothrow) Instance();
+        if (!I) return bail(RTC_E_NOMEM);
+        e->inst.push_back(I);
+        I->d = desc->inst[i];
+        I->d.wfs = nullptr;
+        I->n_act = I->d.n_act;
+        I->gain[0] = I->gain[1] = I->d.gain;
+        I->leak[0] = I->leak[1] = I->d.leak;
+        I->wfs.resize(I->d.n_wfs);
+        for (int w = 0; w < I->d.n_wfs; ++w) {
+            WfsState &S = I->wfs[w];
+            S.d = desc->inst[i].wfs[w];
+            if (S.d.kind == RTC_WFS_SH) {
+                S.valid.assign(S.d.subap_valid, S.d.subap_valid + (size_t)S.d.nsub * S.d.nsub);
+                S.d.subap_valid = nullptr;
+            } else {
+                S.valid.assign(S.d.pupil_valid,
+                               S.d.pupil_valid + (size_t)S.d.pupil_px * S.d.pupil_px);
+                S.d.pupil_valid = nullptr;
+            }
+        }
+        rtc_status s = build_instance(e, I);
+        if (s != RTC_OK) return bail(s);
+        s = alloc_instance(e, I);
+        if (s != RTC_OK) return bail(s);
+    }
+    *out = e;
+    return RTC_OK;
+}
+
+rtc_status rtc_destroy(rtc_engine *e) {
+    if (!e) return RTC_E_INVAL;
+    (void)hipSetDevice(e->device);
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    for (Instance *I : e->inst) {
+        for (auto &sl : I->slots)
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        delete I;
+    }
+    for (auto &b : e->allocs) (void)hipFree(b.p);
+    for (void *p : e->pinned) (void)hipHostFree(p);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+    return RTC_OK;
+}
+
+rtc_status rtc_get_info(rtc_engine *e, int32_t inst, rtc_instance_info *info) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!info) return RTC_E_INVAL;
+    info->n_wfs = (int)I->wfs.size();
+    info->n_units = I->n_units;
+    info->n_slopes = I->n_slopes;
+    info->n_act = I->n_act;
+    info->n_kblocks = (int)I->kb.size();
+    info->mask_words = I->mask_words;
+    info->cm_bytes = I->cm_bytes;
+    info->cm_bytes_logical = (int64_t)I->n_act * I->n_slopes * elem_size(I->d.cm_dtype) +
+                             (I->d.cm_dtype == RTC_CM_FP8 ? 4LL * I->n_act : 0);
+    info->polc_bytes = I->m_bytes;
+    return RTC_OK;
+}
+
+rtc_status rtc_chunk_rows(rtc_engine *e, int32_t inst, int32_t wfs, int32_t chunk,
+                          int32_t *row_begin, int32_t *row_end) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (wfs < 0 || wfs >= (int)I->wfs.size()) return RTC_E_INVAL;
+    const WfsState &S = I->wfs[wfs];
+    if (chunk < 0 || chunk >= S.d.n_chunks || !row_begin || !row_end) return RTC_E_INVAL;
+    *row_begin = S.row0[chunk];
+    *row_end = S.row0[chunk + 1];
+    return RTC_OK;
+}
+
+rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const double *D,
+                             const float *M) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!R) return RTC_E_INVAL;
+    if (I->d.polc && !D && !M) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    const int na = I->n_act, ns = I->n_slopes;
+    const int dt = I->d.cm_dtype;
+    std::vector<float> scale(na, 1.0f);
+    if (dt == RTC_CM_FP8) {
+        for (int r = 0; r < na; ++r) {
+            float amax = 0.0f;
+            const float *row = R + (size_t)r * ns;
+            for (int c = 0; c < ns; ++c) amax = std::max(amax, std::fabs(row[c]));
+            if (!std::isfinite(amax)) return RTC_E_INVAL;
+            scale[r] = amax > 0.0f ? amax / 448.0f : 1.0f;
+        }
+    }
+    std::vector<uint8_t> enc;
+    encode_matrix(I, R, dt, nullptr, scale, enc, I->kb, ns, I->cm_bytes);
+    HIP_TRY(hipMemcpy(I->d_cm, enc.data(), enc.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(I->d_scale, scale.data(), na * 4, hipMemcpyHostToDevice));
+    enc.clear();
+    enc.shrink_to_fit();
+    if (I->d.polc) {
+        std::vector<float> Mf((size_t)na * na);
+        if (M) {
+            std::memcpy(Mf.data(), M, Mf.size() * 4);
+        } else {
+            // M = R.D in FP64 on the device, rounded once to FP32
+            float *dR = nullptr;
+            double *dD = nullptr, *dM = nullptr;
+            HIP_TRY(hipMalloc(&dR, (size_t)na * ns * 4));
+            HIP_TRY(hipMalloc(&dD, (size_t)ns * na * 8));
+            HIP_TRY(hipMalloc(&dM, (size_t)na * na * 8));
+            HIP_TRY(hipMemcpy(dR, R, (size_t)na * ns * 4, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(dD, D, (size_t)ns * na * 8, hipMemcpyHostToDevice));
+            launch_dgemm_rd(e->stream, dR, dD, dM, na, ns);
+            TRY(last_error(e));
+            HIP_TRY(hipStreamSynchronize(e->stream));
+            std::vector<double> Md((size_t)na * na);
+            HIP_TRY(hipMemcpy(Md.data(), dM, Md.size() * 8, hipMemcpyDeviceToHost));
+            (void)hipFree(dR);
+            (void)hipFree(dD);
+            (void)hipFree(dM);
+            for (size_t i = 0; i < Md.size(); ++i) Mf[i] = (float)Md[i];
+        }
+        std::vector<float> one(na, 1.0f);
+        encode_matrix(I, Mf.data(), RTC_CM_F32, nullptr, one, enc, I->kbm, na, I->m_bytes);
+        HIP_TRY(hipMemcpy(I->d_M, enc.data(), enc.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemset(I->d_ppart, 0, I->kbm.size() * (size_t)na * 4));
+    }
+    HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
+    HIP_TRY(hipMemset(I->d_spad, 0, (size_t)I->spad_len * 4));
+    I->next_frame = 0;
+    I->loaded = true;
+    return RTC_OK;
+}
+
+rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs, const float *dark,
+                                const float *flat, const float *bg, const float *thr,
+                                const float *ref) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (wfs < 0 || wfs >= (int)I->wfs.size()) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    WfsState &S = I->wfs[wfs];
+    const int W = S.d.frame_w;
+    auto pick = [](const float *m, size_t idx, float dflt) { return m ? m[idx] : dflt; };
+    if (S.d.kind == RTC_WFS_SH) {
+        const int p = S.d.px;
+        const int n = S.u1 - S.u0;
+        std::vector<float> dk((size_t)n * p * p), fl(dk.size()), bgv(dk.size()), th(n);
+        for (int k = 0; k < n; ++k) {
+            const ShUnit &u = I->sh[S.kind0 + k];
+            for (int i = 0; i < p * p; ++i) {
+                const size_t idx = (size_t)(u.row0 + i / p) * W + (u.col0 + i % p);
+                dk[(size_t)k * p * p + i] = pick(dark, idx, 0.0f);
+                fl[(size_t)k * p * p + i] = pick(flat, idx, 1.0f);
+                bgv[(size_t)k * p * p + i] = pick(bg, idx, 0.0f);
+            }
+            th[k] = pick(thr, k, 0.0f);
+        }
+        const size_t off = I->sh[S.kind0].cal;
+        HIP_TRY(hipMemcpy(I->d_sh_dark + off, dk.data(), dk.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_sh_flat + off, fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_sh_bg + off, bgv.data(), bgv.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_sh_thr + S.kind0, th.data(), th.size() * 4, hipMemcpyHostToDevice));
+    } else {
+        const int n = S.u1 - S.u0;
+        const int np = I->n_pyr;
+        std::vector<float> dk(4 * (size_t)np), fl(dk.size()), bgv(dk.size());
+        HIP_TRY(hipMemcpy(dk.data(), I->d_py_dark, dk.size() * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(fl.data(), I->d_py_flat, fl.size() * 4, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(bgv.data(), I->d_py_bg, bgv.size() * 4, hipMemcpyDeviceToHost));
+        std::vector<float> th(n, pick(thr, 0, 0.0f));
+        for (int k = 0; k < n; ++k) {
+            const PyrUnit &u = I->py[S.kind0 + k];
+            for (int q = 0; q < 4; ++q) {
+                const size_t idx = (size_t)(S.d.quad_row[q] + u.i) * W + (S.d.quad_col[q] + u.j);
+                dk[(size_t)q * np + S.kind0 + k] = pick(dark, idx, 0.0f);
+                fl[(size_t)q * np + S.kind0 + k] = pick(flat, idx, 1.0f);
+                bgv[(size_t)q * np + S.kind0 + k] = pick(bg, idx, 0.0f);
+            }
+        }
+        HIP_TRY(hipMemcpy(I->d_py_dark, dk.data(), dk.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_py_flat, fl.data(), fl.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_py_bg, bgv.data(), bgv.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(I->d_py_thr + S.kind0, th.data(), th.size() * 4, hipMemcpyHostToDevice));
+    }
+    std::vector<float> rf(2 * (size_t)(S.u1 - S.u0));
+    for (size_t i = 0; i < rf.size(); ++i) rf[i] = pick(ref, i, 0.0f);
+    HIP_TRY(hipMemcpy(I->d_ref + 2 * S.u0, rf.data(), rf.size() * 4, hipMemcpyHostToDevice));
+    return RTC_OK;
+}
+
+rtc_status rtc_set_params(rtc_engine *e, int32_t inst, float gain, float leak,
+                          uint64_t *f_eff_out) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!std::isfinite(gain) || !std::isfinite(leak)) return RTC_E_INVAL;
+    std::lock_guard<std::mutex> lk(I->mu);
+    // a still-pending change is replaced; the staged slot is the inactive one
+    const int s = 1 - I->active;
+    I->gain[s] = gain;
+    I->leak[s] = leak;
+    uint64_t f = I->next_frame;
+    if (I->cur_frame != ~0ull && I->cur_started) f = std::max(f, I->cur_frame + 1);
+    I->f_switch = f;
+    I->pending = true;
+    if (f_eff_out) *f_eff_out = f;
+    return RTC_OK;
+}
+
+rtc_status rtc_get_state(rtc_engine *e, int32_t inst, float *a, float *p, uint64_t *next_frame) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (a) HIP_TRY(hipMemcpy(a, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost));
+    if (p) {
+        if (I->d.polc) {
+            std::vector<float> part(I->kbm.size() * (size_t)I->n_act);
+            HIP_TRY(hipMemcpy(part.data(), I->d_ppart, part.size() * 4, hipMemcpyDeviceToHost));
+            for (int r = 0; r < I->n_act; ++r) {
+                float s = 0.0f;
+                for (size_t j = 0; j < I->kbm.size(); ++j) s += part[j * I->n_act + r];
+                p[r] = s;
+            }
+        } else {
+            std::memset(p, 0, I->n_act * 4);
+        }
+    }
+    if (next_frame) *next_frame = I->next_frame;
+    return RTC_OK;
+}
+
+rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const float *p,
+                         uint64_t next_frame) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
+    if (a) HIP_TRY(hipMemcpy(I->d_a, a, I->n_act * 4, hipMemcpyHostToDevice));
+    if (I->d.polc) {
+        HIP_TRY(hipMemset(I->d_ppart, 0, I->kbm.size() * (size_t)I->n_act * 4));
+        if (p) HIP_TRY(hipMemcpy(I->d_ppart, p, I->n_act * 4, hipMemcpyHostToDevice));
+    }
+    I->next_frame = next_frame;
+    I->cur_frame = ~0ull;
+    I->cur_started = false;
+    return RTC_OK;
+}
+
+rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const *frames,
+                              const int64_t *frame_stride, int32_t n_frames, float *cmds,
+                              float *slopes, int32_t *counts, void *stream) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!I->loaded) return RTC_E_STATE;
+    if (!frames || !frame_stride || n_frames < 0) return RTC_E_INVAL;
+    for (size_t w = 0; w < I->wfs.size(); ++w) {
+        if (!frames[w]) return RTC_E_INVAL;
+        if (n_frames > 1 && frame_stride[w] < (int64_t)I->wfs[w].d.frame_h * I->wfs[w].d.frame_w)
+            return RTC_E_INVAL;
+    }
+    HIP_TRY(hipSetDevice(e->device));
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : e->stream;
+    std::lock_guard<std::mutex> lk(I->mu);
+    for (int f = 0; f < n_frames; ++f) {
+        FrameSet fs{};
+        for (size_t w = 0; w < I->wfs.size(); ++w) fs.f[w] = frames[w] + (int64_t)f * frame_stride[w];
+        // every unit of every sensor, then every column block
+        if (I->n_sh > 0)
+            launch_sh_centroid(st, I->d_sh, 0, I->n_sh, fs, I->params, I->d_sh_dark,
+                               I->d_sh_flat, I->d_sh_bg, I->d_sh_thr, I->d_ref, I->d_spad,
+                               I->d_sout, I->d_counts, I->d_masks);
+        if (I->n_pyr > 0)
+            launch_pyr_slopes(st, I->d_py, 0, I->n_pyr, I->n_pyr, fs, I->params, I->d_py_dark,
+                              I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, I->d_spad,
+                              I->d_sout, I->d_counts, I->d_masks);
+        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, 0, (int)I->kb.size(), I->n_act,
+                   I->d_spad, I->d_ypart);
+        enqueue_finish(I, st, I->next_frame, cmds ? cmds + (size_t)f * I->n_act : nullptr);
+        enqueue_polc(I, st);
+        if (slopes)
+            HIP_TRY(hipMemcpyAsync(slopes + (size_t)f * I->n_slopes, I->d_sout, I->n_slopes * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        if (counts)
+            HIP_TRY(hipMemcpyAsync(counts + (size_t)f * I->n_units, I->d_counts, I->n_units * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        I->next_frame++;
+    }
+    return last_error(e);
+}
+
+rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!I->loaded) return RTC_E_STATE;
+    if (n_iter < 0) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : e->stream;
+    for (int i = 0; i < n_iter; ++i)
+        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, 0, (int)I->kb.size(), I->n_act,
+                   I->d_spad, I->d_ypart);
+    return last_error(e);
+}
+
+rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
+                           uint64_t *masks) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipDeviceSynchronize());
+    if (slopes) HIP_TRY(hipMemcpy(slopes, I->d_sout, I->n_slopes * 4, hipMemcpyDeviceToHost));
+    if (counts) HIP_TRY(hipMemcpy(counts, I->d_counts, I->n_units * 4, hipMemcpyDeviceToHost));
+    if (masks)
+        HIP_TRY(hipMemcpy(masks, I->d_masks, (size_t)I->mask_words * 8, hipMemcpyDeviceToHost));
+    return RTC_OK;
+}
+
+rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scales) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!I->loaded) return RTC_E_STATE;
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (codes) {
+        std::vector<uint8_t> enc((size_t)I->cm_bytes);
+        HIP_TRY(hipMemcpy(enc.data(), I->d_cm, enc.size(), hipMemcpyDeviceToHost));
+        const int es = elem_size(I->d.cm_dtype), E = 16 / es;
+        const int ns = I->n_slopes;
+        uint8_t *dst = static_cast<uint8_t *>(codes);
+        const int n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
+        for (int t = 0; t < n_tiles; ++t) {
+            const int nr = std::min(kTileRows, I->n_act - t * kTileRows);
+            for (const KBlock &K : I->kb) {
+                const uint8_t *blk = enc.data() + K.base + (int64_t)t * kTileRows * K.kv * 16;
+                for (int l = 0; l < nr; ++l) {
+                    const int r = t * kTileRows + l;
+                    for (int c = 0; c < K.k; ++c) {
+                        const int v = c / E, el = c % E;
+                        std::memcpy(dst + ((size_t)r * ns + K.k0 + c) * es,
+                                    blk + ((size_t)v * nr + l) * 16 + el * es, es);
+                    }
+                }
+            }
+        }
+    }
+    if (scales) HIP_TRY(hipMemcpy(scales, I->d_scale, I->n_act * 4, hipMemcpyDeviceToHost));
+    return RTC_OK;
+}
+
+// ------------------------------------------------------------- serving (stream mode)
+rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                                  int32_t chunk, const uint16_t *rows) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!I->loaded) return RTC_E_STATE;
+    if (wfs < 0 || wfs >= (int)I->wfs.size() || !rows) return RTC_E_INVAL;
+    WfsState &S = I->wfs[wfs];
+    if (chunk < 0 || chunk >= S.d.n_chunks) return RTC_E_INVAL;
+    std::lock_guard<std::mutex> lk(I->mu);
+    if (I->cur_frame != ~0ull && frame < I->cur_frame) return RTC_E_FRAME_DROPPED;
+    if (frame < I->next_frame) return RTC_E_FRAME_DROPPED;
+    if (I->cur_frame == ~0ull || frame > I->cur_frame) {
+        if (I->cur_frame != ~0ull && I->cur_started) {
+            // the frame in progress never completed: drop it
+            FrameSlot &old = I->slots[I->cur_frame % I->slots.size()];
+            old.dropped = true;
+            I->drops++;
+        }
+        FrameSlot &sl = I->slots[frame % I->slots.size()];
+        if (sl.frame != ~0ull) {
+            if (sl.complete) {
+                const hipError_t q = hipEventQuery(sl.done);
+                if (q == hipErrorNotReady) return RTC_E_RING_FULL;
+                if (q != hipSuccess) return fail(e, RTC_E_DEVICE);
+            } else {
+                // an abandoned frame may still have copies in flight from this slot
+                HIP_TRY(hipStreamSynchronize(e->stream));
+            }
+        }
+        I->cur_frame = frame;
+        I->cur_started = false;
+        for (auto &W : I->wfs) W.next_chunk = 0;
+        sl.frame = frame;
+        sl.complete = false;
+        sl.dropped = false;
+    }
+    if (chunk != S.next_chunk) return RTC_E_INVAL;
+    I->cur_started = true;
+    HIP_TRY(hipSetDevice(e->device));
+    const int slot = (int)(frame % (uint64_t)e->ring_depth);
+    const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
+    const int r0 = S.row0[chunk], r1 = S.row0[chunk + 1];
+    const size_t off = (size_t)slot * fpx + (size_t)r0 * S.d.frame_w;
+    const size_t n = (size_t)(r1 - r0) * S.d.frame_w;
+    std::memcpy(S.h_stage + off, rows, n * 2);
+    HIP_TRY(hipMemcpyAsync(S.d_ring + off, S.h_stage + off, n * 2, hipMemcpyHostToDevice,
+                           e->stream));
+    const int kb = S.kb_of_chunk[chunk];
+    if (kb >= 0) {
+        const KBlock &K = I->kb[kb];
+        FrameSet fs{};
+        for (size_t w = 0; w < I->wfs.size(); ++w)
+            fs.f[w] = I->wfs[w].d_ring + (size_t)slot * I->wfs[w].d.frame_h * I->wfs[w].d.frame_w;
+        const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
+        enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
+        launch_mvm(e->stream, I->d.cm_dtype, I->d_cm, I->d_kb, kb, 1, I->n_act, I->d_spad,
+                   I->d_ypart);
+    }
+    S.next_chunk++;
+    bool all = true;
+    for (auto &W : I->wfs) all = all && W.next_chunk == W.d.n_chunks;
+    if (all) {
+        FrameSlot &sl = I->slots[frame % I->slots.size()];
+        float *mail = I->h_mail + (size_t)slot * I->n_act;
+        enqueue_finish(I, e->stream, frame, nullptr);
+        HIP_TRY(hipMemcpyAsync(mail, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost, e->stream));
+        HIP_TRY(hipEventRecord(sl.done, e->stream));
+        enqueue_polc(I, e->stream);
+        sl.t_last_chunk = now_ns();
+        sl.complete = true;
+        I->next_frame = frame + 1;
+        I->cur_started = false;
+        I->cur_frame = ~0ull;
+    }
+    return last_error(e);
+}
+
+rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float *cmds,
+                             int64_t timeout_ns, rtc_frame_info *info) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!cmds) return RTC_E_INVAL;
+    const int64_t t0 = now_ns();
+    FrameSlot *sl = &I->slots[frame % I->slots.size()];
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(I->mu);
+            if (sl->frame == frame && sl->dropped) return RTC_E_FRAME_DROPPED;
+            if (sl->frame == frame && sl->complete) break;
+            if (sl->frame != ~0ull && sl->frame > frame) return RTC_E_FRAME_DROPPED;
+        }
+        if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
+        std::this_thread::yield();
+    }
+    for (;;) {
+        const hipError_t q = hipEventQuery(sl->done);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) return fail(e, RTC_E_DEVICE);
+        if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
+    }
+    const int64_t t_ready = now_ns();
+    const int slot = (int)(frame % (uint64_t)e->ring_depth);
+    std::memcpy(cmds, I->h_mail + (size_t)slot * I->n_act, I->n_act * 4);
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->frame = frame;
+        info->t_last_chunk_ns = sl->t_last_chunk;
+        info->t_ready_ns = t_ready;
+        info->drops = I->drops;
+    }
+    return RTC_OK;
+}
+
+}  // extern "C"
