@@ -182,8 +182,8 @@ rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float 
  * the serving path would.  frames[w] (device) points at n_frames frames of
  * sensor w spaced frame_stride[w] uint16 apart.  Outputs (device, nullable):
  * cmds n_frames x n_act, slopes n_frames x n_slopes, counts n_frames x n_units.
- * Work is enqueued on `stream` (a hipStream_t; NULL = the engine's stream)
- * and the call returns without waiting. */
+ * Work is enqueued on `stream` (a hipStream_t; NULL is the device's null
+ * stream) and the call returns without waiting. */
 rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const *frames,
                               const int64_t *frame_stride, int32_t n_frames,
                               float *cmds, float *slopes, int32_t *counts, void *stream);
@@ -200,7 +200,8 @@ rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *
 rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scales);
 
 /* Timing aid: enqueue the reconstruction MVM alone (every column block, on
- * the current slopes) n_iter times on `stream`.  Changes no command state. */
+ * the current slopes) n_iter times on `stream` (hipStream_t, NULL = null
+ * stream).  Changes no command state. */
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
 
 #ifdef __cplusplus

@@ -825,7 +825,8 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     Instance *I;
     TRY(check(e, inst, &I));
     HIP_TRY(hipSetDevice(e->device));
-    HIP_TRY(hipStreamSynchronize(e->stream));
+    HIP_TRY(hipDeviceSynchronize());
+    std::lock_guard<std::mutex> lk(I->mu);
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     if (a) HIP_TRY(hipMemcpy(I->d_a, a, I->n_act * 4, hipMemcpyHostToDevice));
     if (I->d.polc) {
@@ -835,6 +836,12 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     I->next_frame = next_frame;
     I->cur_frame = ~0ull;
     I->cur_started = false;
+    for (auto &sl : I->slots) {
+        sl.frame = ~0ull;
+        sl.complete = false;
+        sl.dropped = false;
+    }
+    for (auto &W : I->wfs) W.next_chunk = 0;
     return RTC_OK;
 }
 
@@ -851,7 +858,7 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             return RTC_E_INVAL;
     }
     HIP_TRY(hipSetDevice(e->device));
-    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : e->stream;
+    hipStream_t st = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(I->mu);
     for (int f = 0; f < n_frames; ++f) {
         FrameSet fs{};
@@ -886,7 +893,7 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     if (!I->loaded) return RTC_E_STATE;
     if (n_iter < 0) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
-    hipStream_t st = stream ? static_cast<hipStream_t>(stream) : e->stream;
+    hipStream_t st = static_cast<hipStream_t>(stream);
     for (int i = 0; i < n_iter; ++i)
         launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, 0, (int)I->kb.size(), I->n_act,
                    I->d_spad, I->d_ypart);
@@ -941,6 +948,7 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
 // ------------------------------------------------------------- serving (stream mode)
 rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
                                   int32_t chunk, const uint16_t *rows) {
+    const int64_t t_in = now_ns();
     Instance *I;
     TRY(check(e, inst, &I));
     if (!I->loaded) return RTC_E_STATE;
@@ -1007,7 +1015,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         HIP_TRY(hipMemcpyAsync(mail, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost, e->stream));
         HIP_TRY(hipEventRecord(sl.done, e->stream));
         enqueue_polc(I, e->stream);
-        sl.t_last_chunk = now_ns();
+        sl.t_last_chunk = t_in;
         sl.complete = true;
         I->next_frame = frame + 1;
         I->cur_started = false;
