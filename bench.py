@@ -220,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -253,6 +255,15 @@ def main():
                         "gbs_warm": alg / warm / 1e9, "gbs_cold": alg / cold / 1e9})
         log(f"bench: {dtype}: {res}")
         return eng, res
+
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copy probe: 5 x {src.numel() * 4} bytes read and written")
+        del src, dst
 
     eng, main_res = one(args.dtype, True)
     variants = {}

@@ -72,8 +72,8 @@ typedef struct {
     int32_t frame_h, frame_w;     /* uint16 pixels */
     int32_t n_chunks;             /* chunk c holds rows [c*H/n, (c+1)*H/n) (floor) */
     int32_t thr_mode;             /* RTC_THR_* */
-    /* Shack-Hartmann: nsub x nsub subapertures of px x px pixels whose first
-     * pixel is at (origin_row, origin_col). */
+    /* Shack-Hartmann: nsub x nsub subapertures of px x px pixels (px <= 16)
+     * whose first pixel is at (origin_row, origin_col). */
     int32_t nsub, px, origin_row, origin_col;
     const uint8_t *subap_valid;   /* host, nsub*nsub flags, raster order */
     /* Pyramid: four pupil images of pupil_px x pupil_px pixels, image q at

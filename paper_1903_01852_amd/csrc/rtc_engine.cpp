@@ -100,6 +100,10 @@ struct Instance {
     std::vector<PyrUnit> py;
     std::vector<KBlock> kb;        // reconstruction column blocks
     std::vector<KBlock> kbm;       // POLC column blocks
+    std::vector<Segment> seg, segm;            // segments: reconstruction, POLC
+    std::vector<Piece> pieces, pieces_m;       // equal-length pieces (whole frame)
+    std::vector<Piece> single;                 // one piece per reconstruction segment
+    std::vector<int> kb_seg0, kb_nseg;         // segments of each column block
     int spad_len = 0;
     int64_t cm_bytes = 0, m_bytes = 0;
     WfsParamSet params{};
@@ -107,6 +111,8 @@ struct Instance {
     ShUnit *d_sh = nullptr;
     PyrUnit *d_py = nullptr;
     KBlock *d_kb = nullptr, *d_kbm = nullptr;
+    Segment *d_seg = nullptr, *d_segm = nullptr;
+    Piece *d_pieces = nullptr, *d_pieces_m = nullptr, *d_single = nullptr;
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
     float *d_ref = nullptr;
@@ -118,7 +124,14 @@ struct Instance {
     uint8_t *d_M = nullptr;
     float *d_ypart = nullptr, *d_ppart = nullptr;
     float *d_a = nullptr;          // command state, padded to the POLC block size
+    float *d_p = nullptr;          // POLC term for the next frame, M a
+    float *d_yscratch = nullptr;   // destination of the timing-only MVM
+    uint32_t *d_count = nullptr;   // per-tile arrival counters: reconstruction
+    uint32_t *d_count_m = nullptr; //                            POLC
+    uint32_t *d_count_t = nullptr; //                            timing MVM
+    int n_tiles = 0;
     int a_len = 0;
+    float frame_c1 = 0, frame_g = 0;   // coefficients of the frame in progress (serving)
     bool loaded = false;
     // parameters: two slots, the staged one becomes active at frame f_switch
     float gain[2] = {0, 0}, leak[2] = {0, 0};
@@ -198,7 +211,7 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
         return RTC_E_INVAL;
     if (w.thr_mode < RTC_THR_SUBTRACT || w.thr_mode > RTC_THR_NONE) return RTC_E_INVAL;
     if (w.kind == RTC_WFS_SH) {
-        if (w.nsub <= 0 || w.px <= 0 || w.px > 64 || !w.subap_valid) return RTC_E_INVAL;
+        if (w.nsub <= 0 || w.px <= 0 || w.px > kMaxShPx || !w.subap_valid) return RTC_E_INVAL;
         if (w.origin_row < 0 || w.origin_col < 0) return RTC_E_INVAL;
         if (w.origin_row + (int64_t)w.nsub * w.px > w.frame_h) return RTC_E_INVAL;
         if (w.origin_col + (int64_t)w.nsub * w.px > w.frame_w) return RTC_E_INVAL;
@@ -213,6 +226,36 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
         return RTC_E_INVAL;
     }
     return RTC_OK;
+}
+
+// Cut the concatenated vector range of the blocks into pieces of about
+// `target` vectors, but at least `min_pieces` of them; a piece's
+// intersections with blocks are its segments.
+void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces,
+                    std::vector<Segment> &seg, std::vector<Piece> &pieces) {
+    int64_t V = 0;
+    std::vector<int64_t> start(kbs.size() + 1, 0);
+    for (size_t b = 0; b < kbs.size(); ++b) {
+        start[b] = V;
+        V += kbs[b].kv;
+    }
+    start[kbs.size()] = V;
+    const int64_t P = std::min<int64_t>(V, std::max<int64_t>(min_pieces, (V + target / 2) / target));
+    size_t b = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t lo = p * V / P;
+        const int64_t hi = (p + 1) * V / P;
+        if (lo == hi) continue;
+        Piece pc{(int32_t)seg.size(), 0};
+        while (lo < hi) {
+            while (start[b + 1] <= lo) ++b;
+            const int64_t end = std::min(hi, start[b + 1]);
+            seg.push_back(Segment{(int32_t)b, (int32_t)(lo - start[b]), (int32_t)(end - lo), 0});
+            lo = end;
+        }
+        pc.nseg = (int32_t)seg.size() - pc.seg0;
+        pieces.push_back(pc);
+    }
 }
 
 // Geometry -> units, chunk readiness, column blocks, padded slope layout.
@@ -338,6 +381,16 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                       (int64_t)last_nr * L.kv * 16;
     }
     I->spad_len = spad;
+    const int min_pieces = (kMinMvmWaves + n_tiles - 1) / n_tiles;
+    build_segments(I->kb, kPieceVectors, min_pieces, I->seg, I->pieces);
+    I->kb_seg0.assign(I->kb.size(), 0);
+    I->kb_nseg.assign(I->kb.size(), 0);
+    for (size_t i = 0; i < I->seg.size(); ++i) {
+        const int b = I->seg[i].kb;
+        if (I->kb_nseg[b] == 0) I->kb_seg0[b] = (int)i;
+        I->kb_nseg[b]++;
+        I->single.push_back(Piece{(int32_t)i, 1});
+    }
     // POLC column blocks of kPolcBlock commands, F32
     if (I->d.polc) {
         const int nb = (I->n_act + kPolcBlock - 1) / kPolcBlock;
@@ -357,6 +410,8 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->m_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
                      (int64_t)last_nr * L.kv * 16;
         I->a_len = nb * kPolcBlock;
+        build_segments(I->kbm, kPieceVectors, (kMinMvmWaves + n_tiles - 1) / n_tiles, I->segm,
+                       I->pieces_m);
     } else {
         I->a_len = I->n_act;
     }
@@ -370,6 +425,11 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_py, std::max<size_t>(I->py.size(), 1)));
     TRY(dev_alloc(e, &I->d_kb, nkb));
     TRY(dev_alloc(e, &I->d_kbm, std::max<size_t>(I->kbm.size(), 1)));
+    TRY(dev_alloc(e, &I->d_seg, I->seg.size()));
+    TRY(dev_alloc(e, &I->d_single, I->single.size()));
+    TRY(dev_alloc(e, &I->d_pieces, I->pieces.size()));
+    TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
+    TRY(dev_alloc(e, &I->d_pieces_m, std::max<size_t>(I->pieces_m.size(), 1)));
     size_t sh_px = 0;
     for (auto &u : I->sh) sh_px += (size_t)I->params.w[u.wfs].p * I->params.w[u.wfs].p;
     TRY(dev_alloc(e, &I->d_sh_dark, sh_px));
@@ -389,16 +449,30 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_scale, I->n_act));
     if (I->d.polc) {
         TRY(dev_alloc(e, &I->d_M, (size_t)I->m_bytes));
-        TRY(dev_alloc(e, &I->d_ppart, I->kbm.size() * (size_t)I->n_act));
+        TRY(dev_alloc(e, &I->d_ppart, I->segm.size() * (size_t)I->n_act));
     }
-    TRY(dev_alloc(e, &I->d_ypart, nkb * (size_t)I->n_act));
+    TRY(dev_alloc(e, &I->d_ypart, I->seg.size() * (size_t)I->n_act));
     TRY(dev_alloc(e, &I->d_a, I->a_len));
+    TRY(dev_alloc(e, &I->d_p, I->n_act));
+    TRY(dev_alloc(e, &I->d_yscratch, I->n_act));
+    I->n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
+    TRY(dev_alloc(e, &I->d_count, I->n_tiles));
+    TRY(dev_alloc(e, &I->d_count_m, I->n_tiles));
+    TRY(dev_alloc(e, &I->d_count_t, I->n_tiles));
     HIP_TRY(hipMemcpy(I->d_sh, I->sh.data(), I->sh.size() * sizeof(ShUnit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(I->d_py, I->py.data(), I->py.size() * sizeof(PyrUnit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(I->d_kb, I->kb.data(), nkb * sizeof(KBlock), hipMemcpyHostToDevice));
     if (!I->kbm.empty())
         HIP_TRY(hipMemcpy(I->d_kbm, I->kbm.data(), I->kbm.size() * sizeof(KBlock),
                           hipMemcpyHostToDevice));
+    auto up = [](void *dst, const void *src, size_t bytes) {
+        return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    HIP_TRY(up(I->d_seg, I->seg.data(), I->seg.size() * sizeof(Segment)));
+    HIP_TRY(up(I->d_single, I->single.data(), I->single.size() * sizeof(Piece)));
+    HIP_TRY(up(I->d_pieces, I->pieces.data(), I->pieces.size() * sizeof(Piece)));
+    HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));
+    HIP_TRY(up(I->d_pieces_m, I->pieces_m.data(), I->pieces_m.size() * sizeof(Piece)));
     // default calibration: dark 0, flat 1, bg 0, threshold 0, reference 0
     std::vector<float> ones(std::max(sh_px, 4 * I->py.size()), 1.0f);
     HIP_TRY(hipMemcpy(I->d_sh_flat, ones.data(), sh_px * 4, hipMemcpyHostToDevice));
@@ -456,21 +530,32 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
     }
 }
 
-// Integrator + POLC precompute for frame f (slopes and partials in place).
-void enqueue_finish(Instance *I, hipStream_t st, uint64_t f, float *out) {
-    float c1, g;
-    coeffs(I, f, &c1, &g);
-    settle_params(I, f);
-    launch_integrate(st, I->d_ypart, (int)I->kb.size(), I->d.polc ? I->d_ppart : nullptr,
-                     (int)I->kbm.size(), I->n_act,
-                     I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr, I->d_a, I->d_a, out, c1,
-                     g);
+// Epilogue of the reconstruction MVM: integrate frame f's commands.
+MvmEpilogue integrate_epi(Instance *I, float c1, float g, float *out) {
+    MvmEpilogue E{};
+    E.mode = EPI_INTEGRATE;
+    E.n_parts = (int)I->seg.size();
+    E.count = I->d_count;
+    E.p = I->d.polc ? I->d_p : nullptr;
+    E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr;
+    E.a = I->d_a;
+    E.out = out;
+    E.c1 = c1;
+    E.g = g;
+    return E;
 }
 
+// POLC term for the next frame: p = M a (section 3.4: formed after the
+// command is ready, off the latency path of the next frame).
 void enqueue_polc(Instance *I, hipStream_t st) {
     if (!I->d.polc) return;
-    launch_mvm(st, RTC_CM_F32, I->d_M, I->d_kbm, 0, (int)I->kbm.size(), I->n_act, I->d_a,
-               I->d_ppart);
+    MvmEpilogue E{};
+    E.mode = EPI_REDUCE;
+    E.n_parts = (int)I->segm.size();
+    E.count = I->d_count_m;
+    E.y = I->d_p;
+    launch_mvm(st, RTC_CM_F32, I->d_M, I->d_kbm, I->d_segm, I->d_pieces_m, 0,
+               (int)I->pieces_m.size(), I->n_act, I->d_a, I->d_ppart, E);
 }
 
 rtc_status check(rtc_engine *e, int32_t inst, Instance **out) {
@@ -712,8 +797,9 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
         std::vector<float> one(na, 1.0f);
         encode_matrix(I, Mf.data(), RTC_CM_F32, nullptr, one, enc, I->kbm, na, I->m_bytes);
         HIP_TRY(hipMemcpy(I->d_M, enc.data(), enc.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemset(I->d_ppart, 0, I->kbm.size() * (size_t)na * 4));
     }
+    HIP_TRY(hipMemset(I->d_p, 0, (size_t)na * 4));
+    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     HIP_TRY(hipMemset(I->d_spad, 0, (size_t)I->spad_len * 4));
     I->next_frame = 0;
@@ -803,19 +889,7 @@ rtc_status rtc_get_state(rtc_engine *e, int32_t inst, float *a, float *p, uint64
     HIP_TRY(hipSetDevice(e->device));
     HIP_TRY(hipStreamSynchronize(e->stream));
     if (a) HIP_TRY(hipMemcpy(a, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost));
-    if (p) {
-        if (I->d.polc) {
-            std::vector<float> part(I->kbm.size() * (size_t)I->n_act);
-            HIP_TRY(hipMemcpy(part.data(), I->d_ppart, part.size() * 4, hipMemcpyDeviceToHost));
-            for (int r = 0; r < I->n_act; ++r) {
-                float s = 0.0f;
-                for (size_t j = 0; j < I->kbm.size(); ++j) s += part[j * I->n_act + r];
-                p[r] = s;
-            }
-        } else {
-            std::memset(p, 0, I->n_act * 4);
-        }
-    }
+    if (p) HIP_TRY(hipMemcpy(p, I->d_p, I->n_act * 4, hipMemcpyDeviceToHost));
     if (next_frame) *next_frame = I->next_frame;
     return RTC_OK;
 }
@@ -829,10 +903,9 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     std::lock_guard<std::mutex> lk(I->mu);
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     if (a) HIP_TRY(hipMemcpy(I->d_a, a, I->n_act * 4, hipMemcpyHostToDevice));
-    if (I->d.polc) {
-        HIP_TRY(hipMemset(I->d_ppart, 0, I->kbm.size() * (size_t)I->n_act * 4));
-        if (p) HIP_TRY(hipMemcpy(I->d_ppart, p, I->n_act * 4, hipMemcpyHostToDevice));
-    }
+    HIP_TRY(hipMemset(I->d_p, 0, (size_t)I->n_act * 4));
+    if (p && I->d.polc) HIP_TRY(hipMemcpy(I->d_p, p, I->n_act * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
     I->next_frame = next_frame;
     I->cur_frame = ~0ull;
     I->cur_started = false;
@@ -872,9 +945,12 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             launch_pyr_slopes(st, I->d_py, 0, I->n_pyr, I->n_pyr, fs, I->params, I->d_py_dark,
                               I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, I->d_spad,
                               I->d_sout, I->d_counts, I->d_masks);
-        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, 0, (int)I->kb.size(), I->n_act,
-                   I->d_spad, I->d_ypart);
-        enqueue_finish(I, st, I->next_frame, cmds ? cmds + (size_t)f * I->n_act : nullptr);
+        float c1, g;
+        coeffs(I, I->next_frame, &c1, &g);
+        settle_params(I, I->next_frame);
+        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
+                   (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart,
+                   integrate_epi(I, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr));
         enqueue_polc(I, st);
         if (slopes)
             HIP_TRY(hipMemcpyAsync(slopes + (size_t)f * I->n_slopes, I->d_sout, I->n_slopes * 4,
@@ -894,9 +970,15 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     if (n_iter < 0) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
+    MvmEpilogue E{};
+    E.mode = EPI_REDUCE;
+    E.n_parts = (int)I->seg.size();
+    E.count = I->d_count_t;
+    E.y = I->d_yscratch;
+    std::lock_guard<std::mutex> lk(I->mu);
     for (int i = 0; i < n_iter; ++i)
-        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, 0, (int)I->kb.size(), I->n_act,
-                   I->d_spad, I->d_ypart);
+        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
+                   (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
     return last_error(e);
 }
 
@@ -964,6 +1046,8 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             FrameSlot &old = I->slots[I->cur_frame % I->slots.size()];
             old.dropped = true;
             I->drops++;
+            // its column blocks left partial arrival counts behind
+            HIP_TRY(hipMemsetAsync(I->d_count, 0, (size_t)I->n_tiles * 4, e->stream));
         }
         FrameSlot &sl = I->slots[frame % I->slots.size()];
         if (sl.frame != ~0ull) {
@@ -979,6 +1063,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         I->cur_frame = frame;
         I->cur_started = false;
         for (auto &W : I->wfs) W.next_chunk = 0;
+        coeffs(I, frame, &I->frame_c1, &I->frame_g);
         sl.frame = frame;
         sl.complete = false;
         sl.dropped = false;
@@ -1002,8 +1087,9 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             fs.f[w] = I->wfs[w].d_ring + (size_t)slot * I->wfs[w].d.frame_h * I->wfs[w].d.frame_w;
         const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
-        launch_mvm(e->stream, I->d.cm_dtype, I->d_cm, I->d_kb, kb, 1, I->n_act, I->d_spad,
-                   I->d_ypart);
+        launch_mvm(e->stream, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_single,
+                   I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad, I->d_ypart,
+                   integrate_epi(I, I->frame_c1, I->frame_g, nullptr));
     }
     S.next_chunk++;
     bool all = true;
@@ -1011,7 +1097,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
     if (all) {
         FrameSlot &sl = I->slots[frame % I->slots.size()];
         float *mail = I->h_mail + (size_t)slot * I->n_act;
-        enqueue_finish(I, e->stream, frame, nullptr);
+        settle_params(I, frame);
         HIP_TRY(hipMemcpyAsync(mail, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost, e->stream));
         HIP_TRY(hipEventRecord(sl.done, e->stream));
         enqueue_polc(I, e->stream);

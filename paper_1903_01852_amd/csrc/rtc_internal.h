@@ -11,6 +11,10 @@ namespace rtc {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kTileRows = 64;      // matrix rows per MVM tile: one row per lane
 constexpr int kPolcBlock = 512;    // command elements per POLC column block
+constexpr int kPieceVectors = 128; // target length of an MVM piece (16-byte vectors per row)
+constexpr int kMinMvmWaves = 1536; // at least this many wavefronts per full MVM (6 per CU)
+constexpr int kMaxShPx = 16;       // largest SH subaperture side (pixels)
+constexpr int kMaxShPasses = (kMaxShPx * kMaxShPx + kWave - 1) / kWave;
 
 // Per-sensor constants the kernels need.
 struct WfsParam {
@@ -64,6 +68,34 @@ struct KBlock {
     int32_t wfs, chunk;
 };
 
+// A segment is the part of one column block that one wavefront streams for a
+// tile: vectors [v0, v0 + nv) of block kb.  Each segment owns one partial
+// (its index in the global segment order).  The column range of every tile is
+// cut into pieces of nearly equal length so that wavefronts finish together;
+// a piece is a run of consecutive segments.  The serving path launches the
+// same segments chunk by chunk, so both paths add the same partials in the
+// same order.
+struct Segment {
+    int32_t kb, v0, nv, r;
+};
+struct Piece {
+    int32_t seg0, nseg;
+};
+
+// Work done by the last wavefront to finish a row tile of an MVM.
+enum { EPI_NONE = 0, EPI_INTEGRATE = 1, EPI_REDUCE = 2 };
+struct MvmEpilogue {
+    int32_t mode;          // EPI_*
+    int32_t n_parts;       // column-block partials per row (all launches of the frame)
+    uint32_t *count;       // per-tile arrival counters, zero between frames
+    const float *p;        // INTEGRATE: POLC term (nullable)
+    const float *scale;    // INTEGRATE: FP8 row scales (nullable)
+    float *a;              // INTEGRATE: command state, updated in place
+    float *out;            // INTEGRATE: copy of the new commands (nullable)
+    float *y;              // REDUCE: destination
+    float c1, g;           // INTEGRATE: a = c1 a + g (y + p)
+};
+
 // Launchers (defined in rtc_kernels.hip).
 void launch_sh_centroid(hipStream_t st, const ShUnit *units, int u0, int u1,
                         const FrameSet &frames, const WfsParamSet &params,
@@ -75,11 +107,9 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        const float *dark4, const float *flat4, const float *bg4,
                        const float *thr, const float *ref, float *s_pad, float *s_out,
                        int32_t *counts, uint64_t *masks);
-void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs, int kb0, int n_kb,
-                int n_rows, const float *x_pad, float *y_part);
-void launch_integrate(hipStream_t st, const float *y_part, int n_kb, const float *p_part,
-                      int n_pkb, int n_rows, const float *scale, float *a, float *a_pad,
-                      float *out, float c1, float g);
+void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs,
+                const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
+                const float *x_pad, float *y_part, const MvmEpilogue &epi);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
                      int n_s);
 

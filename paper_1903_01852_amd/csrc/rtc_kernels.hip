@@ -8,8 +8,10 @@
 //                  (column block, 64-row tile), one matrix row per lane,
 //                  FP32 / BF16 / FP8-e4m3 storage, FP32 accumulation
 //                  (section 2.3; the product is memory-bandwidth bound)
-//  k_integrate     fixed-order sum of the column-block partials, FP8 row scale,
-//                  implicit POLC term and leaky integrator (sections 1.1, 3.4)
+//                  The last wavefront to finish a 64-row tile sums the tile's
+//                  partials in fixed block order and applies the FP8 row scale,
+//                  the implicit POLC term and the leaky integrator
+//                  (sections 1.1, 3.4), or forms the POLC term itself.
 //  k_dgemm_rd      one-off FP64 product M = R.D for implicit POLC
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -38,10 +40,23 @@ __device__ __forceinline__ float threshold_px(float c, float thr, int mode, bool
     return mode == RTC_THR_SUBTRACT ? c - thr : c;
 }
 
+// Sum over the 64 lanes in a fixed order: DPP within each row of 16 lanes
+// (pair swap, quad swap, half-row mirror, row mirror), then the four row
+// sums in row order.  The result is uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp<0xB1>(v);    // quad_perm(1,0,3,2)
+    v += dpp<0x4E>(v);    // quad_perm(2,3,0,1)
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return ((r0 + r1) + r2) + r3;
 }
 
 // ---------------------------------------------------------------------------
@@ -64,16 +79,36 @@ __global__ __launch_bounds__(256) void k_sh_centroid(
     const int npx = p * p;
     const float T = thr[u];
     const int mode = P.thr_mode;
+    // every pixel and calibration load of the subaperture is issued before
+    // any is used (at most kMaxShPasses per lane)
+    uint32_t raw[kMaxShPasses];
+    float dk[kMaxShPasses], fl[kMaxShPasses], bgv[kMaxShPasses];
+#pragma unroll
+    for (int j = 0; j < kMaxShPasses; ++j) {
+        const int i = j * kWave + lane;
+        raw[j] = 0;
+        dk[j] = 0.0f;
+        fl[j] = 0.0f;
+        bgv[j] = 0.0f;
+        if (i < npx) {
+            const int r = i / p;
+            const int c = i - r * p;
+            raw[j] = fr[(size_t)(d.row0 + r) * P.W + (d.col0 + c)];
+            dk[j] = dark[d.cal + i];
+            fl[j] = flat[d.cal + i];
+            bgv[j] = bg[d.cal + i];
+        }
+    }
     float sw = 0.0f, sx = 0.0f, sy = 0.0f;
     int cnt = 0;
-    for (int base = 0, j = 0; base < npx; base += kWave, ++j) {
-        const int i = base + lane;
+#pragma unroll
+    for (int j = 0; j < kMaxShPasses; ++j) {
+        const int i = j * kWave + lane;
         bool m = false;
         if (i < npx) {
             const int r = i / p;
             const int c = i - r * p;
-            const float raw = (float)fr[(size_t)(d.row0 + r) * P.W + (d.col0 + c)];
-            const float cv = calibrate_px(raw, dark[d.cal + i], flat[d.cal + i], bg[d.cal + i]);
+            const float cv = calibrate_px((float)raw[j], dk[j], fl[j], bgv[j]);
             const float w = threshold_px(cv, T, mode, m);
             const float x = (float)c - P.half;
             const float y = (float)r - P.half;
@@ -83,7 +118,7 @@ __global__ __launch_bounds__(256) void k_sh_centroid(
         }
         const uint64_t bal = __ballot(m);
         cnt += __popcll(bal);
-        if (masks != nullptr && lane == 0) masks[d.mask + j] = bal;
+        if (masks != nullptr && lane == 0 && j * kWave < npx) masks[d.mask + j] = bal;
     }
     sw = wave_sum(sw);
     sx = wave_sum(sx);
@@ -155,6 +190,7 @@ template <> struct Elem<RTC_CM_FP8> { static constexpr int E = 16; };
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
+// Accumulates the E products of one 16-byte vector.
 template <int DT>
 __device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ xs, int v,
                                       float &a0, float &a1) {
@@ -190,60 +226,126 @@ __device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ 
     }
 }
 
-template <int DT, int U>
-__global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
-                                             const KBlock *__restrict__ kbs, int kb0, int n_kb,
-                                             int n_tiles, int n_rows,
-                                             const float *__restrict__ x,
-                                             float *__restrict__ y_part) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    if (wv >= n_kb * n_tiles) return;
-    const int kbl = wv / n_tiles;
-    const int t = wv - kbl * n_tiles;
-    const KBlock K = kbs[kb0 + kbl];
-    const int nr = min(kTileRows, n_rows - t * kTileRows);
-    const uint4 *__restrict__ blk =
-        reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16);
-    const float4 *__restrict__ xs = reinterpret_cast<const float4 *>(x + K.spad);
-    float a0 = 0.0f, a1 = 0.0f;
-    if (lane < nr) {
-        const uint4 *__restrict__ p = blk + lane;
-        int v = 0;
-        for (; v + U <= K.kv; v += U) {
-            uint4 q[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) q[u] = p[(v + u) * nr];
-#pragma unroll
-            for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, v + u, a0, a1);
-        }
-        for (; v < K.kv; ++v) dot16<DT>(p[v * nr], xs, v, a0, a1);
-        y_part[(size_t)(kb0 + kbl) * n_rows + t * kTileRows + lane] = a0 + a1;
-    }
+// Sum of the n column-block partials of row r, in increasing block order.
+// The partials were written by wavefronts on any XCD; agent-scope atomic loads
+// read them past this XCD's (non-coherent) L2.
+__device__ __forceinline__ float load_part(const float *part, size_t i) {
+    return __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---------------------------------------------------------------------------
-// a_f = c1 * a_{f-1} + g * (scale * sum_kb y_part[kb] + sum_j p_part[j]),
-// sums in fixed block order, so the result does not depend on how many
-// blocks were in flight.
-__global__ __launch_bounds__(256) void k_integrate(const float *__restrict__ y_part, int n_kb,
-                                                   const float *__restrict__ p_part, int n_pkb,
-                                                   int n_rows, const float *__restrict__ scale,
-                                                   float *__restrict__ a,
-                                                   float *__restrict__ out, float c1, float g) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n_rows) return;
+__device__ __forceinline__ float sum_parts(const float *__restrict__ part, int n, int n_rows,
+                                          int r) {
     float y = 0.0f;
-    for (int kb = 0; kb < n_kb; ++kb) y += y_part[(size_t)kb * n_rows + r];
-    if (scale != nullptr) y *= scale[r];
-    if (p_part != nullptr) {
-        float p = 0.0f;
-        for (int j = 0; j < n_pkb; ++j) p += p_part[(size_t)j * n_rows + r];
-        y += p;
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = load_part(part, (size_t)(j + u) * n_rows + r);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y += v[u];
     }
-    const float an = fmaf(c1, a[r], g * y);
-    a[r] = an;
-    if (out != nullptr) out[r] = an;
+    for (; j < n; ++j) y += load_part(part, (size_t)j * n_rows + r);
+    return y;
+}
+
+// Epilogue run by the last wavefront to finish a 64-row tile (every column
+// block of the tile has then written its partial):
+//   EPI_INTEGRATE: a = c1 a + g (scale * sum partials + p)   (commands)
+//   EPI_REDUCE:    y = sum partials                          (POLC term p)
+__device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float *__restrict__ part,
+                                              int n_rows, int t, int lane, int nr) {
+    const int r = t * kTileRows + lane;
+    if (lane >= nr) return;
+    float y = sum_parts(part, E.n_parts, n_rows, r);
+    if (E.mode == EPI_REDUCE) {
+        E.y[r] = y;
+        return;
+    }
+    if (E.scale != nullptr) y *= E.scale[r];
+    if (E.p != nullptr) y += E.p[r];
+    const float an = fmaf(E.c1, E.a[r], E.g * y);
+    E.a[r] = an;
+    if (E.out != nullptr) E.out[r] = an;
+}
+
+// Streams vectors [0, nv) of one segment for this lane's row, U vectors (U
+// loads in flight) per batch; the slope values of a batch are contiguous, so
+// they arrive in a few wide scalar loads issued beside the vector loads.  The
+// last, partial batch guards each load instead.
+template <int DT, int U>
+__device__ __forceinline__ float stream_segment(const uint4 *__restrict__ p, int nr,
+                                                const float4 *__restrict__ xs, int nv) {
+    float a0 = 0.0f, a1 = 0.0f;
+    int v = 0;
+    for (; v + U <= nv; v += U) {
+        uint4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = p[(v + u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, v + u, a0, a1);
+    }
+    if (v < nv) {
+        uint4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u < nv) q[u] = p[(v + u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u < nv) dot16<DT>(q[u], xs, v + u, a0, a1);
+    }
+    return a0 + a1;
+}
+
+template <int DT, int U>
+__global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
+                                             const KBlock *__restrict__ kbs,
+                                             const Segment *__restrict__ segs,
+                                             const Piece *__restrict__ pieces, int p0,
+                                             int n_pieces, int n_tiles, int n_rows,
+                                             const float *__restrict__ x,
+                                             float *__restrict__ y_part, MvmEpilogue E) {
+    constexpr int kE = Elem<DT>::E;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    if (wv >= n_pieces * n_tiles) return;
+    const int pi = wv / n_tiles;
+    const int t = wv - pi * n_tiles;
+    const Piece P = pieces[p0 + pi];
+    const int nr = min(kTileRows, n_rows - t * kTileRows);
+    for (int sgi = 0; sgi < P.nseg; ++sgi) {
+        const int sg = P.seg0 + sgi;
+        const Segment S = segs[sg];
+        const KBlock K = kbs[S.kb];
+        if (lane < nr) {
+            const uint4 *__restrict__ p =
+                reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
+                (int64_t)S.v0 * nr + lane;
+            const float4 *__restrict__ xs =
+                reinterpret_cast<const float4 *>(x + K.spad + (int64_t)S.v0 * kE);
+            const float part = stream_segment<DT, U>(p, nr, xs, S.nv);
+            // agent-scope atomic store: written through to the memory side,
+            // where every XCD's agent-scope loads see it
+            __hip_atomic_store(y_part + (size_t)sg * n_rows + t * kTileRows + lane, part,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (E.mode == EPI_NONE) return;
+    // Count this tile's partials only once their stores have completed
+    // (vmcnt drained); the wavefront bringing the count to E.n_parts runs the
+    // epilogue.
+    // Whole-L2 release/acquire fences are avoided on purpose: every datum
+    // handed between wavefronts goes through agent-scope atomics.
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    uint32_t old = 0;
+    if (lane == 0)
+        old = __hip_atomic_fetch_add(&E.count[t], (uint32_t)P.nseg, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    old = __shfl(old, 0, kWave);
+    if (old + (uint32_t)P.nseg != (uint32_t)E.n_parts) return;
+    if (lane == 0) __hip_atomic_store(&E.count[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tile_epilogue(E, y_part, n_rows, t, lane, nr);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,35 +417,28 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        counts, masks);
 }
 
-void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs, int kb0, int n_kb,
-                int n_rows, const float *x_pad, float *y_part) {
-    if (n_kb <= 0 || n_rows <= 0) return;
+void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs,
+                const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
+                const float *x_pad, float *y_part, const MvmEpilogue &epi) {
+    if (n_pieces <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
-    const int waves = n_kb * n_tiles;
+    const int waves = n_pieces * n_tiles;
     const dim3 grid((waves + 3) / 4), block(256);
     const uint8_t *c = static_cast<const uint8_t *>(cm);
     switch (dtype) {
     case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 8>), grid, block, 0, st, c, kbs, kb0, n_kb,
-                           n_tiles, n_rows, x_pad, y_part);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 8>), grid, block, 0, st, c, kbs, kb0, n_kb,
-                           n_tiles, n_rows, x_pad, y_part);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     default:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 8>), grid, block, 0, st, c, kbs, kb0, n_kb,
-                           n_tiles, n_rows, x_pad, y_part);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     }
-}
-
-void launch_integrate(hipStream_t st, const float *y_part, int n_kb, const float *p_part,
-                      int n_pkb, int n_rows, const float *scale, float *a, float *a_pad,
-                      float *out, float c1, float g) {
-    (void)a_pad;
-    hipLaunchKernelGGL(k_integrate, dim3((n_rows + 255) / 256), dim3(256), 0, st, y_part, n_kb,
-                       p_part, n_pkb, n_rows, scale, a, out, c1, g);
 }
 
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
