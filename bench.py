@@ -224,9 +224,8 @@ def main():
                     help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the hot path is single-GPU; see the sharding notes in the design document)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the "
+              "controller's hot path runs on a single MI355X", file=sys.stderr)
         sys.exit(2)
 
     import torch
