@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librtc.so")
-SOURCES = ["rtc_kernels.hip", "rtc_engine.cpp"]
+SOURCES = ["rtc_kernels.hip", "rtc_persist.hip", "rtc_engine.cpp", "rtc_serve.cpp"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

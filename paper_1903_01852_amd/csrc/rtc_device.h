@@ -1,0 +1,299 @@
+// Device building blocks shared by the per-launch kernels and the persistent
+// frame loop.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtc_internal.h"
+
+namespace rtc {
+
+// Binary32 calibration, one rounding per operation: contraction into a fused
+// multiply-add would change the thresholded-pixel masks.
+__device__ __forceinline__ float calibrate_px(float raw, float dark, float flat, float bg) {
+#pragma clang fp contract(off)
+    const float t = raw - dark;
+    const float u = t * flat;
+    return u - bg;
+}
+
+__device__ __forceinline__ float threshold_px(float c, float thr, int mode, bool &m) {
+#pragma clang fp contract(off)
+    if (mode == RTC_THR_NONE) {
+        m = true;
+        return c;
+    }
+    m = c > thr;
+    if (!m) return 0.0f;
+    return mode == RTC_THR_SUBTRACT ? c - thr : c;
+}
+
+// Sum over the 64 lanes in a fixed order: DPP within each row of 16 lanes
+// (pair swap, quad swap, half-row mirror, row mirror), then the four row
+// sums in row order.  The result is uniform.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp<0xB1>(v);    // quad_perm(1,0,3,2)
+    v += dpp<0x4E>(v);    // quad_perm(2,3,0,1)
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return ((r0 + r1) + r2) + r3;
+}
+
+// ---------------------------------------------------------------------------
+// Store policies for slope values: STORE_PLAIN when consumers run in later
+// kernels, STORE_AGENT when wavefronts of the same kernel on other XCDs read
+// them (agent-scope atomic store, written through the non-coherent L2).
+enum { STORE_PLAIN = 0, STORE_AGENT = 1 };
+template <int SP>
+__device__ __forceinline__ void put(float *p, float v) {
+    if constexpr (SP == STORE_AGENT)
+        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *p = v;
+}
+
+// Load policies for pixels: LOAD_PLAIN for frames in device memory written
+// before the kernel started; LOAD_SYSTEM for the pinned host ring that the host
+// refills while the kernel runs (system-scope 32-bit loads bypass the GPU
+// caches, which could otherwise return a ring slot's previous frame; the
+// aligned word may include the neighbouring pixel, so ring buffers carry four
+// bytes of slack).
+enum { LOAD_PLAIN = 0, LOAD_SYSTEM = 1 };
+template <int LP>
+__device__ __forceinline__ uint32_t load_px(const uint16_t *p) {
+    if constexpr (LP == LOAD_SYSTEM) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+        const uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return (a & 2) ? (v >> 16) : (v & 0xFFFFu);
+    } else {
+        return *p;
+    }
+}
+
+struct SlopeOut {
+    float *s_pad;          // padded slope vector read by the MVM
+    float *s_out;          // compact slopes (nullable)
+    int32_t *counts;       // thresholded pixels per unit (nullable)
+    uint64_t *masks;       // thresholded-pixel masks (nullable)
+};
+
+// Shack-Hartmann unit: one wavefront.  Lane l handles pixels l, l+64, ... of
+// the subaperture (raster order), so the ballot of pass j is mask word j.
+// Every pixel and calibration load is issued before any is used.
+template <int SP, int LP = LOAD_PLAIN>
+__device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t *__restrict__ fr,
+                                        const WfsParam &P, const float *__restrict__ dark,
+                                        const float *__restrict__ flat,
+                                        const float *__restrict__ bg,
+                                        const float *__restrict__ ref, const SlopeOut &o,
+                                        int lane) {
+    const int p = P.p;
+    const int npx = p * p;
+    const int mode = P.thr_mode;
+    uint32_t raw[kMaxShPasses];
+    float dk[kMaxShPasses], fl[kMaxShPasses], bgv[kMaxShPasses];
+#pragma unroll
+    for (int j = 0; j < kMaxShPasses; ++j) {
+        const int i = j * kWave + lane;
+        raw[j] = 0;
+        dk[j] = 0.0f;
+        fl[j] = 0.0f;
+        bgv[j] = 0.0f;
+        if (i < npx) {
+            const int r = i / p;
+            const int c = i - r * p;
+            raw[j] = load_px<LP>(fr + (size_t)(d.row0 + r) * P.W + (d.col0 + c));
+            dk[j] = dark[d.cal + i];
+            fl[j] = flat[d.cal + i];
+            bgv[j] = bg[d.cal + i];
+        }
+    }
+    float sw = 0.0f, sx = 0.0f, sy = 0.0f;
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kMaxShPasses; ++j) {
+        const int i = j * kWave + lane;
+        bool m = false;
+        if (i < npx) {
+            const int r = i / p;
+            const int c = i - r * p;
+            const float cv = calibrate_px((float)raw[j], dk[j], fl[j], bgv[j]);
+            const float w = threshold_px(cv, T, mode, m);
+            const float x = (float)c - P.half;
+            const float y = (float)r - P.half;
+            sw += w;
+            sx = fmaf(w, x, sx);
+            sy = fmaf(w, y, sy);
+        }
+        const uint64_t bal = __ballot(m);
+        cnt += __popcll(bal);
+        if (o.masks != nullptr && lane == 0 && j * kWave < npx) o.masks[d.mask + j] = bal;
+    }
+    sw = wave_sum(sw);
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if (lane == 0) {
+        float ox = 0.0f, oy = 0.0f;
+        if (sw > 0.0f) {
+            ox = sx / sw - ref[2 * d.unit];
+            oy = sy / sw - ref[2 * d.unit + 1];
+        }
+        put<SP>(o.s_pad + d.pad, ox);
+        put<SP>(o.s_pad + d.pad + 1, oy);
+        if (o.s_out != nullptr) {
+            o.s_out[2 * d.unit] = ox;
+            o.s_out[2 * d.unit + 1] = oy;
+        }
+        if (o.counts != nullptr) o.counts[d.unit] = cnt;
+    }
+}
+
+// Pyramid unit: one lane.  Calibration arrays are [quadrant][unit] so that
+// lanes read consecutive addresses.
+template <int SP, int LP = LOAD_PLAIN>
+__device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, float T,
+                                         const uint16_t *__restrict__ fr, const WfsParam &P,
+                                         const float *__restrict__ dark4,
+                                         const float *__restrict__ flat4,
+                                         const float *__restrict__ bg4,
+                                         const float *__restrict__ ref, const SlopeOut &o) {
+    uint32_t raw[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        raw[q] = load_px<LP>(fr + (size_t)(P.qrow[q] + d.i) * P.W + (P.qcol[q] + d.j));
+    float I[4];
+    uint64_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float cv = calibrate_px((float)raw[q], dark4[q * n_pyr + k], flat4[q * n_pyr + k],
+                                      bg4[q * n_pyr + k]);
+        bool m;
+        I[q] = threshold_px(cv, T, P.thr_mode, m);
+        bits |= (uint64_t)m << q;
+    }
+    const float S = (I[0] + I[1]) + (I[2] + I[3]);
+    float sx = 0.0f, sy = 0.0f;
+    if (S > 0.0f) {
+        sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - ref[2 * d.unit];
+        sy = ((I[0] + I[2]) - (I[1] + I[3])) / S - ref[2 * d.unit + 1];
+    }
+    put<SP>(o.s_pad + d.pad, sx);
+    put<SP>(o.s_pad + d.pad + 1, sy);
+    if (o.s_out != nullptr) {
+        o.s_out[2 * d.unit] = sx;
+        o.s_out[2 * d.unit + 1] = sy;
+    }
+    if (o.counts != nullptr) o.counts[d.unit] = __popcll(bits);
+    if (o.masks != nullptr) o.masks[d.mask] = bits;
+}
+
+// ---------------------------------------------------------------------------
+// Split-K MVM.  Each 16-byte vector of a tile holds E consecutive columns of
+// one row, so lane l streams row 64t + l while the 64 lanes of a load cover
+// 1 KiB of contiguous memory.  The slope values of a vector are the same for
+// every lane, so they come through the scalar unit.
+template <int DT> struct Elem;
+template <> struct Elem<RTC_CM_F32> { static constexpr int E = 4; };
+template <> struct Elem<RTC_CM_BF16> { static constexpr int E = 8; };
+template <> struct Elem<RTC_CM_FP8> { static constexpr int E = 16; };
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// Accumulates the E products of one 16-byte vector.
+template <int DT>
+__device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ xs, int v,
+                                      float &a0, float &a1) {
+    if constexpr (DT == RTC_CM_F32) {
+        const float4 s = xs[v];
+        a0 = fmaf(__uint_as_float(q.x), s.x, a0);
+        a1 = fmaf(__uint_as_float(q.y), s.y, a1);
+        a0 = fmaf(__uint_as_float(q.z), s.z, a0);
+        a1 = fmaf(__uint_as_float(q.w), s.w, a1);
+    } else if constexpr (DT == RTC_CM_BF16) {
+        const float4 s0 = xs[2 * v];
+        const float4 s1 = xs[2 * v + 1];
+        a0 = fmaf(bf16_lo(q.x), s0.x, a0);
+        a1 = fmaf(bf16_hi(q.x), s0.y, a1);
+        a0 = fmaf(bf16_lo(q.y), s0.z, a0);
+        a1 = fmaf(bf16_hi(q.y), s0.w, a1);
+        a0 = fmaf(bf16_lo(q.z), s1.x, a0);
+        a1 = fmaf(bf16_hi(q.z), s1.y, a1);
+        a0 = fmaf(bf16_lo(q.w), s1.z, a0);
+        a1 = fmaf(bf16_hi(q.w), s1.w, a1);
+    } else {
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const float4 s = xs[4 * v + h];
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], true);
+            a0 = fmaf(lo[0], s.x, a0);
+            a1 = fmaf(lo[1], s.y, a1);
+            a0 = fmaf(hi[0], s.z, a0);
+            a1 = fmaf(hi[1], s.w, a1);
+        }
+    }
+}
+
+// Streams vectors [0, nv) of one segment for this lane's row, U vectors (U
+// loads in flight) per batch; the slope values of a batch are contiguous, so
+// they arrive in a few wide scalar loads issued beside the vector loads.  The
+// last, partial batch guards each load instead.
+template <int DT, int U>
+__device__ __forceinline__ float stream_segment(const uint4 *__restrict__ p, int nr,
+                                                const float4 *__restrict__ xs, int nv) {
+    float a0 = 0.0f, a1 = 0.0f;
+    int v = 0;
+    for (; v + U <= nv; v += U) {
+        uint4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = p[(v + u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, v + u, a0, a1);
+    }
+    if (v < nv) {
+        uint4 q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u < nv) q[u] = p[(v + u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v + u < nv) dot16<DT>(q[u], xs, v + u, a0, a1);
+    }
+    return a0 + a1;
+}
+
+// The partials were written by wavefronts on any XCD; agent-scope atomic loads
+// read them past this XCD's (non-coherent) L2.
+__device__ __forceinline__ float load_agent(const float *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum of partials [s0, s0 + n) of row r, in increasing order.
+__device__ __forceinline__ float sum_parts(const float *__restrict__ part, int s0, int n,
+                                          int n_rows, int r) {
+    float y = 0.0f;
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = load_agent(part + (size_t)(s0 + j + u) * n_rows + r);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) y += v[u];
+    }
+    for (; j < n; ++j) y += load_agent(part + (size_t)(s0 + j) * n_rows + r);
+    return y;
+}
+
+}  // namespace rtc

@@ -18,20 +18,12 @@
 #include <vector>
 
 #include "rtc.h"
+#include "rtc_engine.h"
 #include "rtc_internal.h"
 
 using namespace rtc;
 
-namespace {
 
-int64_t now_ns() {
-    timespec ts;
-    clock_gettime(CLOCK_MONOTONIC, &ts);
-    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
-}
-
-int elem_size(int dt) { return dt == RTC_CM_F32 ? 4 : dt == RTC_CM_BF16 ? 2 : 1; }
-int elems_per_vec(int dt) { return 16 / elem_size(dt); }
 
 // ---------------------------------------------------------------- encoders
 uint16_t bf16_rne(float f) {
@@ -60,149 +52,6 @@ uint8_t fp8_rne(float f) {
     }
     return (uint8_t)(sign | code);
 }
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t n = 0;
-};
-
-}  // namespace
-
-// ---------------------------------------------------------------- engine state
-struct WfsState {
-    rtc_wfs_desc d{};
-    std::vector<uint8_t> valid;
-    int u0 = 0, u1 = 0;            // unit range in the instance
-    int kind0 = 0;                 // first index in the SH or pyramid unit list
-    std::vector<int> row0;         // chunk row starts, n_chunks + 1 entries
-    std::vector<int> kb_of_chunk;  // column block produced by each chunk, or -1
-    std::vector<int> unit_ready;   // last frame row each unit needs (per unit)
-    // serving
-    int next_chunk = 0;
-    uint16_t *d_ring = nullptr;    // ring_depth frames on the device
-    uint16_t *h_stage = nullptr;   // pinned staging ring (ring_depth frames)
-};
-
-struct FrameSlot {
-    uint64_t frame = ~0ull;
-    bool complete = false;         // work enqueued
-    bool dropped = false;
-    hipEvent_t done = nullptr;
-    int64_t t_last_chunk = 0;
-};
-
-struct Instance {
-    rtc_instance_desc d{};
-    std::vector<WfsState> wfs;
-    int n_units = 0, n_slopes = 0, n_act = 0, n_sh = 0, n_pyr = 0;
-    int mask_words = 0;
-    std::vector<ShUnit> sh;
-    std::vector<PyrUnit> py;
-    std::vector<KBlock> kb;        // reconstruction column blocks
-    std::vector<KBlock> kbm;       // POLC column blocks
-    std::vector<Segment> seg, segm;            // segments: reconstruction, POLC
-    std::vector<Piece> pieces, pieces_m;       // equal-length pieces (whole frame)
-    std::vector<Piece> single;                 // one piece per reconstruction segment
-    std::vector<int> kb_seg0, kb_nseg;         // segments of each column block
-    int spad_len = 0;
-    int64_t cm_bytes = 0, m_bytes = 0;
-    WfsParamSet params{};
-    // device
-    ShUnit *d_sh = nullptr;
-    PyrUnit *d_py = nullptr;
-    KBlock *d_kb = nullptr, *d_kbm = nullptr;
-    Segment *d_seg = nullptr, *d_segm = nullptr;
-    Piece *d_pieces = nullptr, *d_pieces_m = nullptr, *d_single = nullptr;
-    float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
-    float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
-    float *d_ref = nullptr;
-    float *d_spad = nullptr, *d_sout = nullptr;
-    int32_t *d_counts = nullptr;
-    uint64_t *d_masks = nullptr;
-    uint8_t *d_cm = nullptr;
-    float *d_scale = nullptr;
-    uint8_t *d_M = nullptr;
-    float *d_ypart = nullptr, *d_ppart = nullptr;
-    float *d_a = nullptr;          // command state, padded to the POLC block size
-    float *d_p = nullptr;          // POLC term for the next frame, M a
-    float *d_yscratch = nullptr;   // destination of the timing-only MVM
-    uint32_t *d_count = nullptr;   // per-tile arrival counters: reconstruction
-    uint32_t *d_count_m = nullptr; //                            POLC
-    uint32_t *d_count_t = nullptr; //                            timing MVM
-    int n_tiles = 0;
-    int a_len = 0;
-    float frame_c1 = 0, frame_g = 0;   // coefficients of the frame in progress (serving)
-    bool loaded = false;
-    // parameters: two slots, the staged one becomes active at frame f_switch
-    float gain[2] = {0, 0}, leak[2] = {0, 0};
-    int active = 0;
-    bool pending = false;
-    uint64_t f_switch = 0;
-    uint64_t next_frame = 0;       // next frame the batch path processes
-    uint32_t drops = 0;
-    // serving
-    uint64_t cur_frame = ~0ull;
-    bool cur_started = false;
-    std::vector<FrameSlot> slots;
-    float *h_mail = nullptr;       // pinned, ring_depth x n_act
-    std::mutex mu;
-};
-
-struct rtc_engine {
-    int device = 0;
-    int ring_depth = 2;
-    int mode = RTC_MODE_STREAM;
-    hipStream_t stream = nullptr;
-    std::vector<Instance *> inst;
-    std::vector<DevBuf> allocs;
-    std::vector<void *> pinned;
-    std::atomic<int> sticky{RTC_OK};
-};
-
-namespace {
-
-#define HIP_TRY(expr)                                                                \
-    do {                                                                             \
-        hipError_t _e = (expr);                                                      \
-        if (_e != hipSuccess) {                                                      \
-            std::fprintf(stderr, "rtc: %s failed: %s (%s:%d)\n", #expr,              \
-                         hipGetErrorString(_e), __FILE__, __LINE__);                 \
-            return RTC_E_DEVICE;                                                     \
-        }                                                                            \
-    } while (0)
-
-template <class T>
-rtc_status dev_alloc(rtc_engine *e, T **p, size_t count) {
-    void *q = nullptr;
-    const size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-    if (hipMalloc(&q, bytes) != hipSuccess) return RTC_E_NOMEM;
-    if (hipMemset(q, 0, bytes) != hipSuccess) return RTC_E_DEVICE;
-    e->allocs.push_back({q, bytes});
-    *p = static_cast<T *>(q);
-    return RTC_OK;
-}
-
-template <class T>
-rtc_status host_pinned(rtc_engine *e, T **p, size_t count) {
-    void *q = nullptr;
-    const size_t bytes = std::max<size_t>(count * sizeof(T), 64);
-    if (hipHostMalloc(&q, bytes, hipHostMallocDefault) != hipSuccess) return RTC_E_NOMEM;
-    std::memset(q, 0, bytes);
-    e->pinned.push_back(q);
-    *p = static_cast<T *>(q);
-    return RTC_OK;
-}
-
-rtc_status fail(rtc_engine *e, rtc_status s) {
-    if (s == RTC_E_DEVICE && e) e->sticky.store(RTC_E_DEVICE);
-    return s;
-}
-
-#define TRY(expr)                                                                    \
-    do {                                                                             \
-        rtc_status _s = (expr);                                                      \
-        if (_s != RTC_OK) return fail(e, _s);                                        \
-    } while (0)
 
 int chunk_row(int H, int n, int c) { return (int)(((int64_t)c * H) / n); }
 
@@ -240,7 +89,7 @@ void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces,
         V += kbs[b].kv;
     }
     start[kbs.size()] = V;
-    const int64_t P = std::min<int64_t>(V, std::max<int64_t>(min_pieces, (V + target / 2) / target));
+    const int64_t P = std::min<int64_t>(V, std::max<int64_t>(min_pieces, (V + target - 1) / target));
     size_t b = 0;
     for (int64_t p = 0; p < P; ++p) {
         int64_t lo = p * V / P;
@@ -332,19 +181,35 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         }
     }
     // column blocks: units become ready in raster order, so each chunk
-    // completes a contiguous unit range of its sensor
+    // completes a contiguous unit range of its sensor.  Blocks are numbered in
+    // readout order (chunk index major, sensor minor): the order in which the
+    // frame loop accumulates them.
     int spad = 0;
     int64_t base = 0;
     const int n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
+    std::vector<std::vector<std::pair<int, int>>> ranges(I->wfs.size());
+    int max_chunks = 0;
     for (int w = 0; w < (int)I->wfs.size(); ++w) {
         WfsState &S = I->wfs[w];
         S.kb_of_chunk.assign(S.d.n_chunks, -1);
+        max_chunks = std::max(max_chunks, S.d.n_chunks);
         int next = 0;     // next unit (relative) not yet assigned
         const int nu = S.u1 - S.u0;
         for (int c = 0; c < S.d.n_chunks; ++c) {
             const int last_row = S.row0[c + 1] - 1;
             int end = next;
             while (end < nu && S.unit_ready[end] <= last_row) ++end;
+            ranges[w].push_back({next, end});
+            next = end;
+        }
+        if (next != nu) return RTC_E_INVAL;
+    }
+    for (int c = 0; c < max_chunks; ++c) {
+        for (int w = 0; w < (int)I->wfs.size(); ++w) {
+            WfsState &S = I->wfs[w];
+            if (c >= S.d.n_chunks) continue;
+            const int next = ranges[w][c].first, end = ranges[w][c].second;
+            I->steps.push_back(Step{w, c, end > next ? (int)I->kb.size() : -1, 0});
             if (end == next) continue;
             KBlock K{};
             K.k0 = 2 * (S.u0 + next);
@@ -356,21 +221,17 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
             K.chunk = c;
             // map units to padded slope indices
             for (int u = next; u < end; ++u) {
-                const int gu = S.u0 + u;
                 const int pad = spad + 2 * (u - next);
                 if (S.d.kind == RTC_WFS_SH)
                     I->sh[S.kind0 + u].pad = pad;
                 else
                     I->py[S.kind0 + u].pad = pad;
-                (void)gu;
             }
             S.kb_of_chunk[c] = (int)I->kb.size();
             I->kb.push_back(K);
             spad += ((K.kv * E + 15) / 16) * 16;    // 64-byte aligned block starts
             base += (int64_t)n_tiles * kTileRows * K.kv * 16;
-            next = end;
         }
-        if (next != nu) return RTC_E_INVAL;
     }
     // the last tile of each block holds fewer rows; trim the allocation to the
     // real end of the last block
@@ -391,6 +252,7 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->kb_nseg[b]++;
         I->single.push_back(Piece{(int32_t)i, 1});
     }
+    for (size_t b = 0; b < I->kb.size(); ++b) I->kb_segs.push_back(int2{I->kb_seg0[b], I->kb_nseg[b]});
     // POLC column blocks of kPolcBlock commands, F32
     if (I->d.polc) {
         const int nb = (I->n_act + kPolcBlock - 1) / kPolcBlock;
@@ -412,6 +274,13 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->a_len = nb * kPolcBlock;
         build_segments(I->kbm, kPieceVectors, (kMinMvmWaves + n_tiles - 1) / n_tiles, I->segm,
                        I->pieces_m);
+        std::vector<int> s0(I->kbm.size(), 0), ns(I->kbm.size(), 0);
+        for (size_t i = 0; i < I->segm.size(); ++i) {
+            const int b = I->segm[i].kb;
+            if (ns[b] == 0) s0[b] = (int)i;
+            ns[b]++;
+        }
+        for (size_t b = 0; b < I->kbm.size(); ++b) I->kbm_segs.push_back(int2{s0[b], ns[b]});
     } else {
         I->a_len = I->n_act;
     }
@@ -426,6 +295,8 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_kb, nkb));
     TRY(dev_alloc(e, &I->d_kbm, std::max<size_t>(I->kbm.size(), 1)));
     TRY(dev_alloc(e, &I->d_seg, I->seg.size()));
+    TRY(dev_alloc(e, &I->d_kb_segs, I->kb_segs.size()));
+    TRY(dev_alloc(e, &I->d_kbm_segs, std::max<size_t>(I->kbm_segs.size(), 1)));
     TRY(dev_alloc(e, &I->d_single, I->single.size()));
     TRY(dev_alloc(e, &I->d_pieces, I->pieces.size()));
     TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
@@ -452,7 +323,7 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
         TRY(dev_alloc(e, &I->d_ppart, I->segm.size() * (size_t)I->n_act));
     }
     TRY(dev_alloc(e, &I->d_ypart, I->seg.size() * (size_t)I->n_act));
-    TRY(dev_alloc(e, &I->d_a, I->a_len));
+    TRY(dev_alloc(e, &I->d_a, 2 * (size_t)I->a_len));   // buffer 1: frame-loop parity
     TRY(dev_alloc(e, &I->d_p, I->n_act));
     TRY(dev_alloc(e, &I->d_yscratch, I->n_act));
     I->n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
@@ -469,6 +340,8 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
     HIP_TRY(up(I->d_seg, I->seg.data(), I->seg.size() * sizeof(Segment)));
+    HIP_TRY(up(I->d_kb_segs, I->kb_segs.data(), I->kb_segs.size() * sizeof(int2)));
+    HIP_TRY(up(I->d_kbm_segs, I->kbm_segs.data(), I->kbm_segs.size() * sizeof(int2)));
     HIP_TRY(up(I->d_single, I->single.data(), I->single.size() * sizeof(Piece)));
     HIP_TRY(up(I->d_pieces, I->pieces.data(), I->pieces.size() * sizeof(Piece)));
     HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));
@@ -483,7 +356,7 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     for (auto &S : I->wfs) {
         const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
         TRY(dev_alloc(e, &S.d_ring, fpx * e->ring_depth));
-        TRY(host_pinned(e, &S.h_stage, fpx * e->ring_depth));
+        TRY(host_pinned(e, &S.h_stage, fpx * e->ring_depth + 2));   // + slack for word loads
     }
     TRY(host_pinned(e, &I->h_mail, (size_t)e->ring_depth * I->n_act));
     I->slots.resize(e->ring_depth);
@@ -535,6 +408,8 @@ MvmEpilogue integrate_epi(Instance *I, float c1, float g, float *out) {
     MvmEpilogue E{};
     E.mode = EPI_INTEGRATE;
     E.n_parts = (int)I->seg.size();
+    E.n_kb = (int)I->kb.size();
+    E.kb_segs = I->d_kb_segs;
     E.count = I->d_count;
     E.p = I->d.polc ? I->d_p : nullptr;
     E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr;
@@ -552,6 +427,8 @@ void enqueue_polc(Instance *I, hipStream_t st) {
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
     E.n_parts = (int)I->segm.size();
+    E.n_kb = (int)I->kbm.size();
+    E.kb_segs = I->d_kbm_segs;
     E.count = I->d_count_m;
     E.y = I->d_p;
     launch_mvm(st, RTC_CM_F32, I->d_M, I->d_kbm, I->d_segm, I->d_pieces_m, 0,
@@ -621,7 +498,6 @@ void encode_matrix(const Instance *I, const float *R, int dt, const float *inv_s
     for (auto &t : pool) t.join();
 }
 
-}  // namespace
 
 // =========================================================================
 extern "C" {
@@ -645,7 +521,7 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
     *out = nullptr;
     if (desc->n_inst < 1 || desc->n_inst > RTC_MAX_INST || !desc->inst) return RTC_E_INVAL;
     if (desc->ring_depth < 2 || desc->ring_depth > 64) return RTC_E_INVAL;
-    if (desc->mode != RTC_MODE_STREAM) return RTC_E_INVAL;
+    if (desc->mode != RTC_MODE_STREAM && desc->mode != RTC_MODE_PERSISTENT) return RTC_E_INVAL;
     for (int i = 0; i < desc->n_inst; ++i) {
         const rtc_instance_desc &d = desc->inst[i];
         if (d.n_wfs < 1 || d.n_wfs > RTC_MAX_WFS || !d.wfs || d.n_act < 1) return RTC_E_INVAL;
@@ -696,6 +572,10 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
         s = alloc_instance(e, I);
         if (s != RTC_OK) return bail(s);
     }
+    if (e->mode == RTC_MODE_PERSISTENT) {
+        rtc_status s = persist_alloc(e);
+        if (s != RTC_OK) return bail(s);
+    }
     *out = e;
     return RTC_OK;
 }
@@ -703,6 +583,10 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
 rtc_status rtc_destroy(rtc_engine *e) {
     if (!e) return RTC_E_INVAL;
     (void)hipSetDevice(e->device);
+    if (e->mode == RTC_MODE_PERSISTENT) {
+        (void)persist_stop(e);
+        persist_free(e);
+    }
     if (e->stream) (void)hipStreamSynchronize(e->stream);
     for (Instance *I : e->inst) {
         for (auto &sl : I->slots)
@@ -752,7 +636,8 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     if (!R) return RTC_E_INVAL;
     if (I->d.polc && !D && !M) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
-    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
+    HIP_TRY(hipDeviceSynchronize());
     const int na = I->n_act, ns = I->n_slopes;
     const int dt = I->d.cm_dtype;
     std::vector<float> scale(na, 1.0f);
@@ -803,6 +688,9 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     HIP_TRY(hipMemset(I->d_spad, 0, (size_t)I->spad_len * 4));
     I->next_frame = 0;
+    I->cur_frame = ~0ull;
+    I->cur_started = false;
+    if (e->mode == RTC_MODE_PERSISTENT) persist_reset(I);
     I->loaded = true;
     return RTC_OK;
 }
@@ -814,7 +702,8 @@ rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs, const 
     TRY(check(e, inst, &I));
     if (wfs < 0 || wfs >= (int)I->wfs.size()) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
-    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
+    HIP_TRY(hipDeviceSynchronize());
     WfsState &S = I->wfs[wfs];
     const int W = S.d.frame_w;
     auto pick = [](const float *m, size_t idx, float dflt) { return m ? m[idx] : dflt; };
@@ -880,6 +769,7 @@ rtc_status rtc_set_params(rtc_engine *e, int32_t inst, float gain, float leak,
     I->f_switch = f;
     I->pending = true;
     if (f_eff_out) *f_eff_out = f;
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_params(e, I));
     return RTC_OK;
 }
 
@@ -887,7 +777,8 @@ rtc_status rtc_get_state(rtc_engine *e, int32_t inst, float *a, float *p, uint64
     Instance *I;
     TRY(check(e, inst, &I));
     HIP_TRY(hipSetDevice(e->device));
-    HIP_TRY(hipStreamSynchronize(e->stream));
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
+    HIP_TRY(hipDeviceSynchronize());
     if (a) HIP_TRY(hipMemcpy(a, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost));
     if (p) HIP_TRY(hipMemcpy(p, I->d_p, I->n_act * 4, hipMemcpyDeviceToHost));
     if (next_frame) *next_frame = I->next_frame;
@@ -899,8 +790,10 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     Instance *I;
     TRY(check(e, inst, &I));
     HIP_TRY(hipSetDevice(e->device));
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
     HIP_TRY(hipDeviceSynchronize());
     std::lock_guard<std::mutex> lk(I->mu);
+    if (e->mode == RTC_MODE_PERSISTENT) persist_reset(I);
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     if (a) HIP_TRY(hipMemcpy(I->d_a, a, I->n_act * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(I->d_p, 0, (size_t)I->n_act * 4));
@@ -933,6 +826,11 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
     HIP_TRY(hipSetDevice(e->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::lock_guard<std::mutex> lk(I->mu);
+    if (e->mode == RTC_MODE_PERSISTENT) {
+        if (I->cur_started) return RTC_E_STATE;
+        TRY(persist_batch(e, I, frames, frame_stride, n_frames, cmds, slopes, counts, st));
+        return last_error(e);
+    }
     for (int f = 0; f < n_frames; ++f) {
         FrameSet fs{};
         for (size_t w = 0; w < I->wfs.size(); ++w) fs.f[w] = frames[w] + (int64_t)f * frame_stride[w];
@@ -969,10 +867,13 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     if (!I->loaded) return RTC_E_STATE;
     if (n_iter < 0) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
+    if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
     hipStream_t st = static_cast<hipStream_t>(stream);
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
     E.n_parts = (int)I->seg.size();
+    E.n_kb = (int)I->kb.size();
+    E.kb_segs = I->d_kb_segs;
     E.count = I->d_count_t;
     E.y = I->d_yscratch;
     std::lock_guard<std::mutex> lk(I->mu);
@@ -986,6 +887,7 @@ rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *
                            uint64_t *masks) {
     Instance *I;
     TRY(check(e, inst, &I));
+    if (e->mode == RTC_MODE_PERSISTENT) return RTC_E_STATE;
     HIP_TRY(hipSetDevice(e->device));
     HIP_TRY(hipDeviceSynchronize());
     if (slopes) HIP_TRY(hipMemcpy(slopes, I->d_sout, I->n_slopes * 4, hipMemcpyDeviceToHost));
@@ -1038,6 +940,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
     WfsState &S = I->wfs[wfs];
     if (chunk < 0 || chunk >= S.d.n_chunks) return RTC_E_INVAL;
     std::lock_guard<std::mutex> lk(I->mu);
+    if (e->mode == RTC_MODE_PERSISTENT) return persist_submit(e, I, wfs, frame, chunk, rows, t_in);
     if (I->cur_frame != ~0ull && frame < I->cur_frame) return RTC_E_FRAME_DROPPED;
     if (frame < I->next_frame) return RTC_E_FRAME_DROPPED;
     if (I->cur_frame == ~0ull || frame > I->cur_frame) {
@@ -1115,6 +1018,7 @@ rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float 
     Instance *I;
     TRY(check(e, inst, &I));
     if (!cmds) return RTC_E_INVAL;
+    if (e->mode == RTC_MODE_PERSISTENT) return persist_wait(e, I, frame, cmds, timeout_ns, info);
     const int64_t t0 = now_ns();
     FrameSlot *sl = &I->slots[frame % I->slots.size()];
     for (;;) {

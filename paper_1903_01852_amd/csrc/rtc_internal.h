@@ -68,6 +68,12 @@ struct KBlock {
     int32_t wfs, chunk;
 };
 
+// One (sensor, chunk) of the readout order and the column block it completes
+// (-1 when the chunk completes no unit).
+struct Step {
+    int32_t wfs, chunk, kb, r;
+};
+
 // A segment is the part of one column block that one wavefront streams for a
 // tile: vectors [v0, v0 + nv) of block kb.  Each segment owns one partial
 // (its index in the global segment order).  The column range of every tile is
@@ -86,7 +92,9 @@ struct Piece {
 enum { EPI_NONE = 0, EPI_INTEGRATE = 1, EPI_REDUCE = 2 };
 struct MvmEpilogue {
     int32_t mode;          // EPI_*
-    int32_t n_parts;       // column-block partials per row (all launches of the frame)
+    int32_t n_parts;       // segment partials per row (all launches of the frame)
+    int32_t n_kb;          // column blocks; kb_segs[b] = {first segment, segments}
+    const int2 *kb_segs;
     uint32_t *count;       // per-tile arrival counters, zero between frames
     const float *p;        // INTEGRATE: POLC term (nullable)
     const float *scale;    // INTEGRATE: FP8 row scales (nullable)
@@ -95,6 +103,123 @@ struct MvmEpilogue {
     float *y;              // REDUCE: destination
     float c1, g;           // INTEGRATE: a = c1 a + g (y + p)
 };
+
+// ---------------------------------------------------------------------------
+// Persistent frame loop (rtc_persist.hip).
+
+// Work of one column block in the frame loop: its centroid tasks (one per SH
+// unit, one per 64 pyramid units) and its MVM tasks (segment x tile).  Task j
+// of a block goes to worker (base + j) mod n_workers.
+struct KbWork {
+    int32_t kind;          // RTC_WFS_*
+    int32_t wfs;
+    int32_t cu0, cu1;      // unit range in the SH or pyramid list
+    int32_t n_cen;         // centroid tasks
+    int32_t cen_base;
+    int32_t seg0, nseg;    // the block's segments
+    int32_t mvm_base;
+    int32_t r0, r1, r2;
+};
+
+// Frame coefficients a = c1 a + g (y + p): slot A for frames < q_switch,
+// slot B from q_switch on.
+struct Coef {
+    float c1[2], g[2];
+    uint64_t q_switch;
+};
+
+// Host-visible parameter block of a serving instance (pinned).  The host
+// writes the staged slot's values, then `word` = (q_switch << 1) | staged.
+struct ParamBlock {
+    float c1[2], g[2];
+    uint64_t word;
+};
+
+struct FrameTel {
+    uint64_t ticks_last_chunk;     // device clock when the frame's last chunk was seen
+    uint64_t ticks_publish;        // device clock when its commands were published
+};
+
+struct PersistInst {
+    // tables
+    const ShUnit *sh;
+    const PyrUnit *py;
+    int32_t n_sh, n_pyr;
+    const KBlock *kbs;
+    const KbWork *kbw;
+    const Segment *segs;
+    const int2 *kb_segs;
+    const Step *steps;
+    int32_t n_kb, n_seg, n_steps, n_wfs;
+    const WfsParam *wp;
+    // calibration
+    const float *sh_dark, *sh_flat, *sh_bg, *sh_thr;
+    const float *py_dark, *py_flat, *py_bg, *py_thr;
+    const float *ref;
+    // reconstruction matrix
+    const uint8_t *cm;
+    const float *scale;            // FP8 row scales or null
+    int32_t dtype, n_act, n_tiles, polc;
+    // POLC
+    const uint8_t *M;
+    const KBlock *kbm;
+    const Segment *segm;
+    const int2 *kbm_segs;
+    int32_t n_kbm, n_segm;
+    // state and scratch
+    float *s_pad[2];
+    float *y_part[2];
+    float *p_part[2];
+    float *y_acc, *p;
+    float *a;                      // two command buffers of a_stride floats (frame parity)
+    int32_t a_stride, r4;
+    uint64_t *cen_done, *mvm_done, *kbt_cnt, *acc_done, *tiles_done, *pol_cnt, *p_done;
+    uint64_t *pol_tiles;           // tiles whose POLC term is complete (all frames)
+    uint64_t *db_mirror;           // device copy of the doorbells, per sensor
+    uint64_t *drop_mirror;         // per mailbox slot: q + 1 of a dropped frame
+    // frame source
+    int32_t serving;
+    int32_t ring_depth;
+    const uint16_t *src[RTC_MAX_WFS];      // serving: pinned ring; batch: device frames
+    int64_t src_stride[RTC_MAX_WFS];       // uint16 per frame
+    const uint64_t *doorbell;              // pinned, per sensor: (q << 20) | chunks
+    const uint64_t *drop_host;             // pinned, per slot: q + 1 of a dropped frame
+    const ParamBlock *params;              // serving (pinned)
+    ParamBlock *param_mirror;              // serving (device)
+    Coef coef;                             // batch
+    // outputs
+    float *mail;                           // pinned, ring_depth x n_act (serving)
+    uint64_t *cmd_seq;                     // pinned: q + 1 of the last published frame
+    uint64_t *pol_seq;                     // pinned: q + 1 of the last frame whose POLC term is done
+    FrameTel *tel;                         // pinned, per slot
+    float *cmds_out;                       // batch, n_frames x n_act (nullable)
+    float *slopes_out;                     // batch, n_frames x n_slopes (nullable)
+    int32_t *counts_out;                   // batch (nullable)
+    int32_t n_slopes, n_units;
+    // frames and workers
+    uint64_t q_begin, q_end;               // sequence numbers processed by this launch
+    int32_t w0, w1;                        // worker range (a serving instance's first is its sentinel)
+    int32_t r3;
+};
+
+struct PersistArgs {
+    const PersistInst *inst;               // device array
+    int32_t n_inst;
+    int32_t r0;
+    const uint32_t *stop_host;             // pinned: nonzero asks the loop to exit
+    uint32_t *stop_dev;                    // device mirror of the stop request
+    uint32_t *status;                      // pinned: nonzero after a watchdog expiry
+    uint64_t dep_watchdog;                 // device-clock ticks a dependency wait may take
+    uint64_t idle_watchdog;                // device-clock ticks a doorbell wait may take
+};
+
+enum { PERSIST_OK = 0, PERSIST_WATCHDOG = 1 };
+constexpr uint64_t kDbChunkMask = (1ull << 20) - 1;
+constexpr int kDbShift = 20;
+constexpr int kMaxSegVectors = kPieceVectors;   // longest segment (slopes staged in LDS)
+
+void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args);
+int frame_loop_max_blocks_per_cu();
 
 // Launchers (defined in rtc_kernels.hip).
 void launch_sh_centroid(hipStream_t st, const ShUnit *units, int u0, int u1,

@@ -1,0 +1,570 @@
+// Host side of the persistent frame loop (RTC_MODE_PERSISTENT).
+//
+// Serving: the host copies each chunk into a pinned ring slot and rings the
+// sensor's doorbell; the resident kernel centroids, multiplies and integrates
+// on its own and publishes the commands into a pinned mailbox.  Batch: the
+// same kernel runs a finite run of device-resident frames.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "rtc_engine.h"
+
+using namespace rtc;
+
+namespace {
+
+constexpr uint64_t kIdleTicks = 10ull * 100000000ull;    // 10 s of the 100 MHz device clock
+constexpr uint64_t kDepTicks = 2ull * 100000000ull;      // 2 s for any internal dependency
+constexpr int64_t kStopTimeoutNs = 5000000000LL;
+
+uint64_t db_word(uint64_t q, uint64_t chunks) { return (q << kDbShift) | chunks; }
+
+volatile uint64_t *vol(uint64_t *p) { return reinterpret_cast<volatile uint64_t *>(p); }
+
+void store_release(uint64_t *p, uint64_t v) {
+    std::atomic_thread_fence(std::memory_order_release);
+    *vol(p) = v;
+}
+
+uint64_t load_acquire(uint64_t *p) {
+    const uint64_t v = *vol(p);
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return v;
+}
+
+// Fill the device-side descriptor of an instance (fields common to both uses).
+PersistInst describe(rtc_engine *e, Instance *I) {
+    PersistInstState &P = I->ps;
+    PersistInst d{};
+    d.sh = I->d_sh;
+    d.py = I->d_py;
+    d.n_sh = I->n_sh;
+    d.n_pyr = I->n_pyr;
+    d.kbs = I->d_kb;
+    d.kbw = P.kbw;
+    d.segs = I->d_seg;
+    d.kb_segs = I->d_kb_segs;
+    d.steps = nullptr;
+    d.n_kb = (int)I->kb.size();
+    d.n_seg = (int)I->seg.size();
+    d.n_steps = (int)I->steps.size();
+    d.n_wfs = (int)I->wfs.size();
+    d.wp = P.wp;
+    d.sh_dark = I->d_sh_dark;
+    d.sh_flat = I->d_sh_flat;
+    d.sh_bg = I->d_sh_bg;
+    d.sh_thr = I->d_sh_thr;
+    d.py_dark = I->d_py_dark;
+    d.py_flat = I->d_py_flat;
+    d.py_bg = I->d_py_bg;
+    d.py_thr = I->d_py_thr;
+    d.ref = I->d_ref;
+    d.cm = I->d_cm;
+    d.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr;
+    d.dtype = I->d.cm_dtype;
+    d.n_act = I->n_act;
+    d.n_tiles = I->n_tiles;
+    d.polc = I->d.polc;
+    d.M = I->d_M;
+    d.kbm = I->d_kbm;
+    d.segm = I->d_segm;
+    d.kbm_segs = I->d_kbm_segs;
+    d.n_kbm = (int)I->kbm.size();
+    d.n_segm = (int)I->segm.size();
+    d.s_pad[0] = I->d_spad;
+    d.s_pad[1] = P.spad2;
+    d.y_part[0] = I->d_ypart;
+    d.y_part[1] = P.ypart2;
+    d.p_part[0] = I->d_ppart;
+    d.p_part[1] = P.ppart2;
+    d.y_acc = P.yacc;
+    d.p = I->d_p;
+    d.a = I->d_a;
+    d.a_stride = I->a_len;
+    d.cen_done = P.cen_done;
+    d.mvm_done = P.mvm_done;
+    d.kbt_cnt = P.kbt_cnt;
+    d.acc_done = P.acc_done;
+    d.tiles_done = P.tiles_done;
+    d.pol_cnt = P.pol_cnt;
+    d.p_done = P.p_done;
+    d.db_mirror = P.db_mirror;
+    d.drop_mirror = P.drop_mirror;
+    d.ring_depth = e->ring_depth;
+    d.doorbell = P.doorbell;
+    d.drop_host = P.drop_host;
+    d.params = P.params;
+    d.param_mirror = P.param_mirror;
+    d.mail = I->h_mail;
+    d.cmd_seq = P.cmd_seq;
+    d.pol_seq = P.pol_seq;
+    d.pol_tiles = P.pol_tiles;
+    d.tel = P.tel;
+    d.n_slopes = I->n_slopes;
+    d.n_units = I->n_units;
+    return d;
+}
+
+// Device steps array lives in the kbw allocation's tail (see persist_alloc).
+Step *steps_dev(Instance *I) {
+    return reinterpret_cast<Step *>(I->ps.kbw + I->ps.kbw_h.size());
+}
+
+// Serving: descriptors of every instance through a synchronous copy (the
+// loop is launched rarely).  Batch: one descriptor through a pinned staging
+// slot and a copy ordered on the launch stream, so back-to-back batches on a
+// stream never overwrite a descriptor a running kernel still reads.
+rtc_status upload_and_launch(rtc_engine *e, std::vector<PersistInst> &descs, hipStream_t st,
+                             bool batch) {
+    PersistEngine &pe = e->pe;
+    PersistInst *dev = pe.d_inst;
+    if (!batch) {
+        HIP_TRY(hipMemcpy(pe.d_inst, descs.data(), descs.size() * sizeof(PersistInst),
+                          hipMemcpyHostToDevice));
+    } else {
+        const int k = pe.batch_slot;
+        pe.batch_slot ^= 1;
+        HIP_TRY(hipEventSynchronize(pe.batch_copied[k]));   // slot k's last copy has run
+        *pe.h_batch[k] = descs[0];
+        HIP_TRY(hipMemcpyAsync(pe.d_batch[k], pe.h_batch[k], sizeof(PersistInst),
+                               hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(pe.batch_copied[k], st));
+        dev = pe.d_batch[k];
+    }
+    *reinterpret_cast<volatile uint32_t *>(pe.stop_host) = 0;
+    *reinterpret_cast<volatile uint32_t *>(pe.status) = 0;
+    HIP_TRY(hipMemsetAsync(pe.stop_dev, 0, sizeof(uint32_t), st));
+    PersistArgs A{};
+    A.inst = dev;
+    A.n_inst = (int)descs.size();
+    A.stop_host = pe.stop_host;
+    A.stop_dev = pe.stop_dev;
+    A.status = pe.status;
+    A.dep_watchdog = kDepTicks;
+    A.idle_watchdog = kIdleTicks;
+    launch_frame_loop(st, pe.n_blocks, A);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) {
+        std::fprintf(stderr, "rtc: frame loop launch failed: %s\n", hipGetErrorString(err));
+        return fail(e, RTC_E_DEVICE);
+    }
+    return RTC_OK;
+}
+
+// Before a run starting at sequence q0 the state a_{q0-1} must sit in buffer
+// (q0 - 1) & 1; between runs it lives in buffer 0.
+rtc_status stage_state_in(Instance *I, uint64_t q0, hipStream_t st) {
+    if (((q0 - 1) & 1) == 1)
+        HIP_TRY(hipMemcpyAsync(I->d_a + I->a_len, I->d_a, (size_t)I->a_len * 4,
+                               hipMemcpyDeviceToDevice, st));
+    return RTC_OK;
+}
+rtc_status stage_state_out(Instance *I, uint64_t q_last, hipStream_t st) {
+    if ((q_last & 1) == 1)
+        HIP_TRY(hipMemcpyAsync(I->d_a, I->d_a + I->a_len, (size_t)I->a_len * 4,
+                               hipMemcpyDeviceToDevice, st));
+    return RTC_OK;
+}
+
+rtc_status launch_serving(rtc_engine *e) {
+    PersistEngine &pe = e->pe;
+    HIP_TRY(hipDeviceSynchronize());      // no batch work may still run on the state
+    const int W = pe.n_blocks * 4;
+    const int n = (int)e->inst.size();
+    // workers in proportion to the bytes each instance streams per frame
+    std::vector<double> wt(n);
+    double tot = 0;
+    for (int i = 0; i < n; ++i) {
+        wt[i] = (double)e->inst[i]->cm_bytes + (double)e->inst[i]->m_bytes;
+        tot += wt[i];
+    }
+    if (W < n * 66) return RTC_E_INVAL;
+    std::vector<PersistInst> descs;
+    int w = 0;
+    for (int i = 0; i < n; ++i) {
+        Instance *I = e->inst[i];
+        if (!I->loaded) return RTC_E_STATE;
+        int share = i == n - 1 ? W - w : (int)std::floor(wt[i] / tot * (W - n * 66)) + 66;
+        PersistInst d = describe(e, I);
+        d.steps = steps_dev(I);
+        d.serving = 1;
+        for (size_t s = 0; s < I->wfs.size(); ++s) {
+            d.src[s] = I->wfs[s].h_stage;
+            d.src_stride[s] = (int64_t)I->wfs[s].d.frame_h * I->wfs[s].d.frame_w;
+        }
+        d.q_begin = load_acquire(I->ps.cmd_seq);   // first frame not yet published
+        d.q_end = ~0ull;
+        d.w0 = w;
+        d.w1 = w + share;
+        I->ps.w0 = d.w0;
+        I->ps.w1 = d.w1;
+        w += share;
+        TRY(stage_state_in(I, d.q_begin, pe.stream));
+        descs.push_back(d);
+    }
+    TRY(upload_and_launch(e, descs, pe.stream, false));
+    pe.running = true;
+    pe.serving = true;
+    return RTC_OK;
+}
+
+bool stream_done(hipStream_t st) { return hipStreamQuery(st) == hipSuccess; }
+
+}  // namespace
+
+// Device buffers of the frame loop, for every instance of the engine.
+rtc_status persist_alloc(rtc_engine *e) {
+    PersistEngine &pe = e->pe;
+    HIP_TRY(hipStreamCreateWithFlags(&pe.stream, hipStreamNonBlocking));
+    TRY(host_pinned(e, &pe.stop_host, 1));
+    TRY(host_pinned(e, &pe.status, 1));
+    TRY(dev_alloc(e, &pe.stop_dev, 1));
+    TRY(dev_alloc(e, &pe.d_inst, e->inst.size()));
+    for (int k = 0; k < 2; ++k) {
+        TRY(dev_alloc(e, &pe.d_batch[k], 1));
+        TRY(host_pinned(e, &pe.h_batch[k], 1));
+        HIP_TRY(hipEventCreateWithFlags(&pe.batch_copied[k], hipEventDisableTiming));
+    }
+    int dev_cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, e->device));
+    // half the occupancy limit: the grid must be entirely resident, with room
+    // to spare for whatever else shares the device
+    const int per_cu = std::min(2, frame_loop_max_blocks_per_cu());
+    if (per_cu < 1) return RTC_E_DEVICE;
+    pe.n_blocks = dev_cus * per_cu;
+    for (Instance *I : e->inst) {
+        PersistInstState &P = I->ps;
+        const size_t nkb = I->kb.size(), nt = (size_t)I->n_tiles;
+        TRY(dev_alloc(e, &P.spad2, I->spad_len));
+        TRY(dev_alloc(e, &P.ypart2, I->seg.size() * (size_t)I->n_act));
+        TRY(dev_alloc(e, &P.ppart2, std::max<size_t>(I->segm.size(), 1) * (size_t)I->n_act));
+        TRY(dev_alloc(e, &P.yacc, I->n_act));
+        // counters, arrival counters twice (frame parity): cen_done, mvm_done
+        // [2][nkb]; kbt_cnt [2][nkb][nt]; pol_cnt [2][nt]; tiles_done [2];
+        // sequence values once: acc_done, p_done [nt]; pol_tiles [1]
+        P.n_ctr = 4 * nkb + 2 * nkb * nt + 2 * nt + 2 * nt + 2 + 1;
+        TRY(dev_alloc(e, &P.ctr, P.n_ctr));
+        P.cen_done = P.ctr;
+        P.mvm_done = P.cen_done + 2 * nkb;
+        P.kbt_cnt = P.mvm_done + 2 * nkb;
+        P.pol_cnt = P.kbt_cnt + 2 * nkb * nt;
+        P.acc_done = P.pol_cnt + 2 * nt;
+        P.p_done = P.acc_done + nt;
+        P.tiles_done = P.p_done + nt;
+        P.pol_tiles = P.tiles_done + 2;
+        TRY(dev_alloc(e, &P.db_mirror, I->wfs.size()));
+        TRY(dev_alloc(e, &P.drop_mirror, e->ring_depth));
+        TRY(dev_alloc(e, &P.param_mirror, 1));
+        TRY(dev_alloc(e, &P.wp, RTC_MAX_WFS));
+        HIP_TRY(hipMemcpy(P.wp, I->params.w, sizeof(I->params.w), hipMemcpyHostToDevice));
+        TRY(host_pinned(e, &P.doorbell, I->wfs.size()));
+        TRY(host_pinned(e, &P.drop_host, e->ring_depth));
+        TRY(host_pinned(e, &P.params, 1));
+        TRY(host_pinned(e, &P.cmd_seq, 1));
+        TRY(host_pinned(e, &P.pol_seq, 1));
+        TRY(host_pinned(e, &P.tel, e->ring_depth));
+        P.slot_frame.assign(e->ring_depth, ~0ull);
+        P.slot_t_last.assign(e->ring_depth, 0);
+        P.slot_dropped.assign(e->ring_depth, 0);
+        // work of each column block; task 0 of each list goes to the worker
+        // after the previous list's last task so that the load spreads evenly
+        int cen_base = 0, mvm_base = 0;
+        for (size_t b = 0; b < nkb; ++b) {
+            const KBlock &K = I->kb[b];
+            const WfsState &S = I->wfs[K.wfs];
+            KbWork W{};
+            W.kind = S.d.kind;
+            W.wfs = K.wfs;
+            const int ub = K.k0 / 2 - S.u0, ue = (K.k0 + K.k) / 2 - S.u0;
+            W.cu0 = S.kind0 + ub;
+            W.cu1 = S.kind0 + ue;
+            W.n_cen = S.d.kind == RTC_WFS_SH ? ue - ub : (ue - ub + kWave - 1) / kWave;
+            W.cen_base = cen_base;
+            W.seg0 = I->kb_seg0[b];
+            W.nseg = I->kb_nseg[b];
+            W.mvm_base = mvm_base;
+            cen_base += W.n_cen;
+            mvm_base += W.nseg * I->n_tiles;
+            P.kbw_h.push_back(W);
+        }
+        // one allocation: KbWork table followed by the readout steps
+        const size_t bytes = P.kbw_h.size() * sizeof(KbWork) + I->steps.size() * sizeof(Step);
+        uint8_t *buf = nullptr;
+        TRY(dev_alloc(e, &buf, bytes));
+        P.kbw = reinterpret_cast<KbWork *>(buf);
+        HIP_TRY(hipMemcpy(P.kbw, P.kbw_h.data(), P.kbw_h.size() * sizeof(KbWork),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(steps_dev(I), I->steps.data(), I->steps.size() * sizeof(Step),
+                          hipMemcpyHostToDevice));
+        for (const Segment &sg : I->seg)
+            if (sg.nv > kMaxSegVectors) return RTC_E_INVAL;
+        for (const Segment &sg : I->segm)
+            if (sg.nv > kMaxSegVectors) return RTC_E_INVAL;
+        TRY(persist_params(e, I));
+    }
+    return RTC_OK;
+}
+
+// Stop the frame loop (if running) and wait for every wavefront to exit.
+rtc_status persist_stop(rtc_engine *e) {
+    PersistEngine &pe = e->pe;
+    if (!pe.running) return RTC_OK;
+    *reinterpret_cast<volatile uint32_t *>(pe.stop_host) = 1;
+    const int64_t t0 = now_ns();
+    while (!stream_done(pe.stream)) {
+        if (now_ns() - t0 > kStopTimeoutNs) {
+            std::fprintf(stderr, "rtc: frame loop did not stop\n");
+            return fail(e, RTC_E_DEVICE);
+        }
+        std::this_thread::yield();
+    }
+    if (pe.serving) {
+        for (Instance *I : e->inst) {
+            const uint64_t pub = load_acquire(I->ps.cmd_seq);
+            if (pub > 0) TRY(stage_state_out(I, pub - 1, pe.stream));
+        }
+        HIP_TRY(hipStreamSynchronize(pe.stream));
+    }
+    pe.running = false;
+    pe.serving = false;
+    if (*reinterpret_cast<volatile uint32_t *>(pe.status) != PERSIST_OK) {
+        std::fprintf(stderr, "rtc: frame loop ended on a watchdog\n");
+        return fail(e, RTC_E_DEVICE);
+    }
+    return RTC_OK;
+}
+
+// Stop the serving loop once every started frame is published and its POLC
+// term is formed, so that counters and state stay consistent for a restart.
+rtc_status persist_quiesce(rtc_engine *e) {
+    PersistEngine &pe = e->pe;
+    if (!pe.running) return RTC_OK;
+    if (pe.serving) {
+        const int64_t t0 = now_ns();
+        for (Instance *I : e->inst) {
+            if (I->cur_started) return RTC_E_STATE;   // a frame is half delivered
+            PersistInstState &P = I->ps;
+            while (load_acquire(P.cmd_seq) < P.seq ||
+                   (I->d.polc && load_acquire(P.pol_seq) < P.seq)) {
+                if (stream_done(pe.stream) || now_ns() - t0 > kStopTimeoutNs)
+                    return fail(e, RTC_E_DEVICE);
+                std::this_thread::yield();
+            }
+        }
+    }
+    return persist_stop(e);
+}
+
+void persist_free(rtc_engine *e) {
+    PersistEngine &pe = e->pe;
+    for (int k = 0; k < 2; ++k)
+        if (pe.batch_copied[k]) (void)hipEventDestroy(pe.batch_copied[k]);
+    if (pe.stream) (void)hipStreamDestroy(pe.stream);
+}
+
+// Zero every frame-loop counter and sequence (the loop must be stopped).
+void persist_reset(Instance *I) {
+    PersistInstState &P = I->ps;
+    (void)hipMemset(P.ctr, 0, P.n_ctr * sizeof(uint64_t));
+    (void)hipMemset(P.db_mirror, 0, I->wfs.size() * sizeof(uint64_t));
+    (void)hipMemset(P.drop_mirror, 0, P.slot_frame.size() * sizeof(uint64_t));
+    for (size_t w = 0; w < I->wfs.size(); ++w) *vol(P.doorbell + w) = 0;
+    for (size_t k = 0; k < P.slot_frame.size(); ++k) *vol(P.drop_host + k) = 0;
+    *vol(P.cmd_seq) = 0;
+    *vol(P.pol_seq) = 0;
+    P.seq = 0;
+    P.q_cur = 0;
+    std::fill(P.slot_frame.begin(), P.slot_frame.end(), ~0ull);
+    std::fill(P.slot_dropped.begin(), P.slot_dropped.end(), 0);
+    (void)persist_params(nullptr, I);
+}
+
+// Coefficients of both parameter slots into the pinned block, switching at
+// the first frame that has not started.
+rtc_status persist_params(rtc_engine *e, Instance *I) {
+    (void)e;
+    PersistInstState &P = I->ps;
+    const int staged = 1 - I->active;
+    ParamBlock pb{};
+    for (int s = 0; s < 2; ++s) {
+        const double gd = I->gain[s], ld = I->leak[s];
+        pb.g[s] = (float)gd;
+        pb.c1[s] = I->d.polc ? (float)(1.0 - ld - gd) : (float)(1.0 - ld);
+    }
+    const uint64_t q_switch = I->pending ? (I->cur_started ? P.q_cur + 1 : P.seq) : ~0ull >> 2;
+    volatile ParamBlock *h = P.params;
+    for (int s = 0; s < 2; ++s) {
+        h->c1[s] = pb.c1[s];
+        h->g[s] = pb.g[s];
+    }
+    P.param_word = (q_switch << 1) | (uint64_t)staged;
+    store_release(&P.params->word, P.param_word);
+    return RTC_OK;
+}
+
+rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                          const uint16_t *rows, int64_t t_in) {
+    PersistInstState &P = I->ps;
+    PersistEngine &pe = e->pe;
+    WfsState &S = I->wfs[w];
+    if (pe.running && !pe.serving) return RTC_E_STATE;
+    if (I->cur_frame != ~0ull && frame < I->cur_frame) return RTC_E_FRAME_DROPPED;
+    if (frame < I->next_frame) return RTC_E_FRAME_DROPPED;
+    if (I->cur_frame == ~0ull || frame > I->cur_frame) {
+        const uint64_t pub = load_acquire(P.cmd_seq);
+        const uint64_t q = P.seq;
+        if (q - pub >= (uint64_t)e->ring_depth) return RTC_E_RING_FULL;
+        if (I->cur_frame != ~0ull && I->cur_started) {
+            // the frame in progress never completed: deliver it as dropped (the
+            // loop skips its integrator update) so the loop can move on
+            const uint64_t qd = P.q_cur;
+            P.slot_dropped[qd % P.slot_dropped.size()] = 1;
+            I->drops++;
+            store_release(P.drop_host + qd % P.slot_dropped.size(), qd + 1);
+            for (size_t s = 0; s < I->wfs.size(); ++s)
+                if (I->wfs[s].next_chunk < I->wfs[s].d.n_chunks)
+                    store_release(P.doorbell + s, db_word(qd, I->wfs[s].d.n_chunks));
+        }
+        if (I->pending && frame >= I->f_switch) settle_params(I, frame);
+        P.q_cur = q;
+        P.seq = q + 1;
+        const size_t slot = q % P.slot_frame.size();
+        P.slot_frame[slot] = frame;
+        P.slot_dropped[slot] = 0;
+        P.slot_t_last[slot] = 0;
+        I->cur_frame = frame;
+        I->cur_started = false;
+        for (auto &W : I->wfs) W.next_chunk = 0;
+        if (pe.running && stream_done(pe.stream)) {
+            // the loop left on its own: after an idle period (fine) or a watchdog
+            pe.running = false;
+            pe.serving = false;
+            if (*reinterpret_cast<volatile uint32_t *>(pe.status) != PERSIST_OK)
+                return fail(e, RTC_E_DEVICE);
+        }
+        if (!pe.running) TRY(launch_serving(e));
+    }
+    if (chunk != S.next_chunk) return RTC_E_INVAL;
+    const uint64_t q = P.q_cur;
+    const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
+    const int r0 = S.row0[chunk], r1 = S.row0[chunk + 1];
+    const size_t off = (size_t)(q % (uint64_t)e->ring_depth) * fpx + (size_t)r0 * S.d.frame_w;
+    std::memcpy(S.h_stage + off, rows, (size_t)(r1 - r0) * S.d.frame_w * 2);
+    store_release(P.doorbell + w, db_word(q, (uint64_t)chunk + 1));
+    S.next_chunk++;
+    I->cur_started = true;
+    bool all = true;
+    for (auto &W : I->wfs) all = all && W.next_chunk == W.d.n_chunks;
+    if (all) {
+        P.slot_t_last[q % P.slot_t_last.size()] = t_in;
+        I->next_frame = frame + 1;
+        I->cur_frame = ~0ull;
+        I->cur_started = false;
+    }
+    return RTC_OK;
+}
+
+rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
+                        int64_t timeout_ns, rtc_frame_info *info) {
+    PersistInstState &P = I->ps;
+    const int64_t t0 = now_ns();
+    const size_t depth = P.slot_frame.size();
+    uint64_t q = ~0ull;
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(I->mu);
+            for (uint64_t k = 0; k < depth && P.seq > k; ++k) {
+                const uint64_t qq = P.seq - 1 - k;
+                if (P.slot_frame[qq % depth] == frame) {
+                    q = qq;
+                    break;
+                }
+            }
+            if (q == ~0ull && frame < I->next_frame && I->cur_frame != frame)
+                return RTC_E_FRAME_DROPPED;    // too old, or never started
+        }
+        if (q != ~0ull) break;
+        if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
+        std::this_thread::yield();
+    }
+    const size_t slot = q % depth;
+    for (;;) {
+        if (load_acquire(P.cmd_seq) >= q + 1) break;
+        if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
+        if (e->pe.running && stream_done(e->pe.stream)) return fail(e, RTC_E_DEVICE);
+    }
+    const int64_t t_ready = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(I->mu);
+        if (P.slot_frame[slot] != frame) return RTC_E_FRAME_DROPPED;   // slot reused
+        if (P.slot_dropped[slot]) return RTC_E_FRAME_DROPPED;
+    }
+    std::memcpy(cmds, I->h_mail + slot * (size_t)I->n_act, (size_t)I->n_act * 4);
+    if (load_acquire(P.cmd_seq) >= q + 1 + depth) return RTC_E_FRAME_DROPPED;   // overwritten
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->frame = frame;
+        info->t_last_chunk_ns = P.slot_t_last[slot];
+        info->t_ready_ns = t_ready;
+        volatile FrameTel *tel = P.tel + slot;
+        info->dev_ticks_start = tel->ticks_last_chunk;
+        info->dev_ticks_cmd = tel->ticks_publish;
+        info->drops = I->drops;
+    }
+    return RTC_OK;
+}
+
+rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *frames,
+                         const int64_t *frame_stride, int32_t n_frames, float *cmds,
+                         float *slopes, int32_t *counts, hipStream_t st) {
+    PersistEngine &pe = e->pe;
+    if (n_frames == 0) return RTC_OK;
+    if (pe.running) TRY(persist_quiesce(e));
+    PersistInstState &P = I->ps;
+    PersistInst d = describe(e, I);
+    d.steps = steps_dev(I);
+    d.serving = 0;
+    for (size_t s = 0; s < I->wfs.size(); ++s) {
+        d.src[s] = frames[s];
+        d.src_stride[s] = frame_stride[s];
+    }
+    d.q_begin = P.seq;
+    d.q_end = P.seq + (uint64_t)n_frames;
+    // coefficients: slot 0 = active parameters, slot 1 = staged ones from the
+    // first frame at or after the pending switch
+    const int a = I->active;
+    for (int s = 0; s < 2; ++s) {
+        const int src = s == 0 ? a : 1 - a;
+        const double gd = I->gain[src], ld = I->leak[src];
+        d.coef.g[s] = (float)gd;
+        d.coef.c1[s] = I->d.polc ? (float)(1.0 - ld - gd) : (float)(1.0 - ld);
+    }
+    d.coef.q_switch = ~0ull;
+    const uint64_t f0 = I->next_frame;
+    if (I->pending) {
+        const uint64_t fs = std::max(I->f_switch, f0);
+        if (fs < f0 + (uint64_t)n_frames) {
+            d.coef.q_switch = d.q_begin + (fs - f0);
+            settle_params(I, fs);
+        }
+    }
+    d.cmds_out = cmds;
+    d.slopes_out = slopes;
+    d.counts_out = counts;
+    d.w0 = 0;
+    d.w1 = pe.n_blocks * 4;
+    // this instance alone; the other descriptors must not claim workers
+    std::vector<PersistInst> descs(1, d);
+    TRY(stage_state_in(I, d.q_begin, st));
+    TRY(upload_and_launch(e, descs, st, true));
+    TRY(stage_state_out(I, d.q_end - 1, st));
+    P.seq = d.q_end;
+    I->next_frame += (uint64_t)n_frames;
+    return RTC_OK;
+}

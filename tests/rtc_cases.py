@@ -91,7 +91,7 @@ def run_stream(eng, idx: int, case: Case, n: int | None = None, first_frame: int
     for f in range(n):
         frame_no = first_frame + f
         for w, bank in enumerate(case.frames):
-            img = bank[f % bank.shape[0]]
+            img = bank[frame_no % bank.shape[0]]
             for c in range(case.inst.wfs[w].n_chunks):
                 r0, r1 = eng.chunk_rows(idx, w, c)
                 eng.submit_chunk(idx, w, frame_no, c, img[r0:r1])

@@ -1,0 +1,198 @@
+"""GPU tests of the persistent frame loop (RTC_MODE_PERSISTENT).
+
+The frame loop must give bit for bit the commands of the per-launch path (the
+same partials summed in the same order), and match the oracle to the same
+bars as the per-launch path.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from rtc_cases import TOL, Case, log, rel_l2, run_batch, run_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rtc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01852_amd import rtc as mod
+    mod.lib()
+    return mod
+
+
+def _mid_case(polc: bool, n_frames: int = 30, polc_m: str = "from_D", index: int = 92):
+    wfs = synth.ShWfs(nsub=24, px=10, obs=0.28, frame_h=240, frame_w=240, n_chunks=6)
+    inst = synth.Instance(f"mid{index}", (wfs,), 700, ("f32",), polc=polc, gain=0.4, leak=0.01)
+    wl = synth.Workload(index, f"mid{index}", (inst,), n_frames=n_frames, bank=n_frames)
+    synth.workloads.WORKLOADS[wl.name] = wl
+    try:
+        return Case(wl.name, n_frames=n_frames, polc_m=polc_m)
+    finally:
+        del synth.workloads.WORKLOADS[wl.name]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
+def test_frame_loop_batch_equals_launch_path(rtc, dtype):
+    case = Case("scao_sh_74", n_frames=6)
+    log(f"case scao_sh_74 {dtype}: frame loop vs per-launch, 6 frames")
+    with rtc.Engine([(case.inst, dtype)], mode="stream") as e1:
+        case.load(e1)
+        c1, s1, n1 = run_batch(e1, 0, case)
+    with rtc.Engine([(case.inst, dtype)], mode="persistent") as e2:
+        case.load(e2)
+        c2, s2, n2 = run_batch(e2, 0, case)
+    assert np.array_equal(n1, n2)
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(c1, c2)
+
+
+def test_frame_loop_small_sh_vs_oracle(rtc):
+    case = Case("scao_sh_small", n_frames=200)
+    log("case scao_sh_small frame loop 200 frames")
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        cmds, slopes, counts = run_batch(eng, 0, case)
+        a, p, nf = eng.get_state(0)
+    ref = case.run_oracle("f32")
+    assert np.array_equal(counts, ref["counts"])
+    assert np.abs(slopes - ref["slopes"]).max() <= 1e-4
+    rel = rel_l2(cmds, ref["commands"])
+    log(f"  max rel L2 {rel.max():.3e}")
+    assert rel.max() <= TOL["f32"]
+    assert np.array_equal(a, cmds[-1].astype(np.float32)) and nf == 200
+
+
+def test_frame_loop_pyramid_equals_launch_path(rtc):
+    case = Case("scao_pyr_92", n_frames=5)
+    log("case scao_pyr_92 bf16 frame loop vs per-launch")
+    outs = []
+    for mode in ("stream", "persistent"):
+        with rtc.Engine([(case.inst, "bf16")], mode=mode) as eng:
+            case.load(eng)
+            outs.append(run_batch(eng, 0, case))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_frame_loop_polc_vs_oracle_and_launch_path(rtc):
+    case = _mid_case(True, n_frames=30)
+    log("case mid POLC (D given) frame loop, 30 frames")
+    outs = []
+    for mode in ("stream", "persistent"):
+        with rtc.Engine([(case.inst, "f32")], mode=mode) as eng:
+            case.load(eng)
+            outs.append(run_batch(eng, 0, case))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    ref = case.run_oracle("f32")
+    rel = rel_l2(outs[1][0], ref["commands"])
+    log(f"  max rel L2 {rel.max():.3e}")
+    assert rel.max() <= TOL["f32"]
+
+
+def test_frame_loop_batches_continue_state(rtc):
+    """Two back-to-back batches equal one batch of both (state carried on the device)."""
+    import torch
+    case = _mid_case(True, n_frames=20, index=93)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        whole, _, _ = run_batch(eng, 0, case)
+        eng.set_state(0, None, None, 0)
+        dfr = [torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in case.frames]
+        out = torch.zeros((20, case.inst.n_act), dtype=torch.float32, device="cuda")
+        st = torch.cuda.current_stream()
+        eng.process_frames(0, [d[:7].contiguous() for d in dfr], 7, cmds=out[:7], stream=st)
+        eng.process_frames(0, [d[7:].contiguous() for d in dfr], 13, cmds=out[7:], stream=st)
+        torch.cuda.synchronize()
+    assert np.array_equal(whole, out.cpu().numpy().astype(np.float64))
+
+
+def test_serving_frame_loop_equals_batch(rtc):
+    """Chunks through the pinned ring and doorbells give the batch commands bit for bit."""
+    case = Case("scao_sh_small", n_frames=40)
+    log("case scao_sh_small serving frame loop, 40 frames")
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        served, infos = run_stream(eng, 0, case)
+        eng.set_state(0, None, None, 0)
+        batch, _, _ = run_batch(eng, 0, case)
+    assert np.array_equal(served, batch)
+    assert all(i["t_ready_ns"] >= i["t_last_chunk_ns"] > 0 for i in infos)
+    assert all(i["dev_ticks_cmd"] >= i["dev_ticks_start"] > 0 for i in infos)
+    ref = case.run_oracle("f32")
+    assert rel_l2(served, ref["commands"]).max() <= TOL["f32"]
+
+
+def test_serving_two_instances_uneven_sizes(rtc):
+    """Two instances of different sizes share one frame loop; each gives its solo commands."""
+    big = _mid_case(True, n_frames=12, index=94)
+    small = Case("scao_sh_small", n_frames=12)
+    log("case two instances (mid POLC + small) in one frame loop")
+    solo = []
+    for case in (big, small):
+        with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+            case.load(eng)
+            solo.append(run_stream(eng, 0, case)[0])
+    with rtc.Engine([(big.inst, "f32"), (small.inst, "f32")], mode="persistent") as eng:
+        big.load(eng, 0)
+        small.load(eng, 1)
+        got = {0: [], 1: []}
+        for f in range(12):
+            # interleave the two cameras chunk by chunk
+            plans = []
+            for idx, case in ((0, big), (1, small)):
+                img = case.frames[0][f]
+                for c in range(case.inst.wfs[0].n_chunks):
+                    r0, r1 = eng.chunk_rows(idx, 0, c)
+                    plans.append((idx, c, img[r0:r1]))
+            plans.sort(key=lambda x: x[1])
+            for idx, c, rows in plans:
+                eng.submit_chunk(idx, 0, f, c, rows)
+            for idx in (0, 1):
+                got[idx].append(eng.wait_commands(idx, f)[0].astype(np.float64))
+    assert np.array_equal(np.stack(got[0]), solo[0])
+    assert np.array_equal(np.stack(got[1]), solo[1])
+
+
+def test_serving_gain_leak_switch(rtc):
+    """rtc_set_params between frames: the oracle's switch closed form, frame for frame."""
+    case = Case("scao_sh_small", n_frames=30)
+    k = 12
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        first, _ = run_stream(eng, 0, case, n=k)
+        f_eff = eng.set_params(0, 0.3, 0.02)
+        assert f_eff == k
+        rest, _ = run_stream(eng, 0, case, n=30 - k, first_frame=k)
+    got = np.concatenate([first, rest])
+    inst2 = synth.Instance(case.inst.name, case.inst.wfs, case.inst.n_act, ("f32",),
+                           gain=case.inst.gain, leak=case.inst.leak, switch=(k, 0.3, 0.02))
+    ref = oracle.run(inst2, case.frames, case.cals, case.R, 30)
+    rel = rel_l2(got, ref["commands"])
+    log(f"  max rel L2 {rel.max():.3e}")
+    assert rel.max() <= TOL["f32"]
+
+
+def test_serving_dropped_frame(rtc):
+    """A frame superseded before its last chunk leaves the commands untouched."""
+    case = Case("scao_sh_small", n_frames=8)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        got = []
+        for f in range(8):
+            img = case.frames[0][f]
+            n_ch = case.inst.wfs[0].n_chunks
+            last = 1 if f == 3 else n_ch          # frame 3 delivers only its first chunk
+            for c in range(last):
+                r0, r1 = eng.chunk_rows(0, 0, c)
+                eng.submit_chunk(0, 0, f, c, img[r0:r1])
+            if f != 3:
+                got.append(eng.wait_commands(0, f)[0].astype(np.float64))
+        assert eng.wait_status(0, 3, 0.1) == -7
+    kept = [0, 1, 2, 4, 5, 6, 7]
+    frames = [case.frames[0][kept]]
+    ref = oracle.run(case.inst, frames, case.cals, case.R, 7)
+    assert rel_l2(np.stack(got), ref["commands"]).max() <= TOL["f32"]
