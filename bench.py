@@ -1,17 +1,21 @@
 """Benchmark of the pixel -> command hot path on one MI355X.
 
 A step is one frame through every stage: calibration + slopes for every
-sensor, the split-K control-matrix MVM, the partial sum + integrator (and the
-POLC product when the workload has it).  Frames are resident in HBM before the
-timed region; ``value`` is frames per second.
+sensor, the split-K control-matrix MVM, the in-order accumulation +
+integrator (and the POLC product when the workload has it).  Frames are
+resident in HBM before the timed region and run through the persistent frame
+loop in batches of `--bank` frames per launch; ``value`` is frames per second.
 
 Also reported on the same JSON line:
-  latency_us   serving-path latency (last chunk submitted from host memory ->
-               commands seen on the host), frames paced at 500 Hz with the
-               chunks spread over a 1.5 ms readout; this figure includes PCIe;
-  roofline     the MVM kernel's algorithmic bytes / its average duration,
-               from HIP events on the stream it runs on;
-  variants     the same step with BF16 and FP8 matrix storage;
+  latency_us   serving-path latency of the persistent loop (last chunk
+               submitted from host memory -> commands seen on the host), frames
+               paced at 500 Hz with the chunks spread over a 1.5 ms readout;
+               this figure includes PCIe;
+  roofline     the frame-loop kernel's algorithmic bytes per launch / its
+               average launch duration, from HIP events on its stream;
+  mvm          the standalone split-K MVM kernel (warm and after a cache flush);
+  variants     the same step with BF16 and FP8 matrix storage, and the
+               per-launch (non-persistent) path;
   cpu_baseline the CPU oracle on a bounded sample of the same frames.
 """
 from __future__ import annotations
@@ -49,9 +53,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("rtc_device.h", "rtc_internal.h", "rtc_kernels.hip", "rtc_persist.hip")
+
+
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1903_01852_amd", "csrc", "rtc_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1903_01852_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str, dtype: str):
@@ -89,7 +98,20 @@ def build_inputs(workload: str, bank: int):
     return wl, inst, frames, cals, R, M
 
 
-def make_engine(rtc, inst, dtype, cals, R, M, mode="stream"):
+def alg_bytes_per_frame(inst, info, dtype):
+    """Bytes the method must move per frame: matrix (+ FP8 scales), POLC matrix,
+    processed pixels (2 B) and their calibration (dark, flat, bg: 12 B), slopes,
+    commands read and written."""
+    px = 0
+    for w in inst.wfs:
+        px += w.n_units * (w.px * w.px if w.kind == "sh" else 4)
+    b = inst.n_act * info["n_slopes"] * ELEM[dtype] + (4 * inst.n_act if dtype == "fp8" else 0)
+    if inst.polc:
+        b += 4 * inst.n_act * inst.n_act
+    return b + 14 * px + 4 * info["n_slopes"] + 8 * inst.n_act
+
+
+def make_engine(rtc, inst, dtype, cals, R, M, mode="persistent"):
     eng = rtc.Engine([(inst, dtype)], ring_depth=4, mode=mode)
     eng.load_matrices(0, R, M=M)
     for w, cal in enumerate(cals):
@@ -106,14 +128,26 @@ def run_steps(eng, dframes, bank, n, stream):
 
 
 def throughput(torch, eng, dframes, bank, steps, warmup):
+    """Wall time of `steps` frames, and the average duration of one launch
+    (`bank` frames) from HIP events recorded on the launch stream."""
     st = torch.cuda.current_stream()
     run_steps(eng, dframes, bank, warmup, st)
     torch.cuda.synchronize()
+    n_launch = (steps + bank - 1) // bank
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n_launch)]
     t0 = time.perf_counter()
-    run_steps(eng, dframes, bank, steps, st)
+    done = 0
+    for a, b in ev:
+        k = min(bank, steps - done)
+        a.record(st)
+        eng.process_frames(0, dframes, k, stream=st)
+        b.record(st)
+        done += k
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt
+    full = [a.elapsed_time(b) / 1e3 for a, b in ev[:steps // bank]]
+    return dt, (sum(full) / len(full) if full else None)
 
 
 def mvm_timing(torch, eng, n_iter=200, cold=False):
@@ -215,7 +249,7 @@ def main():
     ap.add_argument("--workload", default="scao_sh_74")
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--variants", default="bf16,fp8")
-    ap.add_argument("--bank", type=int, default=32)
+    ap.add_argument("--bank", type=int, default=64)
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
@@ -239,11 +273,16 @@ def main():
     wl, inst, frames, cals, R, M = build_inputs(args.workload, args.bank)
     dframes = [torch.from_numpy(f).cuda() for f in frames]
 
-    def one(dtype, full):
-        eng = make_engine(rtc, inst, dtype, cals, R, M)
+    def one(dtype, full, mode="persistent"):
+        eng = make_engine(rtc, inst, dtype, cals, R, M, mode=mode)
         info = eng.infos[0]
-        dt = throughput(torch, eng, dframes, args.bank, args.steps, args.warmup)
-        res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps}
+        dt, launch_s = throughput(torch, eng, dframes, args.bank, args.steps, args.warmup)
+        res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+               "alg_bytes_per_frame": alg_bytes_per_frame(inst, info, dtype)}
+        if launch_s is not None:
+            res["launch_us"] = launch_s * 1e6
+            res["frames_per_launch"] = args.bank
+            res["loop_gbs"] = res["alg_bytes_per_frame"] * args.bank / launch_s / 1e9
         if full:
             warm = mvm_timing(torch, eng)
             cold = mvm_timing(torch, eng, cold=True)
@@ -271,6 +310,9 @@ def main():
             e2, r2 = one(dt_name, True)
             e2.close()
             variants[dt_name] = r2
+        e3, r3 = one(args.dtype, False, mode="stream")
+        e3.close()
+        variants[f"{args.dtype}_per_launch_path"] = r3
 
     latency = None
     if not args.quick and not args.no_latency:
@@ -285,16 +327,18 @@ def main():
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline(inst, frames, cals, R, M)
 
-    achieved = main_res["gbs_warm"]
+    achieved = main_res["loop_gbs"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, args.dtype),
-            "kernel": f"k_mvm<{args.dtype}>",
-            "avg_launch_us": round(main_res["mvm_us_warm"], 3),
-            "algorithmic_bytes_per_launch": main_res["alg_bytes"],
-            "cold_achieved": round(main_res["gbs_cold"], 1),
-            "cold_frac": round(main_res["gbs_cold"] / HBM_PEAK_GBS, 4),
-            "cold_avg_launch_us": round(main_res["mvm_us_cold"], 3)}
+            "kernel": "k_frame_loop",
+            "avg_launch_us": round(main_res["launch_us"], 3),
+            "frames_per_launch": args.bank,
+            "algorithmic_bytes_per_launch": main_res["alg_bytes_per_frame"] * args.bank}
+    mvm = {"kernel": f"k_mvm<{args.dtype}>", "alg_bytes": main_res["alg_bytes"],
+           "warm_us": round(main_res["mvm_us_warm"], 3), "warm_gbs": round(main_res["gbs_warm"], 1),
+           "cold_us": round(main_res["mvm_us_cold"], 3), "cold_gbs": round(main_res["gbs_cold"], 1),
+           "cold_frac": round(main_res["gbs_cold"] / HBM_PEAK_GBS, 4)}
     out = {
         "metric": METRIC, "value": round(main_res["frames_per_s"], 1), "unit": "frames/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -305,6 +349,7 @@ def main():
         "config": {"workload": args.workload, "description": WORKLOAD_TEXT.get(args.workload),
                    "frames_in_bank": args.bank, "cm_storage": args.dtype},
         "roofline": roof,
+        "mvm": mvm,
         "latency_us": latency,
         "variants": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                          for kk, vv in v.items()} for k, v in variants.items()},

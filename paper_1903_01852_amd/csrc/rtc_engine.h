@@ -61,6 +61,7 @@ struct PersistInstState {
     size_t n_ctr = 0;
     uint64_t *cen_done = nullptr, *mvm_done = nullptr, *kbt_cnt = nullptr, *acc_done = nullptr;
     uint64_t *tiles_done = nullptr, *pol_cnt = nullptr, *p_done = nullptr, *pol_tiles = nullptr;
+    uint64_t *join = nullptr;
     uint64_t *db_mirror = nullptr, *drop_mirror = nullptr;
     ParamBlock *param_mirror = nullptr;
     KbWork *kbw = nullptr;

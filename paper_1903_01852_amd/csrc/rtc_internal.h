@@ -175,6 +175,7 @@ struct PersistInst {
     int32_t a_stride, r4;
     uint64_t *cen_done, *mvm_done, *kbt_cnt, *acc_done, *tiles_done, *pol_cnt, *p_done;
     uint64_t *pol_tiles;           // tiles whose POLC term is complete (all frames)
+    uint64_t *join;                // [2][n_kb][n_tiles] block-accumulation joins
     uint64_t *db_mirror;           // device copy of the doorbells, per sensor
     uint64_t *drop_mirror;         // per mailbox slot: q + 1 of a dropped frame
     // frame source

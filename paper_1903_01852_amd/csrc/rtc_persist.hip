@@ -298,56 +298,81 @@ __device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Accumulate column block kb of frame q into tile t (run by the wavefront
-// that completed the block's last segment on the tile).  Blocks are added in
-// readout order, each block's segments in order: the same arithmetic as the
-// per-launch epilogue.  The last block applies the FP8 row scale, the POLC
-// term and the leaky integrator, and publishes the tile's commands.
-__device__ bool accumulate_block(const PersistInst &I, const PersistArgs &A, uint64_t q, int kb,
-                                 int t, int lane) {
+// Block accumulation as a join.  Accumulating block kb of frame q on tile t
+// needs (E) every partial of the block on the tile, (A) the previous block
+// accumulated (block n_kb - 1 of frame q - 1 for kb = 0) and, for the last
+// block with POLC, (P) the POLC term of the tile.  Each party adds one to the
+// block's join counter; the party that completes the count does the work, so
+// nobody ever waits, and then joins the next block as its (A) party.  Join
+// counters are doubled by frame parity like the arrival counters; the first
+// frame after a reset finds its (A) and (P) parts pre-counted by the host.
+__device__ __forceinline__ uint64_t join_need(const PersistInst &I, int kb) {
+    return (I.polc && kb == I.n_kb - 1) ? 3 : 2;
+}
+__device__ __forceinline__ uint64_t *join_ctr(const PersistInst &I, uint64_t q, int kb, int t) {
+    return I.join + ((size_t)(q & 1) * I.n_kb + kb) * I.n_tiles + t;
+}
+// True when this wavefront's arrival completes the join of (q, kb, t).
+__device__ __forceinline__ bool join(const PersistInst &I, uint64_t q, int kb, int t, int lane) {
+    uint64_t old = 0;
+    if (lane == 0) old = add_agent64(join_ctr(I, q, kb, t), 1);
+    old = __shfl(old, 0, kWave);
+    return (old + 1) % join_need(I, kb) == 0;
+}
+
+// Accumulate block kb of frame q into tile t, then every following block
+// whose join this completes.  Blocks are added in readout order, each block's
+// segments in order: the same arithmetic as the per-launch epilogue.  The
+// last block applies the FP8 row scale, the POLC term and the leaky
+// integrator, and publishes the tile's commands.
+__device__ void run_chain(const PersistInst &I, uint64_t q, int kb, int t, int lane) {
     const uint64_t nkb = (uint64_t)I.n_kb;
-    if (!wait_geq(I.acc_done + t, q * nkb + (uint64_t)kb, A, A.dep_watchdog)) return false;
-    const bool last_block = kb == I.n_kb - 1;
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
-    if (last_block && I.polc)
-        if (!wait_geq(I.p_done + t, q, A, A.dep_watchdog)) return false;
-    if (lane < nr) {
-        const int2 sb = I.kb_segs[kb];
-        float y = kb == 0 ? 0.0f : load_agent(I.y_acc + r);
-        y += sum_parts(I.y_part[q & 1], sb.x, sb.y, I.n_act, r);
-        if (!last_block) {
-            st_agent(I.y_acc + r, y);
-        } else {
-            float c1, g;
-            frame_coef(I, q, c1, g);
-            if (I.scale != nullptr) y *= I.scale[r];
-            if (I.polc) y += load_agent(I.p + r);
-            const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
-            bool dropped = false;
-            if (I.serving)
-                dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
-            const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
-            st_agent(a_buf(I, q) + r, an);
-            if (I.serving)
-                st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
-            else if (I.cmds_out != nullptr)
-                I.cmds_out[(size_t)(q - I.q_begin) * I.n_act + r] = an;
+    for (;;) {
+        const bool last_block = kb == I.n_kb - 1;
+        if (lane < nr) {
+            const int2 sb = I.kb_segs[kb];
+            float y = kb == 0 ? 0.0f : load_agent(I.y_acc + r);
+            y += sum_parts(I.y_part[q & 1], sb.x, sb.y, I.n_act, r);
+            if (!last_block) {
+                st_agent(I.y_acc + r, y);
+            } else {
+                float c1, g;
+                frame_coef(I, q, c1, g);
+                if (I.scale != nullptr) y *= I.scale[r];
+                if (I.polc) y += load_agent(I.p + r);
+                const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
+                bool dropped = false;
+                if (I.serving)
+                    dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
+                const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
+                st_agent(a_buf(I, q) + r, an);
+                if (I.serving)
+                    st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
+                else if (I.cmds_out != nullptr)
+                    I.cmds_out[(size_t)(q - I.q_begin) * I.n_act + r] = an;
+            }
         }
+        drain();
+        if (lane == 0) st_agent64(I.acc_done + t, q * nkb + (uint64_t)kb + 1);
+        if (last_block) {
+            uint64_t old = 0;
+            if (lane == 0) old = add_agent64(I.tiles_done + (q & 1), 1);
+            old = __shfl(old, 0, kWave);
+            if (old + 1 == par_target(q, (uint64_t)I.n_tiles) && I.serving && lane == 0) {
+                FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
+                __hip_atomic_store(&tel->ticks_publish, wall_clock64(), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(I.cmd_seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+            ++q;
+            kb = 0;
+        } else {
+            ++kb;
+        }
+        if (!join(I, q, kb, t, lane)) return;
     }
-    drain();
-    if (lane == 0) st_agent64(I.acc_done + t, q * nkb + (uint64_t)kb + 1);
-    if (!last_block) return true;
-    uint64_t old = 0;
-    if (lane == 0) old = add_agent64(I.tiles_done + (q & 1), 1);
-    old = __shfl(old, 0, kWave);
-    if (old + 1 == par_target(q, (uint64_t)I.n_tiles) && I.serving && lane == 0) {
-        FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
-        __hip_atomic_store(&tel->ticks_publish, wall_clock64(), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(I.cmd_seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    return true;
 }
 
 // POLC term of frame q + 1: p = M a_q, partials per POLC segment, reduced by
@@ -393,6 +418,8 @@ __device__ bool polc_tasks(const PersistInst &I, const PersistArgs &A, uint64_t 
         pt = __shfl(pt, 0, kWave);
         if (I.serving && lane == 0 && pt + 1 == (q + 1) * (uint64_t)I.n_tiles)
             __hip_atomic_store(I.pol_seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // (P) party of frame q + 1's last block on this tile
+        if (join(I, q + 1, I.n_kb - 1, t, lane)) run_chain(I, q + 1, I.n_kb - 1, t, lane);
     }
     return true;
 }
@@ -489,8 +516,9 @@ __device__ void worker(const PersistInst &I, const PersistArgs &A, int rank, int
                         old = add_agent64(
                             I.kbt_cnt + ((size_t)(q & 1) * I.n_kb + S.kb) * I.n_tiles + t, 1);
                     old = __shfl(old, 0, kWave);
-                    if (old + 1 == par_target(q, (uint64_t)W.nseg))
-                        if (!accumulate_block(I, A, q, S.kb, t, lane)) return;
+                    // (E) party: the block's last partial on this tile
+                    if (old + 1 == par_target(q, (uint64_t)W.nseg) && join(I, q, S.kb, t, lane))
+                        run_chain(I, q, S.kb, t, lane);
                 }
                 lds_done();
                 if (lane == 0) add_agent64(I.mvm_done + (q & 1) * I.n_kb + S.kb, n_done);

@@ -105,6 +105,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.cmd_seq = P.cmd_seq;
     d.pol_seq = P.pol_seq;
     d.pol_tiles = P.pol_tiles;
+    d.join = P.join;
     d.tel = P.tel;
     d.n_slopes = I->n_slopes;
     d.n_units = I->n_units;
@@ -248,7 +249,7 @@ rtc_status persist_alloc(rtc_engine *e) {
         // counters, arrival counters twice (frame parity): cen_done, mvm_done
         // [2][nkb]; kbt_cnt [2][nkb][nt]; pol_cnt [2][nt]; tiles_done [2];
         // sequence values once: acc_done, p_done [nt]; pol_tiles [1]
-        P.n_ctr = 4 * nkb + 2 * nkb * nt + 2 * nt + 2 * nt + 2 + 1;
+        P.n_ctr = 4 * nkb + 2 * nkb * nt + 2 * nt + 2 * nt + 2 + 1 + 2 * nkb * nt;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_done = P.ctr;
         P.mvm_done = P.cen_done + 2 * nkb;
@@ -258,6 +259,7 @@ rtc_status persist_alloc(rtc_engine *e) {
         P.p_done = P.acc_done + nt;
         P.tiles_done = P.p_done + nt;
         P.pol_tiles = P.tiles_done + 2;
+        P.join = P.pol_tiles + 1;
         TRY(dev_alloc(e, &P.db_mirror, I->wfs.size()));
         TRY(dev_alloc(e, &P.drop_mirror, e->ring_depth));
         TRY(dev_alloc(e, &P.param_mirror, 1));
@@ -368,10 +370,19 @@ void persist_free(rtc_engine *e) {
     if (pe.stream) (void)hipStreamDestroy(pe.stream);
 }
 
-// Zero every frame-loop counter and sequence (the loop must be stopped).
+// Zero every frame-loop counter and sequence (the loop must be stopped), and
+// pre-count the joins frame 0 inherits: the accumulation before block 0 and,
+// with POLC, the POLC term of the last block.
 void persist_reset(Instance *I) {
     PersistInstState &P = I->ps;
     (void)hipMemset(P.ctr, 0, P.n_ctr * sizeof(uint64_t));
+    const size_t nkb = I->kb.size(), nt = (size_t)I->n_tiles;
+    std::vector<uint64_t> j0(nkb * nt, 0);
+    for (size_t t = 0; t < nt; ++t) {
+        j0[t] += 1;
+        if (I->d.polc) j0[(nkb - 1) * nt + t] += 1;
+    }
+    (void)hipMemcpy(P.join, j0.data(), j0.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     (void)hipMemset(P.db_mirror, 0, I->wfs.size() * sizeof(uint64_t));
     (void)hipMemset(P.drop_mirror, 0, P.slot_frame.size() * sizeof(uint64_t));
     for (size_t w = 0; w < I->wfs.size(); ++w) *vol(P.doorbell + w) = 0;
