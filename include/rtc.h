@@ -204,6 +204,33 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
  * stream).  Changes no command state. */
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
 
+/* Frame-loop timeline (RTC_MODE_PERSISTENT diagnostics).  With n_frames > 0,
+ * every wavefront of every later frame-loop launch records RTC_TRACE_EVENTS
+ * device-clock values (wall clock, 100 MHz) for each of the first n_frames
+ * frames of that launch, overwriting the previous launch's record; 0 turns the
+ * record off (its cost is then one test per frame).  Synchronises the engine;
+ * the loop must not be running (RTC_E_STATE otherwise). */
+#define RTC_TRACE_EVENTS 8
+enum {
+    RTC_TRACE_FRAME_START = 0,   /* the wavefront reached the frame */
+    RTC_TRACE_GATE = 1,          /* frame q - 2 published: the frame may start */
+    RTC_TRACE_CENTROIDS = 2,     /* its centroid tasks of the frame done */
+    RTC_TRACE_MVM_FIRST = 3,     /* its first MVM task starts (slopes ready) */
+    RTC_TRACE_MVM_LAST = 4,      /* its last MVM task (and accumulation) done */
+    RTC_TRACE_CHAIN_TICKS = 5,   /* ticks it spent accumulating blocks (a count) */
+    RTC_TRACE_CHAIN_BLOCKS = 6,  /* blocks it accumulated (a count) */
+    RTC_TRACE_FRAME_END = 7      /* POLC tasks done, leaving the frame */
+};
+rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames);
+/* Copies the record of the last launch into out (host): value
+ * [(frame * n_waves + wave) * RTC_TRACE_EVENTS + event], frame relative to
+ * the launch's first, wave = global wavefront index (a serving instance's
+ * sentinel included, left zero).  Zero marks an event that did not happen.
+ * capacity counts uint64 values; n_waves and n_frames (nullable) receive the
+ * record's shape.  Synchronises the engine stream. */
+rtc_status rtc_trace_read(rtc_engine *e, uint64_t *out, int64_t capacity, int32_t *n_waves,
+                          int32_t *n_frames);
+
 #ifdef __cplusplus
 }
 #endif

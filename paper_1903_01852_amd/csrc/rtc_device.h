@@ -9,6 +9,57 @@
 
 namespace rtc {
 
+// Global-memory view of a pointer.  Pointers that reach a kernel through a
+// table in device memory (rather than as kernel arguments) are generic to the
+// compiler, which then emits flat instructions; flat loads count against the
+// LDS counter too, so every wait for an LDS read would also drain the matrix
+// stream.  Device and pinned host buffers are all global memory.
+#define RTC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ RTC_GLOBAL T *gbl(T *p) {
+    return (RTC_GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ const RTC_GLOBAL T *gbl(const T *p) {
+    return (const RTC_GLOBAL T *)p;
+}
+
+// Read-only data (tables, descriptors written before the launch) in the
+// constant address space: uniform loads become scalar loads, and the compiler
+// may keep them across stores and atomics, which cannot alias them.
+#define RTC_CONST __attribute__((address_space(4)))
+
+// LDS, named explicitly where a pointer travels through calls the compiler
+// may not inline (it would otherwise fall back to flat instructions).
+#define RTC_LDS __attribute__((address_space(3)))
+typedef float lds4_t __attribute__((ext_vector_type(4)));
+
+// One entry of a read-only table, copied out a dword at a time (a struct
+// cannot be copy-constructed from another address space).
+template <class T>
+__device__ __forceinline__ T ldc(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "table entries are dword multiples");
+    const RTC_CONST uint32_t *w = (const RTC_CONST uint32_t *)p;
+    uint32_t t[sizeof(T) / 4];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) t[i] = w[i];
+    T r;
+    __builtin_memcpy(&r, t, sizeof(T));
+    return r;
+}
+// The same for an entry each lane picks for itself (global address space).
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "table entries are dword multiples");
+    const RTC_GLOBAL uint32_t *w = (const RTC_GLOBAL uint32_t *)p;
+    uint32_t t[sizeof(T) / 4];
+#pragma unroll
+    for (size_t i = 0; i < sizeof(T) / 4; ++i) t[i] = w[i];
+    T r;
+    __builtin_memcpy(&r, t, sizeof(T));
+    return r;
+}
+
 // Binary32 calibration, one rounding per operation: contraction into a fused
 // multiply-add would change the thresholded-pixel masks.
 __device__ __forceinline__ float calibrate_px(float raw, float dark, float flat, float bg) {
@@ -56,9 +107,9 @@ enum { STORE_PLAIN = 0, STORE_AGENT = 1 };
 template <int SP>
 __device__ __forceinline__ void put(float *p, float v) {
     if constexpr (SP == STORE_AGENT)
-        __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
-        *p = v;
+        *gbl(p) = v;
 }
 
 // Load policies for pixels: LOAD_PLAIN for frames in device memory written
@@ -73,10 +124,10 @@ __device__ __forceinline__ uint32_t load_px(const uint16_t *p) {
     if constexpr (LP == LOAD_SYSTEM) {
         const uintptr_t a = reinterpret_cast<uintptr_t>(p);
         const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
-        const uint32_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t v = __hip_atomic_load(gbl(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return (a & 2) ? (v >> 16) : (v & 0xFFFFu);
     } else {
-        return *p;
+        return *gbl(p);
     }
 }
 
@@ -113,9 +164,9 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
             const int r = i / p;
             const int c = i - r * p;
             raw[j] = load_px<LP>(fr + (size_t)(d.row0 + r) * P.W + (d.col0 + c));
-            dk[j] = dark[d.cal + i];
-            fl[j] = flat[d.cal + i];
-            bgv[j] = bg[d.cal + i];
+            dk[j] = gbl(dark)[d.cal + i];
+            fl[j] = gbl(flat)[d.cal + i];
+            bgv[j] = gbl(bg)[d.cal + i];
         }
     }
     float sw = 0.0f, sx = 0.0f, sy = 0.0f;
@@ -137,7 +188,7 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
         }
         const uint64_t bal = __ballot(m);
         cnt += __popcll(bal);
-        if (o.masks != nullptr && lane == 0 && j * kWave < npx) o.masks[d.mask + j] = bal;
+        if (o.masks != nullptr && lane == 0 && j * kWave < npx) gbl(o.masks)[d.mask + j] = bal;
     }
     sw = wave_sum(sw);
     sx = wave_sum(sx);
@@ -145,16 +196,16 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
     if (lane == 0) {
         float ox = 0.0f, oy = 0.0f;
         if (sw > 0.0f) {
-            ox = sx / sw - ref[2 * d.unit];
-            oy = sy / sw - ref[2 * d.unit + 1];
+            ox = sx / sw - gbl(ref)[2 * d.unit];
+            oy = sy / sw - gbl(ref)[2 * d.unit + 1];
         }
         put<SP>(o.s_pad + d.pad, ox);
         put<SP>(o.s_pad + d.pad + 1, oy);
         if (o.s_out != nullptr) {
-            o.s_out[2 * d.unit] = ox;
-            o.s_out[2 * d.unit + 1] = oy;
+            gbl(o.s_out)[2 * d.unit] = ox;
+            gbl(o.s_out)[2 * d.unit + 1] = oy;
         }
-        if (o.counts != nullptr) o.counts[d.unit] = cnt;
+        if (o.counts != nullptr) gbl(o.counts)[d.unit] = cnt;
     }
 }
 
@@ -175,8 +226,8 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
     uint64_t bits = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float cv = calibrate_px((float)raw[q], dark4[q * n_pyr + k], flat4[q * n_pyr + k],
-                                      bg4[q * n_pyr + k]);
+        const float cv = calibrate_px((float)raw[q], gbl(dark4)[q * n_pyr + k],
+                                      gbl(flat4)[q * n_pyr + k], gbl(bg4)[q * n_pyr + k]);
         bool m;
         I[q] = threshold_px(cv, T, P.thr_mode, m);
         bits |= (uint64_t)m << q;
@@ -184,17 +235,17 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
     const float S = (I[0] + I[1]) + (I[2] + I[3]);
     float sx = 0.0f, sy = 0.0f;
     if (S > 0.0f) {
-        sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - ref[2 * d.unit];
-        sy = ((I[0] + I[2]) - (I[1] + I[3])) / S - ref[2 * d.unit + 1];
+        sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - gbl(ref)[2 * d.unit];
+        sy = ((I[0] + I[2]) - (I[1] + I[3])) / S - gbl(ref)[2 * d.unit + 1];
     }
     put<SP>(o.s_pad + d.pad, sx);
     put<SP>(o.s_pad + d.pad + 1, sy);
     if (o.s_out != nullptr) {
-        o.s_out[2 * d.unit] = sx;
-        o.s_out[2 * d.unit + 1] = sy;
+        gbl(o.s_out)[2 * d.unit] = sx;
+        gbl(o.s_out)[2 * d.unit + 1] = sy;
     }
-    if (o.counts != nullptr) o.counts[d.unit] = __popcll(bits);
-    if (o.masks != nullptr) o.masks[d.mask] = bits;
+    if (o.counts != nullptr) gbl(o.counts)[d.unit] = __popcll(bits);
+    if (o.masks != nullptr) gbl(o.masks)[d.mask] = bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -207,22 +258,25 @@ template <> struct Elem<RTC_CM_F32> { static constexpr int E = 4; };
 template <> struct Elem<RTC_CM_BF16> { static constexpr int E = 8; };
 template <> struct Elem<RTC_CM_FP8> { static constexpr int E = 16; };
 
+// One 16-byte matrix vector as a native vector (copyable from any address space).
+typedef uint32_t vec16_t __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// Accumulates the E products of one 16-byte vector.
-template <int DT>
-__device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ xs, int v,
-                                      float &a0, float &a1) {
+// Accumulates the E products of one 16-byte vector; xs points at the slope
+// values as float4 (global memory) or lds4_t (LDS).
+template <int DT, class XS>
+__device__ __forceinline__ void dot16(const vec16_t q, XS xs, int v, float &a0, float &a1) {
     if constexpr (DT == RTC_CM_F32) {
-        const float4 s = xs[v];
+        const auto s = xs[v];
         a0 = fmaf(__uint_as_float(q.x), s.x, a0);
         a1 = fmaf(__uint_as_float(q.y), s.y, a1);
         a0 = fmaf(__uint_as_float(q.z), s.z, a0);
         a1 = fmaf(__uint_as_float(q.w), s.w, a1);
     } else if constexpr (DT == RTC_CM_BF16) {
-        const float4 s0 = xs[2 * v];
-        const float4 s1 = xs[2 * v + 1];
+        const auto s0 = xs[2 * v];
+        const auto s1 = xs[2 * v + 1];
         a0 = fmaf(bf16_lo(q.x), s0.x, a0);
         a1 = fmaf(bf16_hi(q.x), s0.y, a1);
         a0 = fmaf(bf16_lo(q.y), s0.z, a0);
@@ -235,7 +289,7 @@ __device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ 
         const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
-            const float4 s = xs[4 * v + h];
+            const auto s = xs[4 * v + h];
             const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], false);
             const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[h], true);
             a0 = fmaf(lo[0], s.x, a0);
@@ -250,20 +304,21 @@ __device__ __forceinline__ void dot16(const uint4 q, const float4 *__restrict__ 
 // loads in flight) per batch; the slope values of a batch are contiguous, so
 // they arrive in a few wide scalar loads issued beside the vector loads.  The
 // last, partial batch guards each load instead.
-template <int DT, int U>
-__device__ __forceinline__ float stream_segment(const uint4 *__restrict__ p, int nr,
-                                                const float4 *__restrict__ xs, int nv) {
+template <int DT, int U, class XS>
+__device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, int nr, XS xs,
+                                                int nv) {
+    const RTC_GLOBAL vec16_t *__restrict__ p = (const RTC_GLOBAL vec16_t *)pg;
     float a0 = 0.0f, a1 = 0.0f;
     int v = 0;
     for (; v + U <= nv; v += U) {
-        uint4 q[U];
+        vec16_t q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) q[u] = p[(v + u) * nr];
 #pragma unroll
         for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, v + u, a0, a1);
     }
     if (v < nv) {
-        uint4 q[U];
+        vec16_t q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (v + u < nv) q[u] = p[(v + u) * nr];
@@ -277,7 +332,7 @@ __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ p, int
 // The partials were written by wavefronts on any XCD; agent-scope atomic loads
 // read them past this XCD's (non-coherent) L2.
 __device__ __forceinline__ float load_agent(const float *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gbl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sum of partials [s0, s0 + n) of row r, in increasing order.

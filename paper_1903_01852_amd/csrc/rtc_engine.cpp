@@ -883,6 +883,31 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     return last_error(e);
 }
 
+rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames) {
+    if (e == nullptr) return RTC_E_INVAL;
+    if (e->mode != RTC_MODE_PERSISTENT || e->pe.running) return RTC_E_STATE;
+    if (n_frames < 0 || n_frames > kMaxTraceFrames) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipDeviceSynchronize());     // no batch launch may still write the record
+    return persist_trace(e, n_frames);
+}
+
+rtc_status rtc_trace_read(rtc_engine *e, uint64_t *out, int64_t capacity, int32_t *n_waves,
+                          int32_t *n_frames) {
+    if (e == nullptr) return RTC_E_INVAL;
+    if (e->mode != RTC_MODE_PERSISTENT) return RTC_E_STATE;
+    const int waves = e->pe.trace_waves;
+    const int64_t n = (int64_t)e->pe.trace_frames * waves * RTC_TRACE_EVENTS;
+    if (n_waves) *n_waves = waves;
+    if (n_frames) *n_frames = e->pe.trace_frames;
+    if (out == nullptr || n == 0) return RTC_OK;
+    if (capacity < n) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(out, e->pe.trace, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return RTC_OK;
+}
+
 rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
                            uint64_t *masks) {
     Instance *I;

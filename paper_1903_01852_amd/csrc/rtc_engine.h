@@ -56,12 +56,16 @@ struct FrameSlot {
 // Persistent frame loop: per-instance buffers and bookkeeping.
 struct PersistInstState {
     // device
-    float *spad2 = nullptr, *ypart2 = nullptr, *ppart2 = nullptr, *yacc = nullptr;
+    // copies 1 .. kDepth - 1 of the slope and partial buffers (copy 0 is the
+    // per-launch path's)
+    float *spad_x[rtc::kDepth - 1] = {}, *ypart_x[rtc::kDepth - 1] = {},
+          *ppart_x[rtc::kDepth - 1] = {};
+    float *yacc = nullptr;
     uint64_t *ctr = nullptr;       // every frame-loop counter, zeroed on reset
     size_t n_ctr = 0;
-    uint64_t *cen_done = nullptr, *mvm_done = nullptr, *kbt_cnt = nullptr, *acc_done = nullptr;
-    uint64_t *tiles_done = nullptr, *pol_cnt = nullptr, *p_done = nullptr, *pol_tiles = nullptr;
-    uint64_t *join = nullptr;
+    uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
+    uint64_t *kbt_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
+    int n_cen_all = 0;             // centroid tasks of a frame
     uint64_t *db_mirror = nullptr, *drop_mirror = nullptr;
     ParamBlock *param_mirror = nullptr;
     KbWork *kbw = nullptr;
@@ -149,7 +153,8 @@ struct PersistEngine {
     hipStream_t stream = nullptr;  // the frame loop's own stream
     bool running = false;
     bool serving = false;
-    int n_blocks = 0;
+    int n_blocks = 0;              // grid of the serving loop (room left on each CU)
+    int n_blocks_batch = 0;        // grid of a batch launch (full occupancy)
     uint32_t *stop_host = nullptr; // pinned
     uint32_t *status = nullptr;    // pinned
     uint32_t *stop_dev = nullptr;  // device
@@ -158,6 +163,9 @@ struct PersistEngine {
     PersistInst *h_batch[2] = {nullptr, nullptr};   // pinned staging of those
     hipEvent_t batch_copied[2] = {nullptr, nullptr};
     int batch_slot = 0;
+    uint64_t *trace = nullptr;     // device timeline record (rtc_trace_enable)
+    int trace_frames = 0;
+    int trace_waves = 0;           // grid of the launch the record holds
 };
 
 struct rtc_engine {
@@ -243,4 +251,7 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
                          float *slopes, int32_t *counts, hipStream_t st);
 rtc_status persist_params(rtc_engine *e, Instance *I);
 rtc_status persist_quiesce(rtc_engine *e);
+// Timeline record of the frame loop: frames per launch (0 = off).
+constexpr int kMaxTraceFrames = 4096;
+rtc_status persist_trace(rtc_engine *e, int n_frames);
 void persist_free(rtc_engine *e);

@@ -140,6 +140,10 @@ struct FrameTel {
     uint64_t ticks_publish;        // device clock when its commands were published
 };
 
+// Frames of one frame-loop instance in flight at once: slopes, partials and
+// arrival counters exist kDepth times, frame q using copy q % kDepth.
+constexpr int kDepth = 3;
+
 struct PersistInst {
     // tables
     const ShUnit *sh;
@@ -151,6 +155,7 @@ struct PersistInst {
     const int2 *kb_segs;
     const Step *steps;
     int32_t n_kb, n_seg, n_steps, n_wfs;
+    int32_t n_cen_all, r5;         // centroid tasks of a frame (every block)
     const WfsParam *wp;
     // calibration
     const float *sh_dark, *sh_flat, *sh_bg, *sh_thr;
@@ -167,15 +172,20 @@ struct PersistInst {
     const int2 *kbm_segs;
     int32_t n_kbm, n_segm;
     // state and scratch
-    float *s_pad[2];
-    float *y_part[2];
-    float *p_part[2];
+    float *s_pad[kDepth];          // frame q uses buffer q % kDepth
+    float *y_part[kDepth];
+    float *p_part[kDepth];
     float *y_acc, *p;
     float *a;                      // two command buffers of a_stride floats (frame parity)
     int32_t a_stride, r4;
-    uint64_t *cen_done, *mvm_done, *kbt_cnt, *acc_done, *tiles_done, *pol_cnt, *p_done;
-    uint64_t *pol_tiles;           // tiles whose POLC term is complete (all frames)
-    uint64_t *join;                // [2][n_kb][n_tiles] block-accumulation joins
+    // counters, one kCtrSlot-sized slot each; [kDepth]: by q % kDepth
+    uint64_t *cen_fan;             // [kDepth][n_kb] fan-in: centroid tasks of a block
+    uint64_t *tile_fan;            // [kDepth] fan-in: tiles whose commands are out
+    uint64_t *pol_fan;             // [kDepth] fan-in: tiles whose POLC term is formed
+    uint64_t *kbt_cnt;             // [kDepth][n_kb][n_tiles] partials of a block on a tile
+    uint64_t *join;                // [kDepth][n_kb][n_tiles] accumulation joins
+    uint64_t *pol_cnt;             // [kDepth][n_tiles] POLC partials of a tile
+    uint64_t *p_done;              // [n_tiles] q + 1 of the last POLC term reduced
     uint64_t *db_mirror;           // device copy of the doorbells, per sensor
     uint64_t *drop_mirror;         // per mailbox slot: q + 1 of a dropped frame
     // frame source
@@ -212,14 +222,27 @@ struct PersistArgs {
     uint32_t *status;                      // pinned: nonzero after a watchdog expiry
     uint64_t dep_watchdog;                 // device-clock ticks a dependency wait may take
     uint64_t idle_watchdog;                // device-clock ticks a doorbell wait may take
+    uint64_t *trace;                       // timeline record or null
+    int32_t trace_frames;                  // frames recorded per launch
+    int32_t n_waves;                       // wavefronts in the grid
 };
 
 enum { PERSIST_OK = 0, PERSIST_WATCHDOG = 1 };
 constexpr uint64_t kDbChunkMask = (1ull << 20) - 1;
 constexpr int kDbShift = 20;
 constexpr int kMaxSegVectors = kPieceVectors;   // longest segment (slopes staged in LDS)
+// Frame-loop counters sit 256 bytes apart: agent-scope atomics on one cache
+// line serialise (~12 ns each), on distinct lines they proceed in parallel.
+constexpr int kCtrSlot = 32;                      // uint64 per counter slot
+// A fan-in barrier of n tasks: task j counts on stripe j % kFanStripes, the
+// arrival completing a stripe's quota counts on the top slot, and waiters
+// poll only the top slot.
+constexpr int kFanStripes = 32;
+constexpr int kFanSlots = kFanStripes + 1;        // stripes, then the top
 
 void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args);
+void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_kb,
+                          int n_tiles, int par, int polc, int serving);
 int frame_loop_max_blocks_per_cu();
 
 // Launchers (defined in rtc_kernels.hip).

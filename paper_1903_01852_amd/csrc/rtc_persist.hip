@@ -10,14 +10,16 @@
 // which the host guarantees by sizing the grid from the occupancy query.
 //
 // Frames are numbered by a sequence q.  Counters are monotonic 64-bit values,
-// never reset.  A worker may reach frame q + 1 while frame q is still in
-// flight (slopes, partials and commands are double-buffered by frame parity),
-// so every arrival counter exists twice, indexed by q & 1; frame q + 2 cannot
-// start a block before frame q has finished it, so the frames sharing a
-// counter never overlap, and the target for frame q is (q / 2 + 1) x (work
-// per frame).  Everything one wavefront hands to another goes through
-// agent-scope atomics (written through past the XCD's non-coherent L2), with
-// the writer draining its stores before it counts them.
+// reset by each launch.  Up to kDepth frames are in flight (slopes, partials
+// and arrival counters exist kDepth times, frame q using copy q % kDepth); a
+// worker starts frame q only once frame q - kDepth has published every tile
+// (the frame gate), so the frames sharing a counter or a buffer never
+// overlap, and the target for frame q is ((q - first) / kDepth + 1) x (work
+// per frame).  Everything one wavefront hands
+// to another goes through agent-scope atomics (written through past the XCD's
+// non-coherent L2), with the writer draining its stores before it counts
+// them.  Counters live 256 bytes apart, and counts with many contributors go
+// through striped fan-in barriers, since same-line atomics serialise.
 //
 // Serving instances read pixels straight from the pinned host ring; a
 // sentinel wavefront per instance mirrors the host doorbells into device
@@ -27,29 +29,43 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rtc_device.h"
 
 namespace rtc {
 
 namespace {
 
+// The instance descriptor is written before the launch and never changes
+// while the loop runs, so it is read as constant memory: scalar loads that hit
+// the scalar cache.  It is also volatile: the compiler then reloads a field
+// where it is used instead of keeping every field it ever needs live in
+// registers across the whole loop (which spills), and a reload after a store
+// or an atomic stays a cheap scalar load rather than a trip to memory.  The
+// kernel arguments are constant memory too.
+using InstRef = volatile const RTC_CONST PersistInst &;
+using ArgsRef = const RTC_CONST PersistArgs &;
+
+// Every buffer the loop touches is global memory (device or pinned host), so
+// each access goes through gbl(): see rtc_device.h.
 __device__ __forceinline__ uint64_t ld_agent64(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gbl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent64(uint64_t *p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t add_agent64(uint64_t *p, uint64_t v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint64_t ld_sys64(const uint64_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return __hip_atomic_load(gbl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void st_agent(float *p, float v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_sys(float *p, float v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 // Wait until every store this wavefront issued has completed.
 __device__ __forceinline__ void drain() {
@@ -57,18 +73,18 @@ __device__ __forceinline__ void drain() {
     __builtin_amdgcn_s_waitcnt(0);
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
-__device__ __forceinline__ bool stopping(const PersistArgs &A) {
-    return __hip_atomic_load(A.stop_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+__device__ __forceinline__ bool stopping(ArgsRef A) {
+    return __hip_atomic_load(gbl(A.stop_dev), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
-__device__ void watchdog_expired(const PersistArgs &A) {
-    __hip_atomic_store(A.status, (uint32_t)PERSIST_WATCHDOG, __ATOMIC_RELAXED,
+__device__ void watchdog_expired(ArgsRef A) {
+    __hip_atomic_store(gbl(A.status), (uint32_t)PERSIST_WATCHDOG, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(A.stop_dev, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gbl(A.stop_dev), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Spin until *ctr >= target.  False when the loop must exit (stop request or
 // watchdog expiry); the stop flag and the clock are checked every 32 polls.
-__device__ bool wait_geq(const uint64_t *ctr, uint64_t target, const PersistArgs &A,
+__device__ bool wait_geq(const uint64_t *ctr, uint64_t target, ArgsRef A,
                          uint64_t limit) {
     if (ld_agent64(ctr) >= target) return true;
     const uint64_t t0 = wall_clock64();
@@ -85,9 +101,6 @@ __device__ bool wait_geq(const uint64_t *ctr, uint64_t target, const PersistArgs
     }
 }
 
-__device__ __forceinline__ uint64_t db_pack(uint64_t q, uint64_t chunks) {
-    return (q << kDbShift) | chunks;
-}
 __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chunks) {
     const uint64_t dq = db >> kDbShift;
     return dq > q || (dq == q && (db & kDbChunkMask) >= chunks);
@@ -95,7 +108,7 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
 
 // Wait for chunk `chunk` of frame q of sensor w (serving instances).  Only a
 // stop request ends this wait: the sentinel turns a long idle period into one.
-__device__ bool wait_chunk(const PersistInst &I, const PersistArgs &A, int w, uint64_t q,
+__device__ bool wait_chunk(InstRef I, ArgsRef A, int w, uint64_t q,
                            int chunk) {
     const uint64_t *m = I.db_mirror + w;
     if (db_reached(ld_agent64(m), q, chunk + 1)) return true;
@@ -108,16 +121,16 @@ __device__ bool wait_chunk(const PersistInst &I, const PersistArgs &A, int w, ui
 
 // Stage n floats written by other wavefronts of this kernel into this
 // wavefront's LDS slice (two floats per agent-scope atomic load).
-__device__ __forceinline__ void stage_lds(float *lds, const float *src, int n, int lane) {
+__device__ __forceinline__ void stage_lds(RTC_LDS float *lds, const float *src, int n, int lane) {
     const uint64_t *s2 = reinterpret_cast<const uint64_t *>(src);
-    uint64_t *d2 = reinterpret_cast<uint64_t *>(lds);
+    RTC_LDS uint64_t *d2 = (RTC_LDS uint64_t *)lds;
     const int n2 = (n + 1) >> 1;
     constexpr int kPer = (kMaxSegVectors * 16 / 2 + kWave - 1) / kWave;   // worst case (FP8)
     uint64_t v[kPer];
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
         const int i = j * kWave + lane;
-        v[j] = i < n2 ? __hip_atomic_load(s2 + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        v[j] = i < n2 ? __hip_atomic_load(gbl(s2 + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     }
 #pragma unroll
     for (int j = 0; j < kPer; ++j) {
@@ -135,9 +148,64 @@ __device__ __forceinline__ void lds_done() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Arrivals counted on a parity counter after frame q (frames q, q - 2, ...).
-__device__ __forceinline__ uint64_t par_target(uint64_t q, uint64_t per_frame) {
-    return (q / 2 + 1) * per_frame;
+// Timeline record (rtc_trace_enable): this wavefront's events of one frame.
+struct Trace {
+    uint64_t *rec = nullptr;        // null when not recorded
+    uint64_t chain_ticks = 0;
+    uint64_t chain_blocks = 0;
+    __device__ void stamp(int ev, int lane) const {
+        if (rec != nullptr && lane == 0) gbl(rec)[ev] = wall_clock64();
+    }
+    __device__ void put(int ev, uint64_t v, int lane) const {
+        if (rec != nullptr && lane == 0) gbl(rec)[ev] = v;
+    }
+};
+
+// Arrivals counted on a parity counter after frame q: the launch resets the
+// counters, so frames q, q - 2, ... down to the launch's first frame.
+__device__ __forceinline__ uint64_t par_target(InstRef I, uint64_t q, uint64_t per_frame) {
+    return ((q - I.q_begin) / kDepth + 1) * per_frame;
+}
+// Copy of the slope/partial buffers and arrival counters frame q uses.
+__device__ __forceinline__ int dslot(uint64_t q) {
+    return (int)(q % kDepth);
+}
+
+// Counter i of an array of counter slots.
+__device__ __forceinline__ uint64_t *slot(uint64_t *base, size_t i) {
+    return base + i * kCtrSlot;
+}
+
+// Fan-in barrier `key` (of n_keys) used by frame q: kFanStripes stripe slots,
+// then the top slot.
+__device__ __forceinline__ uint64_t *fan_grp(uint64_t *base, uint64_t q, int n_keys, int key) {
+    return slot(base, ((size_t)dslot(q) * n_keys + key) * kFanSlots);
+}
+__device__ __forceinline__ uint64_t *fan_top(uint64_t *grp) {
+    return slot(grp, kFanStripes);
+}
+// Top count once frame q has passed a barrier of n tasks.
+__device__ __forceinline__ uint64_t fan_target(InstRef I, uint64_t q, int n) {
+    return par_target(I, q, (uint64_t)min(n, kFanStripes));
+}
+// Count this wavefront's tasks of frame q on a barrier of n tasks: lane
+// s < kFanStripes holds in cnt how many of its tasks j have j % kFanStripes
+// == s (a stripe's quota is the number of such j below n).  The wavefront's
+// stores must be drained.  True, on every lane, for the arrival that
+// completes the barrier.
+__device__ bool fan_arrive(InstRef I, uint64_t *grp, uint64_t q, int n, uint32_t cnt, int lane) {
+    bool done = false;
+    if (cnt != 0) {
+        const uint64_t quota = (uint64_t)((n - lane + kFanStripes - 1) / kFanStripes);
+        const uint64_t old = add_agent64(slot(grp, lane), cnt);
+        if (old + cnt == par_target(I, q, quota))
+            done = add_agent64(fan_top(grp), 1) + 1 == fan_target(I, q, n);
+    }
+    return __any(done);
+}
+// The lane holding task j's stripe count.
+__device__ __forceinline__ bool stripe_lane(int j, int lane) {
+    return lane == (int)((unsigned)j % kFanStripes);
 }
 
 // First task index of this worker among n tasks whose task 0 goes to `base`.
@@ -145,15 +213,21 @@ __device__ __forceinline__ int first_task(int rank, int nw, int base) {
     int j = (rank - base) % nw;
     return j < 0 ? j + nw : j;
 }
+// Round-robin start of frame q's tasks of one kind (n_all per frame): frame q
+// continues where frame q - 1 ended, so the workers holding one task more than
+// the others change from frame to frame.
+__device__ __forceinline__ int rot(uint64_t q, int n_all, int nw) {
+    return (int)(((q % (uint64_t)nw) * (uint64_t)n_all) % (uint64_t)nw);
+}
 
-__device__ __forceinline__ const uint16_t *frame_src(const PersistInst &I, int w, uint64_t q) {
+__device__ __forceinline__ const uint16_t *frame_src(InstRef I, int w, uint64_t q) {
     if (I.serving) return I.src[w] + (int64_t)(q % (uint64_t)I.ring_depth) * I.src_stride[w];
     return I.src[w] + (int64_t)(q - I.q_begin) * I.src_stride[w];
 }
 
 // Commands of frame q live in buffer q & 1: frame q reads buffer (q - 1) & 1
 // while the POLC product of frame q - 1 may still be reading it.
-__device__ __forceinline__ float *a_buf(const PersistInst &I, uint64_t q) {
+__device__ __forceinline__ float *a_buf(InstRef I, uint64_t q) {
     return I.a + (q & 1) * (uint64_t)I.a_stride;
 }
 
@@ -168,18 +242,18 @@ template <int DT> struct LoopBatch { static constexpr int U = 8; };
 template <> struct LoopBatch<RTC_CM_FP8> { static constexpr int U = 4; };
 
 template <int DT>
-__device__ __forceinline__ float mvm_partial(const PersistInst &I, const uint8_t *cm,
+__device__ __forceinline__ float mvm_partial(InstRef I, const uint8_t *cm,
                                              const KBlock &K, const Segment &S, int t, int nr,
-                                             int lane, const float *lds) {
+                                             int lane, const RTC_LDS float *lds) {
     if (lane >= nr) return 0.0f;
     const uint4 *p = reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
                      (int64_t)S.v0 * nr + lane;
-    return stream_segment<DT, LoopBatch<DT>::U>(p, nr, reinterpret_cast<const float4 *>(lds), S.nv);
+    return stream_segment<DT, LoopBatch<DT>::U>(p, nr, (const RTC_LDS lds4_t *)lds, S.nv);
 }
 
-__device__ __forceinline__ float seg_partial(const PersistInst &I, const KBlock &K,
+__device__ __forceinline__ float seg_partial(InstRef I, const KBlock &K,
                                              const Segment &S, int t, int nr, int lane,
-                                             const float *lds) {
+                                             const RTC_LDS float *lds) {
     switch (I.dtype) {
     case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(I, I.cm, K, S, t, nr, lane, lds);
     case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(I, I.cm, K, S, t, nr, lane, lds);
@@ -188,7 +262,7 @@ __device__ __forceinline__ float seg_partial(const PersistInst &I, const KBlock 
 }
 
 // Frame coefficients for frame q.
-__device__ __forceinline__ void frame_coef(const PersistInst &I, uint64_t q, float &c1, float &g) {
+__device__ __forceinline__ void frame_coef(InstRef I, uint64_t q, float &c1, float &g) {
     if (I.serving) {
         // device mirror, refreshed by the sentinel before it mirrors any
         // doorbell that follows a host parameter change
@@ -197,8 +271,8 @@ __device__ __forceinline__ void frame_coef(const PersistInst &I, uint64_t q, flo
         const uint64_t qs = word >> 1;
         const int staged = (int)(word & 1);
         const int s = q >= qs ? staged : 1 - staged;
-        c1 = __hip_atomic_load(&pb->c1[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        g = __hip_atomic_load(&pb->g[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c1 = __hip_atomic_load(gbl(&pb->c1[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        g = __hip_atomic_load(gbl(&pb->g[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
         const int s = q >= I.coef.q_switch ? 1 : 0;
         c1 = I.coef.c1[s];
@@ -210,11 +284,13 @@ __device__ __forceinline__ void frame_coef(const PersistInst &I, uint64_t q, flo
 // Sentinel of a serving instance: mirror the host doorbells, parameters and
 // drop marks into device memory, stamp each frame's last chunk, relay a stop
 // request.
-__device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
+__device__ void sentinel(InstRef I, ArgsRef A, int lane) {
     const int nw = I.n_wfs;
     int nch = 0;          // lane w: chunks per frame of sensor w
-    for (int st = 0; st < I.n_steps; ++st)
-        if (I.steps[st].wfs == lane) nch = max(nch, I.steps[st].chunk + 1);
+    for (int st = 0; st < I.n_steps; ++st) {
+        const Step S = ldc(I.steps + st);
+        if (S.wfs == lane) nch = max(nch, S.chunk + 1);
+    }
     uint64_t last = ~0ull;
     uint64_t last_word = ~0ull;
     uint64_t last_drop = ~0ull;
@@ -228,13 +304,13 @@ __device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
         const uint64_t word = ld_sys64(&I.params->word);
         if (word != last_word) {
             if (lane < 2) {
-                const float c1 = __hip_atomic_load(&I.params->c1[lane], __ATOMIC_RELAXED,
+                const float c1 = __hip_atomic_load(gbl(&I.params->c1[lane]), __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_SYSTEM);
-                const float g = __hip_atomic_load(&I.params->g[lane], __ATOMIC_RELAXED,
+                const float g = __hip_atomic_load(gbl(&I.params->g[lane]), __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(&I.param_mirror->c1[lane], c1, __ATOMIC_RELAXED,
+                __hip_atomic_store(gbl(&I.param_mirror->c1[lane]), c1, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(&I.param_mirror->g[lane], g, __ATOMIC_RELAXED,
+                __hip_atomic_store(gbl(&I.param_mirror->g[lane]), g, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             drain();
@@ -261,13 +337,13 @@ __device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
         if (__all(ok)) {
             if (lane == 0) {
                 FrameTel *tel = I.tel + (seen_q % (uint64_t)I.ring_depth);
-                __hip_atomic_store(&tel->ticks_last_chunk, wall_clock64(), __ATOMIC_RELAXED,
+                __hip_atomic_store(gbl(&tel->ticks_last_chunk), wall_clock64(), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_SYSTEM);
             }
             ++seen_q;
         }
         if ((it & 15) == 0) {
-            const uint32_t stop = __hip_atomic_load(A.stop_host, __ATOMIC_RELAXED,
+            const uint32_t stop = __hip_atomic_load(gbl(A.stop_host), __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_SYSTEM);
             // A serving loop idle for longer than the idle limit ends the kernel
             // (the host relaunches it on demand), but only between frames: no
@@ -276,13 +352,17 @@ __device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
             bool quiet = wall_clock64() - t_change > A.idle_watchdog;
             if (quiet) {
                 const bool none = lane >= nw || !db_reached(db, seen_q, 1);
-                const uint64_t pub = ld_agent64(I.tiles_done) + ld_agent64(I.tiles_done + 1);
-                const uint64_t pol = ld_agent64(I.pol_tiles);
-                quiet = __all(none) && pub == seen_q * (uint64_t)I.n_tiles &&
-                        (!I.polc || pol == seen_q * (uint64_t)I.n_tiles);
+                const uint64_t na = (uint64_t)min(I.n_tiles, kFanStripes);
+                uint64_t pub = 0, pol = 0;
+                for (int k = 0; k < kDepth; ++k) {
+                    pub += ld_agent64(fan_top(fan_grp(I.tile_fan, k, 1, 0)));
+                    pol += ld_agent64(fan_top(fan_grp(I.pol_fan, k, 1, 0)));
+                }
+                const uint64_t nf = seen_q - I.q_begin;   // counters start at the launch
+                quiet = __all(none) && pub == nf * na && (!I.polc || pol == nf * na);
             }
             if (stop != 0 || quiet) {
-                __hip_atomic_store(A.stop_dev, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gbl(A.stop_dev), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return;
             }
             // a frame left half delivered for much longer still ends the loop,
@@ -298,257 +378,467 @@ __device__ void sentinel(const PersistInst &I, const PersistArgs &A, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Block accumulation as a join.  Accumulating block kb of frame q on tile t
-// needs (E) every partial of the block on the tile, (A) the previous block
-// accumulated (block n_kb - 1 of frame q - 1 for kb = 0) and, for the last
-// block with POLC, (P) the POLC term of the tile.  Each party adds one to the
-// block's join counter; the party that completes the count does the work, so
-// nobody ever waits, and then joins the next block as its (A) party.  Join
-// counters are doubled by frame parity like the arrival counters; the first
-// frame after a reset finds its (A) and (P) parts pre-counted by the host.
-__device__ __forceinline__ uint64_t join_need(const PersistInst &I, int kb) {
+// Accumulation as joins.  A tile's commands for frame q need (E) its
+// partials, (A) the tile's commands of frame q - 1 (the integrator reads
+// them, and the sums must follow frame order) and, with POLC, (P) its POLC
+// term.  Each party adds one to a join counter; the party that completes the
+// count does the work, so nobody waits, and then arrives as the (A) party of
+// what follows.  Join counters are doubled by frame parity like the arrival
+// counters; the launch pre-counts the (A) and (P) parts of its first frame.
+//
+// Serving accumulates block by block as the chunks arrive: join (q, kb, t)
+// gathers block kb's partials (E) and the accumulation of block kb - 1 (A),
+// and for the last block also P, so that only the last block's sum is left
+// once the last chunk is in.  Batch has every chunk at once: join (q, 0, t)
+// gathers all of the tile's partials (E), the tile's frame q - 1 (A) and P,
+// and one wavefront sums the blocks in readout order in one pass.
+__device__ __forceinline__ uint64_t join_need(InstRef I, int kb) {
+    if (!I.serving) return I.polc ? 3 : 2;
     return (I.polc && kb == I.n_kb - 1) ? 3 : 2;
 }
-__device__ __forceinline__ uint64_t *join_ctr(const PersistInst &I, uint64_t q, int kb, int t) {
-    return I.join + ((size_t)(q & 1) * I.n_kb + kb) * I.n_tiles + t;
+__device__ __forceinline__ uint64_t *join_ctr(InstRef I, uint64_t q, int kb, int t) {
+    return slot(I.join, ((size_t)dslot(q) * I.n_kb + kb) * I.n_tiles + t);
 }
 // True when this wavefront's arrival completes the join of (q, kb, t).
-__device__ __forceinline__ bool join(const PersistInst &I, uint64_t q, int kb, int t, int lane) {
+__device__ __forceinline__ bool join(InstRef I, uint64_t q, int kb, int t, int lane) {
     uint64_t old = 0;
     if (lane == 0) old = add_agent64(join_ctr(I, q, kb, t), 1);
     old = __shfl(old, 0, kWave);
     return (old + 1) % join_need(I, kb) == 0;
 }
 
-// Accumulate block kb of frame q into tile t, then every following block
-// whose join this completes.  Blocks are added in readout order, each block's
-// segments in order: the same arithmetic as the per-launch epilogue.  The
-// last block applies the FP8 row scale, the POLC term and the leaky
-// integrator, and publishes the tile's commands.
-__device__ void run_chain(const PersistInst &I, uint64_t q, int kb, int t, int lane) {
-    const uint64_t nkb = (uint64_t)I.n_kb;
+// Commands of tile t for frame q from the reconstruction sum y of row r: the
+// FP8 row scale, the POLC term and the leaky integrator (a dropped serving
+// frame keeps the previous commands), then publication.
+__device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, float y, int lane) {
+    if (row) {
+        float c1, g;
+        frame_coef(I, q, c1, g);
+        if (I.scale != nullptr) y *= gbl(I.scale)[r];
+        if (I.polc) y += load_agent(I.p + r);
+        const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
+        bool dropped = false;
+        if (I.serving) dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
+        const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
+        st_agent(a_buf(I, q) + r, an);
+        if (I.serving)
+            st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
+        else if (I.cmds_out != nullptr)
+            gbl(I.cmds_out)[(size_t)(q - I.q_begin) * I.n_act + r] = an;
+    }
+    drain();
+    const bool all = fan_arrive(I, fan_grp(I.tile_fan, q, 1, 0), q, I.n_tiles,
+                                stripe_lane(t, lane) ? 1u : 0u, lane);
+    if (all && I.serving && lane == 0) {
+        FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
+        __hip_atomic_store(gbl(&tel->ticks_publish), wall_clock64(), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(gbl(I.cmd_seq), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+// Serving: accumulate block kb of frame q into tile t, then every following
+// block whose join this completes.  Blocks are added in readout order, each
+// block's segments in order: the arithmetic of the per-launch epilogue.
+// Returns the number of blocks accumulated.
+__device__ int run_chain(InstRef I, uint64_t q, int kb, int t, int lane) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
-    for (;;) {
+    for (int done = 1;; ++done) {
         const bool last_block = kb == I.n_kb - 1;
+        float y = 0.0f;
         if (lane < nr) {
-            const int2 sb = I.kb_segs[kb];
-            float y = kb == 0 ? 0.0f : load_agent(I.y_acc + r);
-            y += sum_parts(I.y_part[q & 1], sb.x, sb.y, I.n_act, r);
-            if (!last_block) {
-                st_agent(I.y_acc + r, y);
-            } else {
-                float c1, g;
-                frame_coef(I, q, c1, g);
-                if (I.scale != nullptr) y *= I.scale[r];
-                if (I.polc) y += load_agent(I.p + r);
-                const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
-                bool dropped = false;
-                if (I.serving)
-                    dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
-                const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
-                st_agent(a_buf(I, q) + r, an);
-                if (I.serving)
-                    st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
-                else if (I.cmds_out != nullptr)
-                    I.cmds_out[(size_t)(q - I.q_begin) * I.n_act + r] = an;
-            }
+            const int2 sb = ldc(I.kb_segs + kb);
+            y = kb == 0 ? 0.0f : load_agent(I.y_acc + r);
+            y += sum_parts(I.y_part[dslot(q)], sb.x, sb.y, I.n_act, r);
+            if (!last_block) st_agent(I.y_acc + r, y);
         }
-        drain();
-        if (lane == 0) st_agent64(I.acc_done + t, q * nkb + (uint64_t)kb + 1);
         if (last_block) {
-            uint64_t old = 0;
-            if (lane == 0) old = add_agent64(I.tiles_done + (q & 1), 1);
-            old = __shfl(old, 0, kWave);
-            if (old + 1 == par_target(q, (uint64_t)I.n_tiles) && I.serving && lane == 0) {
-                FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
-                __hip_atomic_store(&tel->ticks_publish, wall_clock64(), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_SYSTEM);
-                __hip_atomic_store(I.cmd_seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            tile_commands(I, q, t, r, lane < nr, y, lane);
             ++q;
             kb = 0;
         } else {
+            drain();
             ++kb;
         }
-        if (!join(I, q, kb, t, lane)) return;
+        if (!join(I, q, kb, t, lane)) return done;
+    }
+}
+
+// Sum of every partial of row r of frame q's buffer, block by block in
+// readout order and each block's segments in order, up to kSumBatch loads in
+// flight.
+constexpr int kSumBatch = 16;
+__device__ float sum_tile(InstRef I, const float *part, int r) {
+    const int n_seg = I.n_seg, n_kb = I.n_kb, n_act = I.n_act;
+    const int2 *kb_segs = I.kb_segs;
+    float y = 0.0f, blk = 0.0f;
+    int kb = 0;
+    int2 sb = ldc(kb_segs);
+    int blk_end = sb.x + sb.y;
+    for (int s0 = 0; s0 < n_seg; s0 += kSumBatch) {
+        float v[kSumBatch];
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u)
+            v[u] = s0 + u < n_seg ? load_agent(part + (size_t)(s0 + u) * n_act + r) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < kSumBatch; ++u) {
+            const int sg = s0 + u;
+            if (sg < n_seg) {
+                blk += v[u];
+                if (sg + 1 == blk_end) {
+                    y = kb == 0 ? blk : y + blk;
+                    blk = 0.0f;
+                    if (++kb < n_kb) {
+                        sb = ldc(kb_segs + kb);
+                        blk_end = sb.x + sb.y;
+                    }
+                }
+            }
+        }
+    }
+    return y;
+}
+
+// Batch: commands of tile t for frame q, then of every following frame whose
+// join this completes.  Returns the number of frames done.
+__device__ int finish_chain(InstRef I, uint64_t q, int t, int lane) {
+    const int nr = min(kTileRows, I.n_act - t * kTileRows);
+    const int r = t * kTileRows + lane;
+    for (int done = 1;; ++done) {
+        const float y = lane < nr ? sum_tile(I, I.y_part[dslot(q)], r) : 0.0f;
+        tile_commands(I, q, t, r, lane < nr, y, lane);
+        ++q;
+        if (q >= I.q_end || !join(I, q, 0, t, lane)) return done;
+    }
+}
+
+// The accumulation a completed join starts, timed into the frame's record.
+__device__ __forceinline__ void accumulate(InstRef I, uint64_t q, int kb, int t, int lane,
+                                           Trace &tr) {
+    const uint64_t t0 = tr.rec != nullptr ? wall_clock64() : 0;
+    const int n = I.serving ? run_chain(I, q, kb, t, lane) : finish_chain(I, q, t, lane);
+    if (tr.rec != nullptr) {
+        tr.chain_ticks += wall_clock64() - t0;
+        tr.chain_blocks += (uint64_t)n;
     }
 }
 
 // POLC term of frame q + 1: p = M a_q, partials per POLC segment, reduced by
 // the wavefront completing a tile.
-__device__ bool polc_tasks(const PersistInst &I, const PersistArgs &A, uint64_t q, int rank,
-                           int nw, int lane, float *lds) {
+__device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
+                           int nw, int lane, RTC_LDS float *lds, Trace &tr) {
     const int n_tasks = I.n_segm * I.n_tiles;
-    int j = first_task(rank, nw, 0);
+    int j = first_task(rank, nw, rot(q, n_tasks, nw));
     if (j >= n_tasks) return true;
-    if (!wait_geq(I.tiles_done + (q & 1), par_target(q, (uint64_t)I.n_tiles), A, A.dep_watchdog))
+    if (!wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q, I.n_tiles), A,
+                  A.dep_watchdog))
         return false;
     const float *aq = a_buf(I, q);
-    float *part = I.p_part[q & 1];
+    float *part = I.p_part[dslot(q)];
     for (; j < n_tasks; j += nw) {
         const int sg = j / I.n_tiles;
         const int t = j - sg * I.n_tiles;
-        const Segment S = I.segm[sg];
-        const KBlock K = I.kbm[S.kb];
+        const Segment S = ldc(I.segm + sg);
+        const KBlock K = ldc(I.kbm + S.kb);
         stage_lds(lds, aq + K.spad + S.v0 * 4, S.nv * 4, lane);
-        if (q >= 2 && !wait_geq(I.p_done + t, q - 1, A, A.dep_watchdog)) return false;
+        // p_part copy of frame q is free once frame q - kDepth's term of the tile
+        // is reduced
+        if (q >= I.q_begin + kDepth &&
+            !wait_geq(slot(I.p_done, t), q - kDepth + 1, A, A.dep_watchdog))
+            return false;
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
         const float v = mvm_partial<RTC_CM_F32>(I, I.M, K, S, t, nr, lane, lds);
         if (lane < nr) st_agent(part + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         lds_done();
         drain();
         uint64_t old = 0;
-        if (lane == 0) old = add_agent64(I.pol_cnt + (q & 1) * I.n_tiles + t, 1);
+        if (lane == 0) old = add_agent64(slot(I.pol_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
         old = __shfl(old, 0, kWave);
-        if (old + 1 != par_target(q, (uint64_t)I.n_segm)) continue;
+        if (old + 1 != par_target(I, q, (uint64_t)I.n_segm)) continue;
         const int r = t * kTileRows + lane;
         if (lane < nr) {
             float y = 0.0f;
             for (int b = 0; b < I.n_kbm; ++b) {
-                const int2 sb = I.kbm_segs[b];
+                const int2 sb = ldc(I.kbm_segs + b);
                 y += sum_parts(part, sb.x, sb.y, I.n_act, r);
             }
             st_agent(I.p + r, y);
         }
         drain();
-        if (lane == 0) st_agent64(I.p_done + t, q + 1);
-        uint64_t pt = 0;
-        if (lane == 0) pt = add_agent64(I.pol_tiles, 1);
-        pt = __shfl(pt, 0, kWave);
-        if (I.serving && lane == 0 && pt + 1 == (q + 1) * (uint64_t)I.n_tiles)
-            __hip_atomic_store(I.pol_seq, q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        // (P) party of frame q + 1's last block on this tile
-        if (join(I, q + 1, I.n_kb - 1, t, lane)) run_chain(I, q + 1, I.n_kb - 1, t, lane);
+        if (lane == 0) st_agent64(slot(I.p_done, t), q + 1);
+        const bool all = fan_arrive(I, fan_grp(I.pol_fan, q, 1, 0), q, I.n_tiles,
+                                    stripe_lane(t, lane) ? 1u : 0u, lane);
+        if (all && I.serving && lane == 0)
+            __hip_atomic_store(gbl(I.pol_seq), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        // (P) party of frame q + 1 on this tile
+        if (q + 1 < I.q_end) {
+            const int kb = I.serving ? I.n_kb - 1 : 0;
+            if (join(I, q + 1, kb, t, lane)) accumulate(I, q + 1, kb, t, lane, tr);
+        }
     }
     return true;
 }
 
-// One worker of one instance.
-__device__ void worker(const PersistInst &I, const PersistArgs &A, int rank, int nw, int lane,
-                       float *lds) {
-    const uint64_t ntl = (uint64_t)I.n_tiles;
-    for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
-        if (stopping(A)) return;
-        float *spad = I.s_pad[q & 1];
-        const int E = vec_elems(I.dtype);
-        const int64_t qo = (int64_t)(q - I.q_begin);
-        const SlopeOut so{spad,
-                          I.slopes_out ? I.slopes_out + qo * I.n_slopes : nullptr,
-                          I.counts_out ? I.counts_out + qo * I.n_units : nullptr, nullptr};
-        for (int st = 0; st < I.n_steps; ++st) {
-            const Step S = I.steps[st];
-            if (S.kb < 0) continue;
-            const KbWork W = I.kbw[S.kb];
-            const uint64_t n_mvm = (uint64_t)W.nseg * ntl;
-            int jc = first_task(rank, nw, W.cen_base);
-            int jm = first_task(rank, nw, W.mvm_base);
-            const bool any_cen = jc < W.n_cen;
-            const bool any_mvm = (uint64_t)jm < n_mvm;
-            if (!any_cen && !any_mvm) continue;
-            if (I.serving && !wait_chunk(I, A, S.wfs, q, S.chunk)) return;
-            // centroid tasks
-            if (any_cen) {
-                // slopes buffer q & 1 is free once frame q - 2 has finished this block
-                if (q >= 2 && !wait_geq(I.mvm_done + (q & 1) * I.n_kb + S.kb, (q / 2) * n_mvm, A,
-                                        A.dep_watchdog))
-                    return;
-                const uint16_t *fr = frame_src(I, W.wfs, q);
-                const WfsParam &P = I.wp[W.wfs];
-                int n_done = 0;
-                for (; jc < W.n_cen; jc += nw, ++n_done) {
-                    if (W.kind == RTC_WFS_SH) {
-                        const int u = W.cu0 + jc;
-                        const ShUnit d = I.sh[u];
-                        if (I.serving)
-                            sh_unit<STORE_AGENT, LOAD_SYSTEM>(d, I.sh_thr[u], fr, P, I.sh_dark,
-                                                              I.sh_flat, I.sh_bg, I.ref, so, lane);
-                        else
-                            sh_unit<STORE_AGENT, LOAD_PLAIN>(d, I.sh_thr[u], fr, P, I.sh_dark,
-                                                             I.sh_flat, I.sh_bg, I.ref, so, lane);
-                    } else {
-                        const int k = W.cu0 + jc * kWave + lane;
-                        if (k < W.cu1) {
-                            const PyrUnit d = I.py[k];
-                            if (I.serving)
-                                pyr_unit<STORE_AGENT, LOAD_SYSTEM>(d, k, I.n_pyr, I.py_thr[k], fr,
-                                                                   P, I.py_dark, I.py_flat,
-                                                                   I.py_bg, I.ref, so);
-                            else
-                                pyr_unit<STORE_AGENT, LOAD_PLAIN>(d, k, I.n_pyr, I.py_thr[k], fr,
-                                                                  P, I.py_dark, I.py_flat, I.py_bg,
-                                                                  I.ref, so);
-                        }
-                    }
-                }
-                drain();
-                if (lane == 0) add_agent64(I.cen_done + (q & 1) * I.n_kb + S.kb, (uint64_t)n_done);
-            }
-            // MVM tasks of this block
-            if (any_mvm) {
-                if (!wait_geq(I.cen_done + (q & 1) * I.n_kb + S.kb, par_target(q, (uint64_t)W.n_cen),
-                              A, A.dep_watchdog))
-                    return;
-                const KBlock K = I.kbs[S.kb];
-                int staged = -1;
-                uint64_t n_done = 0;
-                for (; (uint64_t)jm < n_mvm; jm += nw, ++n_done) {
-                    const int sl = jm / I.n_tiles;
-                    const int t = jm - sl * I.n_tiles;
-                    const int sg = W.seg0 + sl;
-                    const Segment Sg = I.segs[sg];
-                    if (staged != sg) {
-                        if (staged >= 0) lds_done();
-                        stage_lds(lds, spad + K.spad + Sg.v0 * E, Sg.nv * E, lane);
-                        staged = sg;
-                    }
-                    if (q >= 2 &&
-                        !wait_geq(I.acc_done + t, (q - 2) * (uint64_t)I.n_kb + (uint64_t)S.kb + 1, A,
-                                  A.dep_watchdog))
-                        return;
-                    const int nr = min(kTileRows, I.n_act - t * kTileRows);
-                    const float v = seg_partial(I, K, Sg, t, nr, lane, lds);
-                    if (lane < nr)
-                        st_agent(I.y_part[q & 1] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
-                    drain();
-                    uint64_t old = 0;
-                    if (lane == 0)
-                        old = add_agent64(
-                            I.kbt_cnt + ((size_t)(q & 1) * I.n_kb + S.kb) * I.n_tiles + t, 1);
-                    old = __shfl(old, 0, kWave);
-                    // (E) party: the block's last partial on this tile
-                    if (old + 1 == par_target(q, (uint64_t)W.nseg) && join(I, q, S.kb, t, lane))
-                        run_chain(I, q, S.kb, t, lane);
-                }
-                lds_done();
-                if (lane == 0) add_agent64(I.mvm_done + (q & 1) * I.n_kb + S.kb, n_done);
+// This worker's first task of each kind in frame q, as an index into the
+// frame's whole list of that kind (every block; blocks hold consecutive
+// ranges in readout order).  Its later tasks follow nw apart, so a worker walks
+// its tasks with one running index and no division.
+struct FrameTasks {
+    int cen, mvm;
+};
+__device__ __forceinline__ FrameTasks frame_tasks(InstRef I, uint64_t q, int rank, int nw) {
+    FrameTasks f;
+    f.cen = first_task(rank, nw, rot(q, I.n_cen_all, nw));
+    f.mvm = first_task(rank, nw, rot(q, I.n_seg * I.n_tiles, nw));
+    return f;
+}
+
+// Centroid tasks of this worker in column block W of frame q: the running
+// index j (into the frame's task list) advances past the block.  Lane s
+// accumulates in cnt this worker's tasks on stripe s, counting tasks by their
+// frame index (global_idx: one barrier for the frame) or their block index.
+__device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, int lane,
+                               const SlopeOut &so, bool global_idx, int &j, uint32_t &cnt) {
+    const int end = W.cen_base + W.n_cen;
+    if (j >= end) return;
+    const uint16_t *fr = frame_src(I, W.wfs, q);
+    const WfsParam P = ldc(I.wp + W.wfs);
+    for (; j < end; j += nw) {
+        const int jc = j - W.cen_base;
+        if (stripe_lane(global_idx ? j : jc, lane)) ++cnt;
+        if (W.kind == RTC_WFS_SH) {
+            const int u = W.cu0 + jc;
+            const ShUnit d = ldc(I.sh + u);
+            if (I.serving)
+                sh_unit<STORE_AGENT, LOAD_SYSTEM>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
+                                                  I.sh_bg, I.ref, so, lane);
+            else
+                sh_unit<STORE_AGENT, LOAD_PLAIN>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
+                                                 I.sh_bg, I.ref, so, lane);
+        } else {
+            const int k = W.cu0 + jc * kWave + lane;
+            if (k < W.cu1) {
+                const PyrUnit d = ldg(I.py + k);
+                if (I.serving)
+                    pyr_unit<STORE_AGENT, LOAD_SYSTEM>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
+                                                       I.py_dark, I.py_flat, I.py_bg, I.ref, so);
+                else
+                    pyr_unit<STORE_AGENT, LOAD_PLAIN>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
+                                                      I.py_dark, I.py_flat, I.py_bg, I.ref, so);
             }
         }
-        if (I.polc && !polc_tasks(I, A, q, rank, nw, lane, lds)) return;
     }
+}
+
+// MVM tasks (segment x tile) of this worker in column block kb of frame q;
+// the block's slopes must be complete.  A tile's last partial joins its
+// accumulation (serving: of the block; batch: of the whole frame).
+__device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw, int lane,
+                          RTC_LDS float *lds, int &m, Trace &tr) {
+    const int n_tiles = I.n_tiles;
+    const int end = W.mvm_base + W.nseg * n_tiles;
+    if (m >= end) return;
+    if (tr.rec != nullptr && lane == 0 && gbl(tr.rec)[RTC_TRACE_MVM_FIRST] == 0)
+        gbl(tr.rec)[RTC_TRACE_MVM_FIRST] = wall_clock64();
+    const float *spad = I.s_pad[dslot(q)];
+    const int E = vec_elems(I.dtype);
+    const KBlock K = ldc(I.kbs + kb);
+    int staged = -1;
+    for (; m < end; m += nw) {
+        const int jm = m - W.mvm_base;
+        const int sl = jm / n_tiles;
+        const int t = jm - sl * n_tiles;
+        const int sg = W.seg0 + sl;
+        const Segment Sg = ldc(I.segs + sg);
+        if (staged != sg) {
+            if (staged >= 0) lds_done();
+            stage_lds(lds, spad + K.spad + Sg.v0 * E, Sg.nv * E, lane);
+            staged = sg;
+        }
+        const int nr = min(kTileRows, I.n_act - t * kTileRows);
+        const float v = seg_partial(I, K, Sg, t, nr, lane, lds);
+        if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
+        drain();
+        const int jkb = I.serving ? kb : 0;
+        const uint64_t need = I.serving ? (uint64_t)W.nseg : (uint64_t)I.n_seg;
+        uint64_t old = 0;
+        if (lane == 0)
+            old = add_agent64(slot(I.kbt_cnt, ((size_t)dslot(q) * I.n_kb + jkb) * I.n_tiles + t), 1);
+        old = __shfl(old, 0, kWave);
+        // (E) party: the last partial on this tile
+        if (old + 1 == par_target(I, q, need) && join(I, q, jkb, t, lane))
+            accumulate(I, q, jkb, t, lane, tr);
+    }
+    lds_done();
+    tr.stamp(RTC_TRACE_MVM_LAST, lane);
+}
+
+// This wavefront's timeline record of frame q, if recorded.
+__device__ __forceinline__ Trace trace_of(InstRef I, ArgsRef A, uint64_t q, int wid) {
+    Trace tr;
+    if (A.trace != nullptr && q - I.q_begin < (uint64_t)A.trace_frames)
+        tr.rec = A.trace + ((q - I.q_begin) * (uint64_t)A.n_waves + (uint64_t)wid) *
+                               RTC_TRACE_EVENTS;
+    return tr;
+}
+__device__ __forceinline__ void trace_end(Trace &tr, int lane) {
+    tr.put(RTC_TRACE_CHAIN_TICKS, tr.chain_ticks, lane);
+    tr.put(RTC_TRACE_CHAIN_BLOCKS, tr.chain_blocks, lane);
+    tr.stamp(RTC_TRACE_FRAME_END, lane);
+}
+
+// Frame gate: frame q reuses the buffers and counters of frame q - kDepth.
+__device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
+    return q < I.q_begin + kDepth ||
+           wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q - kDepth, I.n_tiles),
+                    A, A.dep_watchdog);
+}
+
+// Serving worker: column blocks in readout order, each as soon as its chunk
+// is delivered, with a fan-in barrier per block.
+__device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
+                               RTC_LDS float *lds) {
+    for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
+        if (stopping(A)) return;
+        Trace tr = trace_of(I, A, q, wid);
+        tr.stamp(RTC_TRACE_FRAME_START, lane);
+        if (!gate(I, A, q)) return;
+        tr.stamp(RTC_TRACE_GATE, lane);
+        const SlopeOut so{I.s_pad[dslot(q)], nullptr, nullptr, nullptr};
+        FrameTasks ft = frame_tasks(I, q, rank, nw);
+        const int n_steps = I.n_steps, n_tiles = I.n_tiles;
+        for (int st = 0; st < n_steps; ++st) {
+            const Step S = ldc(I.steps + st);
+            if (S.kb < 0) continue;
+            const KbWork W = ldc(I.kbw + S.kb);
+            const bool any_cen = ft.cen < W.cen_base + W.n_cen;
+            const bool any_mvm = ft.mvm < W.mvm_base + W.nseg * n_tiles;
+            if (!any_cen && !any_mvm) continue;
+            if (!wait_chunk(I, A, S.wfs, q, S.chunk)) return;
+            if (any_cen) {
+                uint32_t cnt = 0;
+                centroid_tasks(I, q, W, nw, lane, so, false, ft.cen, cnt);
+                drain();
+                (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt, lane);
+            }
+            tr.stamp(RTC_TRACE_CENTROIDS, lane);
+            if (any_mvm) {
+                if (!wait_geq(fan_top(fan_grp(I.cen_fan, q, I.n_kb, S.kb)),
+                              fan_target(I, q, W.n_cen), A, A.dep_watchdog))
+                    return;
+                mvm_tasks(I, q, W, S.kb, nw, lane, lds, ft.mvm, tr);
+            }
+        }
+        if (I.polc && !polc_tasks(I, A, q, rank, nw, lane, lds, tr)) return;
+        trace_end(tr, lane);
+    }
+}
+
+// Batch: this worker's centroid tasks of frame q (every block; one barrier
+// for the frame).  False when the loop must exit.
+__device__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane,
+                                Trace &tr) {
+    tr.stamp(RTC_TRACE_FRAME_START, lane);
+    if (!gate(I, A, q)) return false;
+    tr.stamp(RTC_TRACE_GATE, lane);
+    const int64_t qo = (int64_t)(q - I.q_begin);
+    const SlopeOut so{I.s_pad[dslot(q)], I.slopes_out ? I.slopes_out + qo * I.n_slopes : nullptr,
+                      I.counts_out ? I.counts_out + qo * I.n_units : nullptr, nullptr};
+    uint32_t cnt = 0;
+    int j = frame_tasks(I, q, rank, nw).cen;
+    const int n_kb = I.n_kb, n_all = I.n_cen_all;
+    for (int kb = 0; kb < n_kb && j < n_all; ++kb)
+        centroid_tasks(I, q, ldc(I.kbw + kb), nw, lane, so, true, j, cnt);
+    drain();
+    (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, 0), q, I.n_cen_all, cnt, lane);
+    tr.stamp(RTC_TRACE_CENTROIDS, lane);
+    return true;
+}
+
+// Batch worker: every pixel is already in device memory, so the loop is
+// software-pipelined over frames.  Iteration q forms the slopes of frame
+// q + 1, multiplies frame q (whose slopes were finished one iteration
+// earlier, so its barrier is normally already passed) and forms the POLC
+// term of frame q from a_{q-1}.  Every wait of iteration q is on work that
+// each worker did in an earlier iteration.
+__device__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
+                             RTC_LDS float *lds) {
+    Trace tc = trace_of(I, A, I.q_begin, wid);
+    if (!batch_centroids(I, A, I.q_begin, rank, nw, lane, tc)) return;
+    for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
+        if (stopping(A)) return;
+        Trace tr = trace_of(I, A, q, wid);
+        if (q + 1 < I.q_end) {
+            Trace tn = trace_of(I, A, q + 1, wid);
+            if (!batch_centroids(I, A, q + 1, rank, nw, lane, tn)) return;
+        }
+        if (!wait_geq(fan_top(fan_grp(I.cen_fan, q, I.n_kb, 0)), fan_target(I, q, I.n_cen_all), A,
+                      A.dep_watchdog))
+            return;
+        int m = frame_tasks(I, q, rank, nw).mvm;
+        const int n_kb = I.n_kb, n_all = I.n_seg * I.n_tiles;
+        for (int kb = 0; kb < n_kb && m < n_all; ++kb)
+            mvm_tasks(I, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr);
+        if (I.polc && q > I.q_begin && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
+        trace_end(tr, lane);
+    }
+    if (I.polc && !polc_tasks(I, A, I.q_end - 1, rank, nw, lane, lds, tc)) return;
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_frame_loop(PersistArgs A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_frame_loop(PersistArgs args) {
+    // the explicit arguments open the kernel-argument segment
+    (void)args;
+    ArgsRef A = *(const RTC_CONST PersistArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     __shared__ __attribute__((aligned(16))) float lds_all[4][kMaxSegVectors * 16];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    float *lds = lds_all[threadIdx.x >> 6];
+    RTC_LDS float *lds = (RTC_LDS float *)lds_all[threadIdx.x >> 6];
     for (int i = 0; i < A.n_inst; ++i) {
-        const PersistInst &I = A.inst[i];
+        InstRef I = ((volatile const RTC_CONST PersistInst *)A.inst)[i];
         if (wid < I.w0 || wid >= I.w1) continue;
         if (I.serving) {
             if (wid == I.w0) {
                 sentinel(I, A, lane);
                 return;
             }
-            worker(I, A, wid - I.w0 - 1, I.w1 - I.w0 - 1, lane, lds);
+            serving_worker(I, A, wid, wid - I.w0 - 1, I.w1 - I.w0 - 1, lane, lds);
         } else {
-            worker(I, A, wid - I.w0, I.w1 - I.w0, lane, lds);
+            batch_worker(I, A, wid, wid - I.w0, I.w1 - I.w0, lane, lds);
         }
         return;
     }
+}
+
+// Counters of one instance at the start of a launch: zero, except the joins
+// of the first frame (copy par), which find their (A) part, and with POLC
+// their (P) part, already counted.
+__global__ void k_seed_counters(uint64_t *ctr, size_t n, size_t join_off, int n_kb, int n_tiles,
+                                int par, int polc, int serving) {
+    const size_t join_end = join_off + (size_t)kDepth * n_kb * n_tiles * kCtrSlot;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t v = 0;
+        if (i >= join_off && i < join_end && (i - join_off) % kCtrSlot == 0) {
+            const size_t sl = (i - join_off) / kCtrSlot;
+            const int p = (int)(sl / ((size_t)n_kb * n_tiles));
+            const int kb = (int)((sl / n_tiles) % n_kb);
+            if (p == par) {
+                if (kb == 0) v += 1;
+                if (polc && kb == (serving ? n_kb - 1 : 0)) v += 1;
+            }
+        }
+        gbl(ctr)[i] = v;
+    }
+}
+
+void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_kb,
+                          int n_tiles, int par, int polc, int serving) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_seed_counters, dim3(blocks), dim3(256), 0, st, ctr, n, join_off, n_kb,
+                       n_tiles, par, polc, serving);
 }
 
 void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args) {

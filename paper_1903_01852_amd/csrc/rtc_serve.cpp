@@ -52,6 +52,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.kb_segs = I->d_kb_segs;
     d.steps = nullptr;
     d.n_kb = (int)I->kb.size();
+    d.n_cen_all = P.n_cen_all;
     d.n_seg = (int)I->seg.size();
     d.n_steps = (int)I->steps.size();
     d.n_wfs = (int)I->wfs.size();
@@ -78,20 +79,22 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.n_kbm = (int)I->kbm.size();
     d.n_segm = (int)I->segm.size();
     d.s_pad[0] = I->d_spad;
-    d.s_pad[1] = P.spad2;
     d.y_part[0] = I->d_ypart;
-    d.y_part[1] = P.ypart2;
     d.p_part[0] = I->d_ppart;
-    d.p_part[1] = P.ppart2;
+    for (int k = 1; k < kDepth; ++k) {
+        d.s_pad[k] = P.spad_x[k - 1];
+        d.y_part[k] = P.ypart_x[k - 1];
+        d.p_part[k] = P.ppart_x[k - 1];
+    }
     d.y_acc = P.yacc;
     d.p = I->d_p;
     d.a = I->d_a;
     d.a_stride = I->a_len;
-    d.cen_done = P.cen_done;
-    d.mvm_done = P.mvm_done;
+    d.cen_fan = P.cen_fan;
+    d.tile_fan = P.tile_fan;
+    d.pol_fan = P.pol_fan;
     d.kbt_cnt = P.kbt_cnt;
-    d.acc_done = P.acc_done;
-    d.tiles_done = P.tiles_done;
+    d.join = P.join;
     d.pol_cnt = P.pol_cnt;
     d.p_done = P.p_done;
     d.db_mirror = P.db_mirror;
@@ -104,8 +107,6 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.mail = I->h_mail;
     d.cmd_seq = P.cmd_seq;
     d.pol_seq = P.pol_seq;
-    d.pol_tiles = P.pol_tiles;
-    d.join = P.join;
     d.tel = P.tel;
     d.n_slopes = I->n_slopes;
     d.n_units = I->n_units;
@@ -121,9 +122,17 @@ Step *steps_dev(Instance *I) {
 // loop is launched rarely).  Batch: one descriptor through a pinned staging
 // slot and a copy ordered on the launch stream, so back-to-back batches on a
 // stream never overwrite a descriptor a running kernel still reads.
-rtc_status upload_and_launch(rtc_engine *e, std::vector<PersistInst> &descs, hipStream_t st,
-                             bool batch) {
+rtc_status upload_and_launch(rtc_engine *e, const std::vector<Instance *> &insts,
+                             std::vector<PersistInst> &descs, hipStream_t st, bool batch,
+                             int n_blocks) {
     PersistEngine &pe = e->pe;
+    // every launch counts from its first frame
+    for (size_t i = 0; i < insts.size(); ++i) {
+        const PersistInstState &P = insts[i]->ps;
+        launch_seed_counters(st, P.ctr, P.n_ctr, (size_t)(P.join - P.ctr), (int)insts[i]->kb.size(),
+                             insts[i]->n_tiles, (int)(descs[i].q_begin % kDepth), insts[i]->d.polc,
+                             descs[i].serving);
+    }
     PersistInst *dev = pe.d_inst;
     if (!batch) {
         HIP_TRY(hipMemcpy(pe.d_inst, descs.data(), descs.size() * sizeof(PersistInst),
@@ -149,7 +158,15 @@ rtc_status upload_and_launch(rtc_engine *e, std::vector<PersistInst> &descs, hip
     A.status = pe.status;
     A.dep_watchdog = kDepTicks;
     A.idle_watchdog = kIdleTicks;
-    launch_frame_loop(st, pe.n_blocks, A);
+    A.n_waves = n_blocks * 4;
+    if (pe.trace != nullptr) {
+        pe.trace_waves = A.n_waves;
+        A.trace = pe.trace;
+        A.trace_frames = pe.trace_frames;
+        HIP_TRY(hipMemsetAsync(pe.trace, 0,
+                               (size_t)pe.trace_frames * A.n_waves * RTC_TRACE_EVENTS * 8, st));
+    }
+    launch_frame_loop(st, n_blocks, A);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         std::fprintf(stderr, "rtc: frame loop launch failed: %s\n", hipGetErrorString(err));
@@ -209,7 +226,7 @@ rtc_status launch_serving(rtc_engine *e) {
         TRY(stage_state_in(I, d.q_begin, pe.stream));
         descs.push_back(d);
     }
-    TRY(upload_and_launch(e, descs, pe.stream, false));
+    TRY(upload_and_launch(e, e->inst, descs, pe.stream, false, pe.n_blocks));
     pe.running = true;
     pe.serving = true;
     return RTC_OK;
@@ -234,32 +251,37 @@ rtc_status persist_alloc(rtc_engine *e) {
     }
     int dev_cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, e->device));
-    // half the occupancy limit: the grid must be entirely resident, with room
-    // to spare for whatever else shares the device
-    const int per_cu = std::min(2, frame_loop_max_blocks_per_cu());
-    if (per_cu < 1) return RTC_E_DEVICE;
-    pe.n_blocks = dev_cus * per_cu;
+    // the grid must be entirely resident: a serving loop runs indefinitely and
+    // leaves room on every CU for whatever else shares the device; a batch
+    // launch is finite and takes the whole occupancy
+    const int occ = frame_loop_max_blocks_per_cu();
+    if (occ < 1) return RTC_E_DEVICE;
+    pe.n_blocks = dev_cus * std::min(2, occ);
+    pe.n_blocks_batch = dev_cus * occ;
     for (Instance *I : e->inst) {
         PersistInstState &P = I->ps;
         const size_t nkb = I->kb.size(), nt = (size_t)I->n_tiles;
-        TRY(dev_alloc(e, &P.spad2, I->spad_len));
-        TRY(dev_alloc(e, &P.ypart2, I->seg.size() * (size_t)I->n_act));
-        TRY(dev_alloc(e, &P.ppart2, std::max<size_t>(I->segm.size(), 1) * (size_t)I->n_act));
+        for (int k = 0; k < kDepth - 1; ++k) {
+            TRY(dev_alloc(e, &P.spad_x[k], I->spad_len));
+            TRY(dev_alloc(e, &P.ypart_x[k], I->seg.size() * (size_t)I->n_act));
+            TRY(dev_alloc(e, &P.ppart_x[k],
+                          std::max<size_t>(I->segm.size(), 1) * (size_t)I->n_act));
+        }
         TRY(dev_alloc(e, &P.yacc, I->n_act));
-        // counters, arrival counters twice (frame parity): cen_done, mvm_done
-        // [2][nkb]; kbt_cnt [2][nkb][nt]; pol_cnt [2][nt]; tiles_done [2];
-        // sequence values once: acc_done, p_done [nt]; pol_tiles [1]
-        P.n_ctr = 4 * nkb + 2 * nkb * nt + 2 * nt + 2 * nt + 2 + 1 + 2 * nkb * nt;
+        // counters, each in a slot of its own; arrival counters kDepth times:
+        // fan-in barriers cen [D][nkb], tile [D], pol [D]; kbt_cnt and join
+        // [D][nkb][nt]; pol_cnt [D][nt]; p_done [nt] once
+        const size_t fan = kFanSlots, D = kDepth;
+        const size_t n_slots = D * nkb * fan + 2 * D * fan + 2 * D * nkb * nt + D * nt + nt;
+        P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
-        P.cen_done = P.ctr;
-        P.mvm_done = P.cen_done + 2 * nkb;
-        P.kbt_cnt = P.mvm_done + 2 * nkb;
-        P.pol_cnt = P.kbt_cnt + 2 * nkb * nt;
-        P.acc_done = P.pol_cnt + 2 * nt;
-        P.p_done = P.acc_done + nt;
-        P.tiles_done = P.p_done + nt;
-        P.pol_tiles = P.tiles_done + 2;
-        P.join = P.pol_tiles + 1;
+        P.cen_fan = P.ctr;
+        P.tile_fan = P.cen_fan + D * nkb * fan * kCtrSlot;
+        P.pol_fan = P.tile_fan + D * fan * kCtrSlot;
+        P.kbt_cnt = P.pol_fan + D * fan * kCtrSlot;
+        P.join = P.kbt_cnt + D * nkb * nt * kCtrSlot;
+        P.pol_cnt = P.join + D * nkb * nt * kCtrSlot;
+        P.p_done = P.pol_cnt + D * nt * kCtrSlot;
         TRY(dev_alloc(e, &P.db_mirror, I->wfs.size()));
         TRY(dev_alloc(e, &P.drop_mirror, e->ring_depth));
         TRY(dev_alloc(e, &P.param_mirror, 1));
@@ -295,6 +317,7 @@ rtc_status persist_alloc(rtc_engine *e) {
             mvm_base += W.nseg * I->n_tiles;
             P.kbw_h.push_back(W);
         }
+        P.n_cen_all = cen_base;
         // one allocation: KbWork table followed by the readout steps
         const size_t bytes = P.kbw_h.size() * sizeof(KbWork) + I->steps.size() * sizeof(Step);
         uint8_t *buf = nullptr;
@@ -363,26 +386,38 @@ rtc_status persist_quiesce(rtc_engine *e) {
     return persist_stop(e);
 }
 
+rtc_status persist_trace(rtc_engine *e, int n_frames) {
+    PersistEngine &pe = e->pe;
+    if (pe.trace != nullptr) {
+        HIP_TRY(hipFree(pe.trace));
+        pe.trace = nullptr;
+    }
+    pe.trace_frames = 0;
+    pe.trace_waves = 0;
+    if (n_frames == 0) return RTC_OK;
+    const size_t bytes =
+        (size_t)n_frames * std::max(pe.n_blocks, pe.n_blocks_batch) * 4 * RTC_TRACE_EVENTS * 8;
+    if (hipMalloc(&pe.trace, bytes) != hipSuccess) {
+        pe.trace = nullptr;
+        return RTC_E_NOMEM;
+    }
+    HIP_TRY(hipMemset(pe.trace, 0, bytes));
+    pe.trace_frames = n_frames;
+    return RTC_OK;
+}
+
 void persist_free(rtc_engine *e) {
     PersistEngine &pe = e->pe;
+    if (pe.trace) (void)hipFree(pe.trace);
     for (int k = 0; k < 2; ++k)
         if (pe.batch_copied[k]) (void)hipEventDestroy(pe.batch_copied[k]);
     if (pe.stream) (void)hipStreamDestroy(pe.stream);
 }
 
-// Zero every frame-loop counter and sequence (the loop must be stopped), and
-// pre-count the joins frame 0 inherits: the accumulation before block 0 and,
-// with POLC, the POLC term of the last block.
+// Zero every frame-loop sequence (the loop must be stopped); each launch
+// resets its own counters.
 void persist_reset(Instance *I) {
     PersistInstState &P = I->ps;
-    (void)hipMemset(P.ctr, 0, P.n_ctr * sizeof(uint64_t));
-    const size_t nkb = I->kb.size(), nt = (size_t)I->n_tiles;
-    std::vector<uint64_t> j0(nkb * nt, 0);
-    for (size_t t = 0; t < nt; ++t) {
-        j0[t] += 1;
-        if (I->d.polc) j0[(nkb - 1) * nt + t] += 1;
-    }
-    (void)hipMemcpy(P.join, j0.data(), j0.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     (void)hipMemset(P.db_mirror, 0, I->wfs.size() * sizeof(uint64_t));
     (void)hipMemset(P.drop_mirror, 0, P.slot_frame.size() * sizeof(uint64_t));
     for (size_t w = 0; w < I->wfs.size(); ++w) *vol(P.doorbell + w) = 0;
@@ -569,11 +604,11 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
     d.slopes_out = slopes;
     d.counts_out = counts;
     d.w0 = 0;
-    d.w1 = pe.n_blocks * 4;
+    d.w1 = pe.n_blocks_batch * 4;
     // this instance alone; the other descriptors must not claim workers
     std::vector<PersistInst> descs(1, d);
     TRY(stage_state_in(I, d.q_begin, st));
-    TRY(upload_and_launch(e, descs, st, true));
+    TRY(upload_and_launch(e, {I}, descs, st, true, pe.n_blocks_batch));
     TRY(stage_state_out(I, d.q_end - 1, st));
     P.seq = d.q_end;
     I->next_frame += (uint64_t)n_frames;

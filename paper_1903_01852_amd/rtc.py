@@ -28,7 +28,10 @@ MAX_WFS = 16
 EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chunk_rows",
            "rtc_load_matrices", "rtc_load_calibration", "rtc_set_params", "rtc_get_state",
            "rtc_set_state", "rtc_submit_pixel_chunk", "rtc_wait_commands",
-           "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm")
+           "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
+           "rtc_trace_enable", "rtc_trace_read")
+TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
+                "chain_blocks", "frame_end")
 
 
 class RtcError(RuntimeError):
@@ -101,6 +104,8 @@ def lib() -> C.CDLL:
         L.rtc_read_slopes.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_read_matrix.argtypes = [vp, i32, vp, vp]
         L.rtc_run_mvm.argtypes = [vp, i32, i32, vp]
+        L.rtc_trace_enable.argtypes = [vp, i32]
+        L.rtc_trace_read.argtypes = [vp, vp, i64, C.POINTER(i32), C.POINTER(i32)]
         for name in EXPORTS:
             if name != "rtc_strerror":
                 getattr(L, name).restype = C.c_int
@@ -288,6 +293,20 @@ class Engine:
 
     def run_mvm(self, inst: int, n_iter: int, stream=None):
         _ok(lib().rtc_run_mvm(self._h, inst, n_iter, _stream_ptr(stream)), "rtc_run_mvm")
+
+    def trace_enable(self, n_frames: int):
+        """Record the frame loop's per-wavefront timeline for the first n_frames
+        frames of each later launch (0 turns it off)."""
+        _ok(lib().rtc_trace_enable(self._h, n_frames), "rtc_trace_enable")
+
+    def trace_read(self) -> np.ndarray:
+        """The last launch's record as (frames, waves, len(TRACE_EVENTS)) uint64."""
+        nw, nf = C.c_int32(0), C.c_int32(0)
+        _ok(lib().rtc_trace_read(self._h, None, 0, C.byref(nw), C.byref(nf)), "rtc_trace_read")
+        out = np.zeros((nf.value, nw.value, len(TRACE_EVENTS)), np.uint64)
+        if out.size:
+            _ok(lib().rtc_trace_read(self._h, _ptr(out), out.size, None, None), "rtc_trace_read")
+        return out
 
     def read_slopes(self, inst: int = 0):
         info = self.infos[inst]
