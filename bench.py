@@ -3,19 +3,27 @@
 A step is one frame through every stage: calibration + slopes for every
 sensor, the split-K control-matrix MVM, the in-order accumulation +
 integrator (and the POLC product when the workload has it).  Frames are
-resident in HBM before the timed region and run through the persistent frame
-loop in batches of `--bank` frames per launch; ``value`` is frames per second.
+resident in HBM before the timed region.  ``value`` is frames per second of
+the batch path named by ``--path``:
+  stream      per-launch kernels (centroids, then the split-K MVM whose last
+              wavefront per row tile runs the integrator), one frame after the
+              other on one stream; the default, and the faster batch form;
+  persistent  the persistent frame loop, ``--bank`` frames per launch.
 
 Also reported on the same JSON line:
-  latency_us   serving-path latency of the persistent loop (last chunk
-               submitted from host memory -> commands seen on the host), frames
-               paced at 500 Hz with the chunks spread over a 1.5 ms readout;
-               this figure includes PCIe;
-  roofline     the frame-loop kernel's algorithmic bytes per launch / its
-               average launch duration, from HIP events on its stream;
-  mvm          the standalone split-K MVM kernel (warm and after a cache flush);
-  variants     the same step with BF16 and FP8 matrix storage, and the
-               per-launch (non-persistent) path;
+  roofline     the dominant kernel of the chosen path (k_mvm, or k_frame_loop):
+               algorithmic bytes per launch / its average duration, from HIP
+               events recorded on its own stream around every launch of the
+               timed region; ``traffic`` from the committed rocprofv3 counter
+               summary when it was taken on the current kernel source;
+  paths        frames/s and kernel GB/s of both batch forms for every storage
+               type (FP32, BF16, FP8);
+  latency_us   serving latency of the persistent loop per storage type (last
+               chunk submitted from host memory -> commands seen on the host),
+               frames paced at 500 Hz with the chunks spread over a 1.5 ms
+               readout; p50 / p99 / RMS jitter; includes PCIe;
+  mvm          the standalone MVM kernel per storage type, warm (back to back)
+               and after a 1 GiB read-only flush of the caches;
   cpu_baseline the CPU oracle on a bounded sample of the same frames.
 """
 from __future__ import annotations
@@ -34,6 +42,7 @@ if ROOT not in sys.path:
 METRIC = ("frame latency p50/p99 µs + RMS jitter; CM MVM HBM GB/s vs peak, "
           "FP32 vs BF16")
 HBM_PEAK_GBS = 8000.0
+MVM_SAMPLE_EVERY = 16      # per-launch path: time one MVM launch in 16
 ELEM = {"f32": 4, "bf16": 2, "fp8": 1}
 
 WORKLOAD_TEXT = {
@@ -63,9 +72,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str):
-    """HBM bytes per MVM launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+def measured_traffic(workload: str, dtype: str, kernel: str = "k_mvm"):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "mvm_traffic.json")
     if not os.path.exists(p):
         return None
@@ -75,7 +84,7 @@ def measured_traffic(workload: str, dtype: str):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    ent = d.get("entries", {}).get(f"{workload}:{dtype}")
+    ent = d.get("entries", {}).get(f"{workload}:{dtype}:{kernel.split('<')[0]}")
     return None if ent is None else ent.get("hbm_bytes_per_launch")
 
 
@@ -127,27 +136,39 @@ def run_steps(eng, dframes, bank, n, stream):
         done += k
 
 
-def throughput(torch, eng, dframes, bank, steps, warmup):
-    """Wall time of `steps` frames, and the average duration of one launch
-    (`bank` frames) from HIP events recorded on the launch stream."""
+def throughput(torch, eng, dframes, bank, steps, warmup, path):
+    """Wall time of `steps` frames and the average duration of the path's
+    dominant kernel: per launch of `bank` frames of the frame loop (HIP events
+    around each process_frames call on its stream), or per MVM launch of the
+    per-launch path (HIP events the library records around each MVM)."""
     st = torch.cuda.current_stream()
     run_steps(eng, dframes, bank, warmup, st)
     torch.cuda.synchronize()
     n_launch = (steps + bank - 1) // bank
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(n_launch)]
+    ev = []
+    if path == "persistent":
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(n_launch)]
+    else:
+        eng.mvm_timing(0, steps, MVM_SAMPLE_EVERY)
     t0 = time.perf_counter()
     done = 0
-    for a, b in ev:
+    for i in range(n_launch):
         k = min(bank, steps - done)
-        a.record(st)
+        if ev:
+            ev[i][0].record(st)
         eng.process_frames(0, dframes, k, stream=st)
-        b.record(st)
+        if ev:
+            ev[i][1].record(st)
         done += k
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    full = [a.elapsed_time(b) / 1e3 for a, b in ev[:steps // bank]]
-    return dt, (sum(full) / len(full) if full else None)
+    if ev:
+        full = [a.elapsed_time(b) / 1e3 for a, b in ev[:steps // bank]]
+        return dt, (sum(full) / len(full) if full else None), len(full), bank
+    n, tot = eng.mvm_timing_read(0)
+    eng.mvm_timing(0, 0, 1)
+    return dt, (tot / n if n else None), n, 1
 
 
 def mvm_timing(torch, eng, n_iter=200, cold=False):
@@ -182,40 +203,147 @@ def mvm_timing(torch, eng, n_iter=200, cold=False):
     return tot / n
 
 
-def serving_latency(rtc, eng, inst, frames, n_frames, warmup=100, period_s=2e-3,
-                    readout_s=1.5e-3):
-    """Paced serving loop from host memory; returns latencies in microseconds."""
+def _pct(v):
     import numpy as np
-    nw = len(inst.wfs)
-    chunks = []        # (wfs, chunk, r0, r1) in readout order, sensors read in parallel
-    n_ch = max(w.n_chunks for w in inst.wfs)
-    for c in range(n_ch):
+    v = np.asarray(v, dtype=np.float64)
+    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)),
+            "mean": float(v.mean()), "rms_jitter": float(v.std()), "max": float(v.max())}
+
+
+def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s=1.5e-3,
+                    switch=None):
+    """Paced serving loop from host memory for one or more instances of one
+    engine, every sensor read out in parallel: chunk c of each sensor of an
+    instance with n chunks is delivered (c + 1) * readout / n after the frame
+    start.  streams: [(instance index, per-sensor frame banks)].  switch:
+    (instance index, frame, gain, leak) applied through the API before that
+    frame.  Returns per instance: host latency (last chunk submitted -> commands
+    seen on the host) and the device part (the loop's own clock from the
+    sentinel seeing the last chunk to the commands being published)."""
+    plan = []
+    for idx, banks in streams:
+        info = eng.infos[idx]
+        nw = info["n_wfs"]
+        n_ch = [eng.n_chunks(idx, w) for w in range(nw)]
         for w in range(nw):
-            if c < inst.wfs[w].n_chunks:
-                r0, r1 = eng.chunk_rows(0, w, c)
-                chunks.append((w, c, r0, r1))
-    gap = readout_s / max(1, n_ch)
-    lat = []
-    bank = frames[0].shape[0]
+            for c in range(n_ch[w]):
+                r0, r1 = eng.chunk_rows(idx, w, c)
+                plan.append(((c + 1) * readout_s / n_ch[w], idx, w, c, r0, r1))
+    plan.sort(key=lambda x: (x[0], x[1], x[2]))
+    host = {idx: [] for idx, _ in streams}
+    dev = {idx: [] for idx, _ in streams}
+    banks = dict(streams)
     t_next = time.perf_counter()
     for f in range(n_frames + warmup):
+        if switch is not None and f == switch[1]:
+            eng.set_params(switch[0], switch[2], switch[3])
         t_frame = t_next
-        for idx, (w, c, r0, r1) in enumerate(chunks):
-            t_c = t_frame + (c + 1) * gap
-            while time.perf_counter() < t_c:
+        for t_c, idx, w, c, r0, r1 in plan:
+            while time.perf_counter() < t_frame + t_c:
                 pass
-            eng.submit_chunk(0, w, f, c, frames[w][f % bank][r0:r1])
-        _, info = eng.wait_commands(0, f, timeout_s=5.0)
-        if f >= warmup:
-            lat.append((info["t_ready_ns"] - info["t_last_chunk_ns"]) / 1e3)
+            bank = banks[idx][w]
+            eng.submit_chunk(idx, w, f, c, bank[f % bank.shape[0]][r0:r1])
+        for idx, _ in streams:
+            _, info = eng.wait_commands(idx, f, timeout_s=5.0)
+            if f >= warmup:
+                host[idx].append((info["t_ready_ns"] - info["t_last_chunk_ns"]) / 1e3)
+                dev[idx].append((info["dev_ticks_cmd"] - info["dev_ticks_start"]) * 0.01)
         t_next = t_frame + period_s
-    lat = np.asarray(lat)
-    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-            "mean": float(lat.mean()), "rms_jitter": float(lat.std()),
-            "max": float(lat.max()), "frames": int(lat.size),
-            "pacing": f"{1 / period_s:.0f} Hz, chunks spread over {readout_s * 1e3:.1f} ms",
-            "includes": "host memcpy into the pinned ring, PCIe copy, last chunk's slopes and "
-                        "K-block MVM, integrator, copy of the commands to pinned host memory"}
+    out = {}
+    for idx, _ in streams:
+        r = _pct(host[idx])
+        r["frames"] = len(host[idx])
+        r["device"] = _pct(dev[idx])
+        out[idx] = r
+    return out
+
+
+SERVING_NOTE = {"pacing": "500 Hz frames, every sensor's chunks spread over a 1.5 ms readout",
+                "host": "last chunk submitted (host memcpy into the pinned ring, doorbell) -> "
+                        "commands seen in the pinned mailbox by the host",
+                "device": "device clock (100 MHz): the loop's sentinel seeing the frame's last "
+                          "chunk -> the last tile's commands published"}
+
+
+def latency_suite(torch, rtc, dtypes, n_frames, log):
+    """ELT-scale serving cases in one persistent launch each: MCAO (6 LGS SH 74x74 + 3 NGS
+    2x2, POLC) and LTAO (6 LGS SH 68x68 + 1 NGS 8x8, POLC, gain and leak switched
+    mid-run) running beside the SCAO SH 74x74 instance of uneven size."""
+    import numpy as np
+    import synth
+    res = {}
+    for name in ("mcao_74", "ltao_68"):
+        wl = synth.get_workload(name)
+        mats, banks = [], []
+        for i, inst in enumerate(wl.instances):
+            R = synth.control_matrix(wl, i)
+            M = None
+            if inst.polc:
+                na = inst.n_act
+                M = synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na),
+                                          synth.seed_for(wl.index, i, 99, 5), np.float32)
+            fr, cal = [], []
+            for w in range(len(inst.wfs)):
+                f_w, c_w = synth.sensor_inputs(wl, i, w, n=16)
+                fr.append(f_w)
+                cal.append(c_w)
+            mats.append((R, M, cal))
+            banks.append(fr)
+        for dtype in dtypes:
+            log(f"bench: serving {name} {dtype}")
+            eng = rtc.Engine([(inst, dtype) for inst in wl.instances], ring_depth=4,
+                             mode="persistent")
+            for i, (R, M, cal) in enumerate(mats):
+                eng.load_matrices(i, R, M=M)
+                for w, c in enumerate(cal):
+                    eng.load_calibration(i, w, c.dark, c.flat, c.bg, c.thr, c.ref)
+            switch = None
+            sw_inst = [i for i, inst in enumerate(wl.instances) if inst.switch is not None]
+            if sw_inst:
+                i = sw_inst[0]
+                switch = (i, n_frames // 2 + 100, wl.instances[i].switch[1],
+                          wl.instances[i].switch[2])
+            lat = serving_latency(eng, [(i, banks[i]) for i in range(len(wl.instances))],
+                                  n_frames, switch=switch)
+            eng.close()
+            for i, inst in enumerate(wl.instances):
+                key = f"{name}:{inst.name}:{dtype}"
+                r = lat[i]
+                r.update({"n_act": inst.n_act, "n_wfs": len(inst.wfs), "polc": inst.polc,
+                          "instances_in_launch": len(wl.instances)})
+                if switch is not None and switch[0] == i:
+                    r["gain_leak_switch_at_frame"] = switch[1] - 100
+                res[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
+                log(f"bench: {key}: p50 {r['p50']:.1f} p99 {r['p99']:.1f} "
+                    f"jitter {r['rms_jitter']:.2f} us (device p50 {r['device']['p50']:.1f})")
+        del mats, banks
+    return res
+
+
+def box_reference(torch, reps=10):
+    """HBM reference of this particular box: a plain 512 MiB device-to-device
+    copy (read + write bytes per second, median of `reps`).  MI355X boxes in one
+    pool have shown different sustained bandwidths for the same code, so every
+    kernel figure is reported beside this one."""
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        dst.copy_(src)
+        b.record(st)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    ts.sort()
+    t = ts[len(ts) // 2]
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    return {"copy_gbs": round(nbytes / t / 1e9, 1), "bytes": nbytes,
+            "what": "median of 10 device-to-device copies of 512 MiB (read + write)"}
 
 
 def cpu_baseline(inst, frames, cals, R, M, budget_s=12.0):
@@ -248,12 +376,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--workload", default="scao_sh_74")
     ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--path", default="stream", choices=("stream", "persistent"))
     ap.add_argument("--variants", default="bf16,fp8")
     ap.add_argument("--bank", type=int, default=64)
     ap.add_argument("--latency-frames", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="throughput only (for profiling)")
+    ap.add_argument("--no-latency-suite", action="store_true",
+                    help="skip the MCAO / LTAO+SCAO serving cases")
+    ap.add_argument("--quick", action="store_true",
+                    help="the chosen path and storage type only (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -273,27 +405,6 @@ def main():
     wl, inst, frames, cals, R, M = build_inputs(args.workload, args.bank)
     dframes = [torch.from_numpy(f).cuda() for f in frames]
 
-    def one(dtype, full, mode="persistent"):
-        eng = make_engine(rtc, inst, dtype, cals, R, M, mode=mode)
-        info = eng.infos[0]
-        dt, launch_s = throughput(torch, eng, dframes, args.bank, args.steps, args.warmup)
-        res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
-               "alg_bytes_per_frame": alg_bytes_per_frame(inst, info, dtype)}
-        if launch_s is not None:
-            res["launch_us"] = launch_s * 1e6
-            res["frames_per_launch"] = args.bank
-            res["loop_gbs"] = res["alg_bytes_per_frame"] * args.bank / launch_s / 1e9
-        if full:
-            warm = mvm_timing(torch, eng)
-            cold = mvm_timing(torch, eng, cold=True)
-            alg = (inst.n_act * info["n_slopes"] * ELEM[dtype] + 4 * info["n_slopes"]
-                   + 4 * inst.n_act)
-            res.update({"mvm_us_warm": warm * 1e6, "mvm_us_cold": cold * 1e6,
-                        "alg_bytes": alg, "cm_bytes_stored": info["cm_bytes"],
-                        "gbs_warm": alg / warm / 1e9, "gbs_cold": alg / cold / 1e9})
-        log(f"bench: {dtype}: {res}")
-        return eng, res
-
     if args.copy_probe:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -303,42 +414,79 @@ def main():
         log(f"bench: copy probe: 5 x {src.numel() * 4} bytes read and written")
         del src, dst
 
-    eng, main_res = one(args.dtype, True)
-    variants = {}
-    if not args.quick:
-        for dt_name in [v for v in args.variants.split(",") if v and v != args.dtype]:
-            e2, r2 = one(dt_name, True)
-            e2.close()
-            variants[dt_name] = r2
-        e3, r3 = one(args.dtype, False, mode="stream")
-        e3.close()
-        variants[f"{args.dtype}_per_launch_path"] = r3
+    def mvm_alg_bytes(info, dtype):
+        return (inst.n_act * info["n_slopes"] * ELEM[dtype] + 4 * info["n_slopes"]
+                + 4 * inst.n_act + (4 * inst.n_act if dtype == "fp8" else 0))
 
-    latency = None
-    if not args.quick and not args.no_latency:
-        log("bench: serving latency")
-        eng.set_state(0, None, None, 0)
-        latency = serving_latency(rtc, eng, inst, frames, args.latency_frames)
-        log(f"bench: latency {latency}")
-    eng.close()
+    def run_path(eng, dtype, path):
+        info = eng.infos[0]
+        dt, kern_s, n_timed, per = throughput(torch, eng, dframes, args.bank, args.steps,
+                                              args.warmup, path)
+        per_frame = alg_bytes_per_frame(inst, info, dtype)
+        res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
+               "alg_bytes_per_frame": per_frame}
+        if kern_s:
+            kb = per_frame * per if path == "persistent" else mvm_alg_bytes(info, dtype)
+            res.update({"kernel": "k_frame_loop" if path == "persistent" else f"k_mvm<{dtype}>",
+                        "kernel_us": kern_s * 1e6, "kernel_launches_timed": n_timed,
+                        "kernel_alg_bytes": kb, "kernel_gbs": kb / kern_s / 1e9})
+        log(f"bench: {dtype} {path}: {res}")
+        return res
+
+    def mvm_standalone(eng, dtype):
+        info = eng.infos[0]
+        warm = mvm_timing(torch, eng)
+        cold = mvm_timing(torch, eng, cold=True)
+        alg = mvm_alg_bytes(info, dtype)
+        return {"alg_bytes": alg, "cm_bytes_stored": info["cm_bytes"],
+                "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9,
+                "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9}
+
+    ref = box_reference(torch)
+    log(f"bench: box reference {ref}")
+
+    dtypes = [args.dtype] + ([] if args.quick else
+                             [v for v in args.variants.split(",") if v and v != args.dtype])
+    paths = {"stream": {}, "persistent": {}}
+    mvm = {}
+    latency = {}
+    for dtype in dtypes:
+        for path in ("stream", "persistent"):
+            if args.quick and path != args.path:
+                continue
+            eng = make_engine(rtc, inst, dtype, cals, R, M, mode=path)
+            paths[path][dtype] = run_path(eng, dtype, path)
+            if path == "stream":
+                mvm[dtype] = mvm_standalone(eng, dtype)
+                log(f"bench: {dtype} mvm: {mvm[dtype]}")
+            elif not args.quick and not args.no_latency:
+                eng.set_state(0, None, None, 0)
+                latency[dtype] = serving_latency(eng, [(0, frames)], args.latency_frames)[0]
+                log(f"bench: {dtype} latency: {latency[dtype]}")
+            eng.close()
+
+    suite = None
+    if not args.quick and not args.no_latency and not args.no_latency_suite:
+        suite = latency_suite(torch, rtc, dtypes, args.latency_frames, log)
 
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
         cpu = cpu_baseline(inst, frames, cals, R, M)
 
-    achieved = main_res["loop_gbs"]
+    main_res = paths[args.path][args.dtype]
+    achieved = main_res["kernel_gbs"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, args.dtype),
-            "kernel": "k_frame_loop",
-            "avg_launch_us": round(main_res["launch_us"], 3),
-            "frames_per_launch": args.bank,
-            "algorithmic_bytes_per_launch": main_res["alg_bytes_per_frame"] * args.bank}
-    mvm = {"kernel": f"k_mvm<{args.dtype}>", "alg_bytes": main_res["alg_bytes"],
-           "warm_us": round(main_res["mvm_us_warm"], 3), "warm_gbs": round(main_res["gbs_warm"], 1),
-           "cold_us": round(main_res["mvm_us_cold"], 3), "cold_gbs": round(main_res["gbs_cold"], 1),
-           "cold_frac": round(main_res["gbs_cold"] / HBM_PEAK_GBS, 4)}
+            "traffic": measured_traffic(args.workload, args.dtype, main_res["kernel"]),
+            "kernel": main_res["kernel"],
+            "avg_launch_us": round(main_res["kernel_us"], 3),
+            "launches_timed": main_res["kernel_launches_timed"],
+            "algorithmic_bytes_per_launch": main_res["kernel_alg_bytes"]}
+
+    def rnd(d):
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+
     out = {
         "metric": METRIC, "value": round(main_res["frames_per_s"], 1), "unit": "frames/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -347,12 +495,16 @@ def main():
         "data": "synthetic (seeded SH spots / pyramid images with the paper's shapes, "
                 "Gaussian control matrix)",
         "config": {"workload": args.workload, "description": WORKLOAD_TEXT.get(args.workload),
+                   "path": {"stream": "per-launch kernels",
+                            "persistent": "persistent frame loop"}[args.path],
                    "frames_in_bank": args.bank, "cm_storage": args.dtype},
         "roofline": roof,
-        "mvm": mvm,
-        "latency_us": latency,
-        "variants": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
-                         for kk, vv in v.items()} for k, v in variants.items()},
+        "box_reference": ref,
+        "latency_us": ({k: rnd(v) for k, v in latency.items()} | {"what": SERVING_NOTE}
+                       if latency else None),
+        "latency_suite_us": ({**suite, "what": SERVING_NOTE} if suite else None),
+        "paths": {p: {k: rnd(v) for k, v in d.items()} for p, d in paths.items() if d},
+        "mvm": {k: rnd(v) for k, v in mvm.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -204,6 +204,17 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
  * stream).  Changes no command state. */
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
 
+/* MVM kernel timer (RTC_MODE_STREAM diagnostics).  With capacity > 0, every
+ * `every`-th later rtc_process_frames frame records a pair of HIP events on
+ * its stream around the reconstruction MVM launch, up to capacity pairs (each
+ * pair adds two queue packets, so sampling keeps the timed run close to an
+ * untimed one); capacity 0 turns the timer off.  rtc_mvm_timing_read
+ * synchronises on the last recorded pair, returns the number of timed
+ * launches and the sum of their durations (ms) and clears the record.
+ * RTC_E_STATE in persistent mode. */
+rtc_status rtc_mvm_timing(rtc_engine *e, int32_t inst, int32_t capacity, int32_t every);
+rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *total_ms);
+
 /* Frame-loop timeline (RTC_MODE_PERSISTENT diagnostics).  With n_frames > 0,
  * every wavefront of every later frame-loop launch records RTC_TRACE_EVENTS
  * device-clock values (wall clock, 100 MHz) for each of the first n_frames
@@ -227,7 +238,8 @@ rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames);
  * the launch's first, wave = global wavefront index (a serving instance's
  * sentinel included, left zero).  Zero marks an event that did not happen.
  * capacity counts uint64 values; n_waves and n_frames (nullable) receive the
- * record's shape.  Synchronises the engine stream. */
+ * record's shape.  Stops a running serving loop (as rtc_get_state does) and
+ * synchronises the device. */
 rtc_status rtc_trace_read(rtc_engine *e, uint64_t *out, int64_t capacity, int32_t *n_waves,
                           int32_t *n_frames);
 

@@ -113,18 +113,18 @@ __device__ __forceinline__ void put(float *p, float v) {
 }
 
 // Load policies for pixels: LOAD_PLAIN for frames in device memory written
-// before the kernel started; LOAD_SYSTEM for the pinned host ring that the host
-// refills while the kernel runs (system-scope 32-bit loads bypass the GPU
-// caches, which could otherwise return a ring slot's previous frame; the
-// aligned word may include the neighbouring pixel, so ring buffers carry four
-// bytes of slack).
-enum { LOAD_PLAIN = 0, LOAD_SYSTEM = 1 };
+// before the kernel started; LOAD_AGENT for the device ring that wavefronts of
+// the same kernel refill while it runs (agent-scope 32-bit loads read past the
+// XCD's non-coherent L2, which could otherwise return a ring slot's previous
+// frame; the aligned word may include the neighbouring pixel, so rings carry
+// slack after the last slot).
+enum { LOAD_PLAIN = 0, LOAD_AGENT = 1 };
 template <int LP>
 __device__ __forceinline__ uint32_t load_px(const uint16_t *p) {
-    if constexpr (LP == LOAD_SYSTEM) {
+    if constexpr (LP == LOAD_AGENT) {
         const uintptr_t a = reinterpret_cast<uintptr_t>(p);
         const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
-        const uint32_t v = __hip_atomic_load(gbl(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t v = __hip_atomic_load(gbl(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return (a & 2) ? (v >> 16) : (v & 0xFFFFu);
     } else {
         return *gbl(p);

@@ -182,8 +182,10 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
     }
     // column blocks: units become ready in raster order, so each chunk
     // completes a contiguous unit range of its sensor.  Blocks are numbered in
-    // readout order (chunk index major, sensor minor): the order in which the
-    // frame loop accumulates them.
+    // readout order, the order in which every path accumulates them: sensors
+    // are read out in parallel over the same frame time, so chunk c of a sensor
+    // cut into n chunks arrives at (c + 1) / n of the readout; steps are sorted
+    // by that fraction, then by sensor.
     int spad = 0;
     int64_t base = 0;
     const int n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
@@ -204,12 +206,22 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         }
         if (next != nu) return RTC_E_INVAL;
     }
-    for (int c = 0; c < max_chunks; ++c) {
-        for (int w = 0; w < (int)I->wfs.size(); ++w) {
+    std::vector<std::pair<int, int>> order;      // (sensor, chunk) in readout order
+    for (int w = 0; w < (int)I->wfs.size(); ++w)
+        for (int c = 0; c < I->wfs[w].d.n_chunks; ++c) order.push_back({w, c});
+    std::stable_sort(order.begin(), order.end(), [&](const std::pair<int, int> &a,
+                                                     const std::pair<int, int> &b) {
+        const int64_t fa = (int64_t)(a.second + 1) * I->wfs[b.first].d.n_chunks;
+        const int64_t fb = (int64_t)(b.second + 1) * I->wfs[a.first].d.n_chunks;
+        return fa != fb ? fa < fb : a.first < b.first;
+    });
+    (void)max_chunks;
+    for (const auto &wc : order) {
+        {
+            const int w = wc.first, c = wc.second;
             WfsState &S = I->wfs[w];
-            if (c >= S.d.n_chunks) continue;
             const int next = ranges[w][c].first, end = ranges[w][c].second;
-            I->steps.push_back(Step{w, c, end > next ? (int)I->kb.size() : -1, 0});
+            I->steps.push_back(Step{w, c, end > next ? (int)I->kb.size() : -1, 0, 0, 0, 0, 0});
             if (end == next) continue;
             KBlock K{};
             K.k0 = 2 * (S.u0 + next);
@@ -354,9 +366,13 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     HIP_TRY(hipMemcpy(I->d_scale, one_scale.data(), I->n_act * 4, hipMemcpyHostToDevice));
     // serving buffers
     for (auto &S : I->wfs) {
-        const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
-        TRY(dev_alloc(e, &S.d_ring, fpx * e->ring_depth));
-        TRY(host_pinned(e, &S.h_stage, fpx * e->ring_depth + 2));   // + slack for word loads
+        // the persistent serving loop pads rows to 16 bytes so that every chunk
+        // is a whole number of 16-byte units; the per-launch path packs rows
+        S.pitch16 = (S.d.frame_w + 7) & ~7;
+        S.slot16 = (size_t)S.d.frame_h * S.pitch16;
+        S.ring_elems = S.slot16 * e->ring_depth + 8;   // + slack for word loads
+        TRY(dev_alloc(e, &S.d_ring, S.ring_elems));
+        TRY(host_pinned(e, &S.h_stage, S.ring_elems));
     }
     TRY(host_pinned(e, &I->h_mail, (size_t)e->ring_depth * I->n_act));
     I->slots.resize(e->ring_depth);
@@ -591,6 +607,8 @@ rtc_status rtc_destroy(rtc_engine *e) {
     for (Instance *I : e->inst) {
         for (auto &sl : I->slots)
             if (sl.done) (void)hipEventDestroy(sl.done);
+        if (!I->mvm_ev.empty()) (void)hipDeviceSynchronize();   // timer events on user streams
+        for (hipEvent_t ev : I->mvm_ev) (void)hipEventDestroy(ev);
         delete I;
     }
     for (auto &b : e->allocs) (void)hipFree(b.p);
@@ -846,9 +864,13 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         float c1, g;
         coeffs(I, I->next_frame, &c1, &g);
         settle_params(I, I->next_frame);
+        const bool timed = 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size() &&
+                           I->mvm_ev_count++ % (uint64_t)I->mvm_ev_every == 0;
+        if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
         launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
                    (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart,
                    integrate_epi(I, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr));
+        if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used++ + 1], st));
         enqueue_polc(I, st);
         if (slopes)
             HIP_TRY(hipMemcpyAsync(slopes + (size_t)f * I->n_slopes, I->d_sout, I->n_slopes * 4,
@@ -883,6 +905,46 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     return last_error(e);
 }
 
+rtc_status rtc_mvm_timing(rtc_engine *e, int32_t inst, int32_t capacity, int32_t every) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (e->mode != RTC_MODE_STREAM) return RTC_E_STATE;
+    if (capacity < 0 || capacity > (1 << 20) || every < 1) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    std::lock_guard<std::mutex> lk(I->mu);
+    HIP_TRY(hipDeviceSynchronize());     // no recorded event may still be pending
+    for (hipEvent_t ev : I->mvm_ev) HIP_TRY(hipEventDestroy(ev));
+    I->mvm_ev.clear();
+    I->mvm_ev_used = 0;
+    I->mvm_ev_every = every;
+    I->mvm_ev_count = 0;
+    for (int32_t k = 0; k < 2 * capacity; ++k) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev));
+        I->mvm_ev.push_back(ev);
+    }
+    return RTC_OK;
+}
+
+rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *total_ms) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (e->mode != RTC_MODE_STREAM) return RTC_E_STATE;
+    HIP_TRY(hipSetDevice(e->device));
+    std::lock_guard<std::mutex> lk(I->mu);
+    double tot = 0.0;
+    if (I->mvm_ev_used > 0) HIP_TRY(hipEventSynchronize(I->mvm_ev[2 * I->mvm_ev_used - 1]));
+    for (size_t k = 0; k < I->mvm_ev_used; ++k) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, I->mvm_ev[2 * k], I->mvm_ev[2 * k + 1]));
+        tot += ms;
+    }
+    if (n) *n = (int32_t)I->mvm_ev_used;
+    if (total_ms) *total_ms = tot;
+    I->mvm_ev_used = 0;
+    return RTC_OK;
+}
+
 rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames) {
     if (e == nullptr) return RTC_E_INVAL;
     if (e->mode != RTC_MODE_PERSISTENT || e->pe.running) return RTC_E_STATE;
@@ -903,6 +965,7 @@ rtc_status rtc_trace_read(rtc_engine *e, uint64_t *out, int64_t capacity, int32_
     if (out == nullptr || n == 0) return RTC_OK;
     if (capacity < n) return RTC_E_INVAL;
     HIP_TRY(hipSetDevice(e->device));
+    TRY(persist_quiesce(e));             // a serving loop never ends on its own soon
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(out, e->pe.trace, (size_t)n * 8, hipMemcpyDeviceToHost));
     return RTC_OK;

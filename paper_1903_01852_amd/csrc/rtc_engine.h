@@ -43,6 +43,9 @@ struct WfsState {
     int next_chunk = 0;
     uint16_t *d_ring = nullptr;    // ring_depth frames on the device
     uint16_t *h_stage = nullptr;   // pinned staging ring (ring_depth frames)
+    size_t ring_elems = 0;         // uint16 in each ring
+    int pitch16 = 0;               // persistent serving: row pitch (uint16), rows padded to 16 B
+    size_t slot16 = 0;             // persistent serving: uint16 per ring slot
 };
 
 struct FrameSlot {
@@ -60,12 +63,15 @@ struct PersistInstState {
     // per-launch path's)
     float *spad_x[rtc::kDepth - 1] = {}, *ypart_x[rtc::kDepth - 1] = {},
           *ppart_x[rtc::kDepth - 1] = {};
-    float *yacc = nullptr;
+    float *bsum = nullptr;         // serving block sums [kDepth][n_kb][n_act]
     uint64_t *ctr = nullptr;       // every frame-loop counter, zeroed on reset
     size_t n_ctr = 0;
     uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
     uint64_t *kbt_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
+    uint64_t *blk_cnt = nullptr;
     int n_cen_all = 0;             // centroid tasks of a frame
+    int n_ing_all = 0;             // ingest pieces of a frame (serving)
+    uint64_t *ing_cnt = nullptr;   // [kDepth][n_steps] ingest counters
     uint64_t *db_mirror = nullptr, *drop_mirror = nullptr;
     ParamBlock *param_mirror = nullptr;
     KbWork *kbw = nullptr;
@@ -90,6 +96,10 @@ struct PersistInstState {
 
 struct Instance {
     rtc_instance_desc d{};
+    std::vector<hipEvent_t> mvm_ev;    // MVM timer: event pairs (rtc_mvm_timing)
+    size_t mvm_ev_used = 0;            // pairs recorded
+    int mvm_ev_every = 1;              // time every n-th frame
+    uint64_t mvm_ev_count = 0;         // frames since the timer was set
     std::vector<WfsState> wfs;
     int n_units = 0, n_slopes = 0, n_act = 0, n_sh = 0, n_pyr = 0;
     int mask_words = 0;

@@ -71,8 +71,14 @@ struct KBlock {
 // One (sensor, chunk) of the readout order and the column block it completes
 // (-1 when the chunk completes no unit).
 struct Step {
-    int32_t wfs, chunk, kb, r;
+    int32_t wfs, chunk, kb;
+    // serving ingest: the chunk's rows of a ring slot are 16-byte units
+    // [u0, u0 + n16) (rows are padded to 16 bytes), copied host -> device in
+    // pieces of kIngestUnits; its pieces are [ing0, ing0 + ing_n) of the
+    // frame's piece list
+    int32_t u0, n16, ing0, ing_n, r;
 };
+constexpr int kIngestUnits = 512;                 // 16-byte units per ingest piece (8 KiB)
 
 // A segment is the part of one column block that one wavefront streams for a
 // tile: vectors [v0, v0 + nv) of block kb.  Each segment owns one partial
@@ -175,7 +181,8 @@ struct PersistInst {
     float *s_pad[kDepth];          // frame q uses buffer q % kDepth
     float *y_part[kDepth];
     float *p_part[kDepth];
-    float *y_acc, *p;
+    float *bsum;                   // serving: [kDepth][n_kb][n_act] block sums
+    float *p;
     float *a;                      // two command buffers of a_stride floats (frame parity)
     int32_t a_stride, r4;
     // counters, one kCtrSlot-sized slot each; [kDepth]: by q % kDepth
@@ -183,7 +190,8 @@ struct PersistInst {
     uint64_t *tile_fan;            // [kDepth] fan-in: tiles whose commands are out
     uint64_t *pol_fan;             // [kDepth] fan-in: tiles whose POLC term is formed
     uint64_t *kbt_cnt;             // [kDepth][n_kb][n_tiles] partials of a block on a tile
-    uint64_t *join;                // [kDepth][n_kb][n_tiles] accumulation joins
+    uint64_t *join;                // [kDepth][n_tiles] accumulation joins
+    uint64_t *blk_cnt;             // [kDepth][n_tiles] serving: block sums of a tile
     uint64_t *pol_cnt;             // [kDepth][n_tiles] POLC partials of a tile
     uint64_t *p_done;              // [n_tiles] q + 1 of the last POLC term reduced
     uint64_t *db_mirror;           // device copy of the doorbells, per sensor
@@ -191,8 +199,13 @@ struct PersistInst {
     // frame source
     int32_t serving;
     int32_t ring_depth;
-    const uint16_t *src[RTC_MAX_WFS];      // serving: pinned ring; batch: device frames
-    int64_t src_stride[RTC_MAX_WFS];       // uint16 per frame
+    const uint16_t *src[RTC_MAX_WFS];      // serving: device ring; batch: device frames
+    int64_t src_stride[RTC_MAX_WFS];       // uint16 per frame (ring slot)
+    int32_t src_pitch[RTC_MAX_WFS];        // uint16 per row
+    const uint16_t *ring_host[RTC_MAX_WFS];  // serving: the pinned ring the host fills
+    uint64_t ring_bytes[RTC_MAX_WFS];      // size of each pinned ring
+    uint64_t *ing_cnt;                     // [kDepth][n_steps] ingest pieces copied
+    int32_t n_ing_all, r6;                 // ingest pieces of a frame
     const uint64_t *doorbell;              // pinned, per sensor: (q << 20) | chunks
     const uint64_t *drop_host;             // pinned, per slot: q + 1 of a dropped frame
     const ParamBlock *params;              // serving (pinned)
@@ -241,8 +254,8 @@ constexpr int kFanStripes = 32;
 constexpr int kFanSlots = kFanStripes + 1;        // stripes, then the top
 
 void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args);
-void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_kb,
-                          int n_tiles, int par, int polc, int serving);
+void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_tiles,
+                          int par, int polc);
 int frame_loop_max_blocks_per_cu();
 
 // Launchers (defined in rtc_kernels.hip).

@@ -106,19 +106,6 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
     return dq > q || (dq == q && (db & kDbChunkMask) >= chunks);
 }
 
-// Wait for chunk `chunk` of frame q of sensor w (serving instances).  Only a
-// stop request ends this wait: the sentinel turns a long idle period into one.
-__device__ bool wait_chunk(InstRef I, ArgsRef A, int w, uint64_t q,
-                           int chunk) {
-    const uint64_t *m = I.db_mirror + w;
-    if (db_reached(ld_agent64(m), q, chunk + 1)) return true;
-    for (uint32_t it = 1;; ++it) {
-        __builtin_amdgcn_s_sleep(1);
-        if (db_reached(ld_agent64(m), q, chunk + 1)) return true;
-        if ((it & 31) == 0 && stopping(A)) return false;
-    }
-}
-
 // Stage n floats written by other wavefronts of this kernel into this
 // wavefront's LDS slice (two floats per agent-scope atomic load).
 __device__ __forceinline__ void stage_lds(RTC_LDS float *lds, const float *src, int n, int lane) {
@@ -378,33 +365,34 @@ __device__ void sentinel(InstRef I, ArgsRef A, int lane) {
 }
 
 // ---------------------------------------------------------------------------
-// Accumulation as joins.  A tile's commands for frame q need (E) its
-// partials, (A) the tile's commands of frame q - 1 (the integrator reads
-// them, and the sums must follow frame order) and, with POLC, (P) its POLC
-// term.  Each party adds one to a join counter; the party that completes the
-// count does the work, so nobody waits, and then arrives as the (A) party of
-// what follows.  Join counters are doubled by frame parity like the arrival
-// counters; the launch pre-counts the (A) and (P) parts of its first frame.
+// Accumulation as a join.  A tile's commands for frame q need (E) its
+// reconstruction sum, (A) the tile's commands of frame q - 1 (the integrator
+// reads them, and frames must be integrated in order) and, with POLC, (P) its
+// POLC term.  Each party adds one to the tile's join counter; the party that
+// completes the count does the work, so nobody waits, and then arrives as the
+// (A) party of the next frame.  Join counters exist kDepth times like the
+// arrival counters; the launch pre-counts the (A) and (P) parts of its first
+// frame.
 //
-// Serving accumulates block by block as the chunks arrive: join (q, kb, t)
-// gathers block kb's partials (E) and the accumulation of block kb - 1 (A),
-// and for the last block also P, so that only the last block's sum is left
-// once the last chunk is in.  Batch has every chunk at once: join (q, 0, t)
-// gathers all of the tile's partials (E), the tile's frame q - 1 (A) and P,
-// and one wavefront sums the blocks in readout order in one pass.
-__device__ __forceinline__ uint64_t join_need(InstRef I, int kb) {
-    if (!I.serving) return I.polc ? 3 : 2;
-    return (I.polc && kb == I.n_kb - 1) ? 3 : 2;
+// The sum is over the column blocks in readout order, each block's segment
+// partials in order: y = ((B_0 + B_1) + B_2) + ... with B_k = ((0 + p_0) + p_1)
+// + ...  Batch has every partial at once, so the wavefront completing a tile's
+// partials is its (E) party and sums them in one pass.  Serving gets blocks
+// over the readout: the last partial of block k on a tile forms B_k at once
+// (blocks in parallel, whatever their order of arrival), and the wavefront
+// completing the tile's block sums is its (E) party and adds them in order.
+__device__ __forceinline__ uint64_t join_need(InstRef I) {
+    return I.polc ? 3 : 2;
 }
-__device__ __forceinline__ uint64_t *join_ctr(InstRef I, uint64_t q, int kb, int t) {
-    return slot(I.join, ((size_t)dslot(q) * I.n_kb + kb) * I.n_tiles + t);
+__device__ __forceinline__ uint64_t *join_ctr(InstRef I, uint64_t q, int t) {
+    return slot(I.join, (size_t)dslot(q) * I.n_tiles + t);
 }
-// True when this wavefront's arrival completes the join of (q, kb, t).
-__device__ __forceinline__ bool join(InstRef I, uint64_t q, int kb, int t, int lane) {
+// True when this wavefront's arrival completes the join of (q, t).
+__device__ __forceinline__ bool join(InstRef I, uint64_t q, int t, int lane) {
     uint64_t old = 0;
-    if (lane == 0) old = add_agent64(join_ctr(I, q, kb, t), 1);
+    if (lane == 0) old = add_agent64(join_ctr(I, q, t), 1);
     old = __shfl(old, 0, kWave);
-    return (old + 1) % join_need(I, kb) == 0;
+    return (old + 1) % join_need(I) == 0;
 }
 
 // Commands of tile t for frame q from the reconstruction sum y of row r: the
@@ -437,61 +425,44 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
     }
 }
 
-// Serving: accumulate block kb of frame q into tile t, then every following
-// block whose join this completes.  Blocks are added in readout order, each
-// block's segments in order: the arithmetic of the per-launch epilogue.
-// Returns the number of blocks accumulated.
-__device__ int run_chain(InstRef I, uint64_t q, int kb, int t, int lane) {
-    const int nr = min(kTileRows, I.n_act - t * kTileRows);
-    const int r = t * kTileRows + lane;
-    for (int done = 1;; ++done) {
-        const bool last_block = kb == I.n_kb - 1;
-        float y = 0.0f;
-        if (lane < nr) {
-            const int2 sb = ldc(I.kb_segs + kb);
-            y = kb == 0 ? 0.0f : load_agent(I.y_acc + r);
-            y += sum_parts(I.y_part[dslot(q)], sb.x, sb.y, I.n_act, r);
-            if (!last_block) st_agent(I.y_acc + r, y);
-        }
-        if (last_block) {
-            tile_commands(I, q, t, r, lane < nr, y, lane);
-            ++q;
-            kb = 0;
-        } else {
-            drain();
-            ++kb;
-        }
-        if (!join(I, q, kb, t, lane)) return done;
-    }
-}
-
-// Sum of every partial of row r of frame q's buffer, block by block in
-// readout order and each block's segments in order, up to kSumBatch loads in
-// flight.
+// Values [0, n) of row r of a [value][row] array, summed in that order with
+// up to kSumBatch loads in flight, as the blocks of a tile: a value ends block
+// kb when its index + 1 is the block's end (blk_end(kb)), and blocks are added
+// in order.  Batch: the values are segment partials; serving: block sums (one
+// value per block).
 constexpr int kSumBatch = 16;
-__device__ float sum_tile(InstRef I, const float *part, int r) {
-    const int n_seg = I.n_seg, n_kb = I.n_kb, n_act = I.n_act;
+template <bool BLOCKS>
+__device__ float sum_tile(InstRef I, const float *vals, int r) {
+    const int n_kb = I.n_kb, n_act = I.n_act;
+    const int n = BLOCKS ? n_kb : (int)I.n_seg;
     const int2 *kb_segs = I.kb_segs;
     float y = 0.0f, blk = 0.0f;
     int kb = 0;
-    int2 sb = ldc(kb_segs);
-    int blk_end = sb.x + sb.y;
-    for (int s0 = 0; s0 < n_seg; s0 += kSumBatch) {
+    int blk_end = 1;
+    if (!BLOCKS) {
+        const int2 sb = ldc(kb_segs);
+        blk_end = sb.x + sb.y;
+    }
+    for (int s0 = 0; s0 < n; s0 += kSumBatch) {
         float v[kSumBatch];
 #pragma unroll
         for (int u = 0; u < kSumBatch; ++u)
-            v[u] = s0 + u < n_seg ? load_agent(part + (size_t)(s0 + u) * n_act + r) : 0.0f;
+            v[u] = s0 + u < n ? load_agent(vals + (size_t)(s0 + u) * n_act + r) : 0.0f;
 #pragma unroll
         for (int u = 0; u < kSumBatch; ++u) {
             const int sg = s0 + u;
-            if (sg < n_seg) {
+            if (sg < n) {
                 blk += v[u];
                 if (sg + 1 == blk_end) {
                     y = kb == 0 ? blk : y + blk;
                     blk = 0.0f;
                     if (++kb < n_kb) {
-                        sb = ldc(kb_segs + kb);
-                        blk_end = sb.x + sb.y;
+                        if (BLOCKS) {
+                            blk_end = kb + 1;
+                        } else {
+                            const int2 sb = ldc(kb_segs + kb);
+                            blk_end = sb.x + sb.y;
+                        }
                     }
                 }
             }
@@ -500,24 +471,26 @@ __device__ float sum_tile(InstRef I, const float *part, int r) {
     return y;
 }
 
-// Batch: commands of tile t for frame q, then of every following frame whose
-// join this completes.  Returns the number of frames done.
+// Commands of tile t for frame q, then of every following frame whose join
+// this completes.  Returns the number of frames done.
 __device__ int finish_chain(InstRef I, uint64_t q, int t, int lane) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
     for (int done = 1;; ++done) {
-        const float y = lane < nr ? sum_tile(I, I.y_part[dslot(q)], r) : 0.0f;
+        float y = 0.0f;
+        if (lane < nr)
+            y = I.serving ? sum_tile<true>(I, I.bsum + (size_t)dslot(q) * I.n_kb * I.n_act, r)
+                          : sum_tile<false>(I, I.y_part[dslot(q)], r);
         tile_commands(I, q, t, r, lane < nr, y, lane);
         ++q;
-        if (q >= I.q_end || !join(I, q, 0, t, lane)) return done;
+        if (q >= I.q_end || !join(I, q, t, lane)) return done;
     }
 }
 
 // The accumulation a completed join starts, timed into the frame's record.
-__device__ __forceinline__ void accumulate(InstRef I, uint64_t q, int kb, int t, int lane,
-                                           Trace &tr) {
+__device__ __forceinline__ void accumulate(InstRef I, uint64_t q, int t, int lane, Trace &tr) {
     const uint64_t t0 = tr.rec != nullptr ? wall_clock64() : 0;
-    const int n = I.serving ? run_chain(I, q, kb, t, lane) : finish_chain(I, q, t, lane);
+    const int n = finish_chain(I, q, t, lane);
     if (tr.rec != nullptr) {
         tr.chain_ticks += wall_clock64() - t0;
         tr.chain_blocks += (uint64_t)n;
@@ -572,10 +545,7 @@ __device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
         if (all && I.serving && lane == 0)
             __hip_atomic_store(gbl(I.pol_seq), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         // (P) party of frame q + 1 on this tile
-        if (q + 1 < I.q_end) {
-            const int kb = I.serving ? I.n_kb - 1 : 0;
-            if (join(I, q + 1, kb, t, lane)) accumulate(I, q + 1, kb, t, lane, tr);
-        }
+        if (q + 1 < I.q_end && join(I, q + 1, t, lane)) accumulate(I, q + 1, t, lane, tr);
     }
     return true;
 }
@@ -603,7 +573,8 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
     const int end = W.cen_base + W.n_cen;
     if (j >= end) return;
     const uint16_t *fr = frame_src(I, W.wfs, q);
-    const WfsParam P = ldc(I.wp + W.wfs);
+    WfsParam P = ldc(I.wp + W.wfs);
+    P.W = I.src_pitch[W.wfs];            // row pitch of the frame source
     for (; j < end; j += nw) {
         const int jc = j - W.cen_base;
         if (stripe_lane(global_idx ? j : jc, lane)) ++cnt;
@@ -611,7 +582,7 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
             const int u = W.cu0 + jc;
             const ShUnit d = ldc(I.sh + u);
             if (I.serving)
-                sh_unit<STORE_AGENT, LOAD_SYSTEM>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
+                sh_unit<STORE_AGENT, LOAD_AGENT>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
                                                   I.sh_bg, I.ref, so, lane);
             else
                 sh_unit<STORE_AGENT, LOAD_PLAIN>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
@@ -621,7 +592,7 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
             if (k < W.cu1) {
                 const PyrUnit d = ldg(I.py + k);
                 if (I.serving)
-                    pyr_unit<STORE_AGENT, LOAD_SYSTEM>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
+                    pyr_unit<STORE_AGENT, LOAD_AGENT>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
                                                        I.py_dark, I.py_flat, I.py_bg, I.ref, so);
                 else
                     pyr_unit<STORE_AGENT, LOAD_PLAIN>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
@@ -635,7 +606,7 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
 // the block's slopes must be complete.  A tile's last partial joins its
 // accumulation (serving: of the block; batch: of the whole frame).
 __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw, int lane,
-                          RTC_LDS float *lds, int &m, Trace &tr) {
+                          RTC_LDS float *lds, int &m, Trace &tr, int budget = 1 << 30) {
     const int n_tiles = I.n_tiles;
     const int end = W.mvm_base + W.nseg * n_tiles;
     if (m >= end) return;
@@ -645,7 +616,7 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
     const int E = vec_elems(I.dtype);
     const KBlock K = ldc(I.kbs + kb);
     int staged = -1;
-    for (; m < end; m += nw) {
+    for (; m < end && budget > 0; m += nw, --budget) {
         const int jm = m - W.mvm_base;
         const int sl = jm / n_tiles;
         const int t = jm - sl * n_tiles;
@@ -666,9 +637,23 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
         if (lane == 0)
             old = add_agent64(slot(I.kbt_cnt, ((size_t)dslot(q) * I.n_kb + jkb) * I.n_tiles + t), 1);
         old = __shfl(old, 0, kWave);
-        // (E) party: the last partial on this tile
-        if (old + 1 == par_target(I, q, need) && join(I, q, jkb, t, lane))
-            accumulate(I, q, jkb, t, lane, tr);
+        if (old + 1 != par_target(I, q, need)) continue;
+        if (I.serving) {
+            // the block's last partial on this tile: its block sum
+            const int r = t * kTileRows + lane;
+            if (lane < nr) {
+                const int2 sb = ldc(I.kb_segs + kb);
+                st_agent(I.bsum + ((size_t)dslot(q) * I.n_kb + kb) * I.n_act + r,
+                         sum_parts(I.y_part[dslot(q)], sb.x, sb.y, I.n_act, r));
+            }
+            drain();
+            uint64_t ob = 0;
+            if (lane == 0) ob = add_agent64(slot(I.blk_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
+            ob = __shfl(ob, 0, kWave);
+            if (ob + 1 != par_target(I, q, (uint64_t)I.n_kb)) continue;
+        }
+        // (E) party: the tile's reconstruction sum is ready
+        if (join(I, q, t, lane)) accumulate(I, q, t, lane, tr);
     }
     lds_done();
     tr.stamp(RTC_TRACE_MVM_LAST, lane);
@@ -695,8 +680,60 @@ __device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
                     A, A.dep_watchdog);
 }
 
-// Serving worker: column blocks in readout order, each as soon as its chunk
-// is delivered, with a fan-in barrier per block.
+// Serving ingest: copy this worker's pieces of readout step `st` (frame q)
+// from the pinned host ring into the device ring, then count them.  Loads are
+// 16-byte system-coherent buffer loads (the host refills ring slots while the
+// loop runs, and per-pixel loads across PCIe are limited by the request rate,
+// not the bytes); stores are 16-byte agent-coherent, so wavefronts on any XCD
+// read the new frame.  Buffer accesses are range-checked against each ring.
+constexpr int kIngestPerLane = kIngestUnits / kWave;
+__device__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int nw, int lane,
+                             int &j) {
+    const int end = S.ing0 + S.ing_n;
+    if (j >= end) return;
+    const int w = S.wfs;
+    const uint32_t nrec = (uint32_t)I.ring_bytes[w];
+    __amdgpu_buffer_rsrc_t hsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void *)I.ring_host[w], (short)0, (int)nrec, 0x00020000);
+    __amdgpu_buffer_rsrc_t ddst =
+        __builtin_amdgcn_make_buffer_rsrc((void *)I.src[w], (short)0, (int)nrec, 0x00020000);
+    const uint32_t base =
+        (uint32_t)((q % (uint64_t)I.ring_depth) * (uint64_t)I.src_stride[w] / 8) + (uint32_t)S.u0;
+    constexpr int kSys = 1 | 16, kAgent = 16;   // cache policy: sc0 sc1, sc1
+    uint64_t cnt = 0;
+    for (; j < end; j += nw, ++cnt) {
+        const int u0 = (j - S.ing0) * kIngestUnits;
+        const int u1 = min(S.n16, u0 + kIngestUnits);
+        vec16_t v[kIngestPerLane];
+#pragma unroll
+        for (int k = 0; k < kIngestPerLane; ++k) {
+            const int u = u0 + k * kWave + lane;
+            if (u < u1) v[k] = __builtin_amdgcn_raw_buffer_load_b128(hsrc, (base + u) * 16, 0, kSys);
+        }
+#pragma unroll
+        for (int k = 0; k < kIngestPerLane; ++k) {
+            const int u = u0 + k * kWave + lane;
+            if (u < u1) __builtin_amdgcn_raw_buffer_store_b128(v[k], ddst, (base + u) * 16, 0, kAgent);
+        }
+    }
+    drain();
+    if (lane == 0) add_agent64(slot(I.ing_cnt, (size_t)dslot(q) * I.n_steps + st), cnt);
+}
+
+// Serving worker: a small scheduler over the frame's readout steps with one
+// cursor per kind of work, in priority order.  Ingest: copy its pieces of
+// every chunk whose doorbell has rung.  Slopes: form its slopes of every step
+// whose chunks (this one and all before it, as a unit's rows may span two
+// chunks) are in device memory; they feed the blocks' barriers, which every
+// worker's MVM tasks wait for.  MVM: run one task of the oldest block whose
+// barrier has completed, then look again.  It never blocks on a barrier while
+// earlier-stage work is available, so no worker holds up a block that others
+// wait on, and the steps of a frame (about a hundred for six laser guide
+// stars) pipeline instead of queueing behind each other.
+__device__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb) {
+    return ld_agent64(fan_top(fan_grp(I.cen_fan, q, I.n_kb, kb))) >= fan_target(I, q, W.n_cen);
+}
+
 __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                                RTC_LDS float *lds) {
     for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
@@ -707,27 +744,75 @@ __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, 
         tr.stamp(RTC_TRACE_GATE, lane);
         const SlopeOut so{I.s_pad[dslot(q)], nullptr, nullptr, nullptr};
         FrameTasks ft = frame_tasks(I, q, rank, nw);
+        int ing = first_task(rank, nw, rot(q, I.n_ing_all, nw));
         const int n_steps = I.n_steps, n_tiles = I.n_tiles;
-        for (int st = 0; st < n_steps; ++st) {
-            const Step S = ldc(I.steps + st);
-            if (S.kb < 0) continue;
-            const KbWork W = ldc(I.kbw + S.kb);
-            const bool any_cen = ft.cen < W.cen_base + W.n_cen;
-            const bool any_mvm = ft.mvm < W.mvm_base + W.nseg * n_tiles;
-            if (!any_cen && !any_mvm) continue;
-            if (!wait_chunk(I, A, S.wfs, q, S.chunk)) return;
-            if (any_cen) {
-                uint32_t cnt = 0;
-                centroid_tasks(I, q, W, nw, lane, so, false, ft.cen, cnt);
-                drain();
-                (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt, lane);
+        int is = 0, ic = 0, cs = 0, ms = 0;   // next step to ingest, known ingested, slopes, MVM
+        uint32_t idle = 0;
+        while (is < n_steps || cs < n_steps || ms < n_steps) {
+            bool progressed = false;
+            // ingest of every delivered chunk
+            while (is < n_steps) {
+                const Step S = ldc(I.steps + is);
+                if (ing < S.ing0 + S.ing_n) {
+                    if (!db_reached(ld_agent64(I.db_mirror + S.wfs), q, (uint64_t)S.chunk + 1))
+                        break;
+                    ingest_tasks(I, q, S, is, nw, lane, ing);
+                    progressed = true;
+                }
+                ++is;
             }
-            tr.stamp(RTC_TRACE_CENTROIDS, lane);
-            if (any_mvm) {
-                if (!wait_geq(fan_top(fan_grp(I.cen_fan, q, I.n_kb, S.kb)),
-                              fan_target(I, q, W.n_cen), A, A.dep_watchdog))
-                    return;
-                mvm_tasks(I, q, W, S.kb, nw, lane, lds, ft.mvm, tr);
+            // slopes of every step whose chunks are all in device memory
+            while (cs < n_steps) {
+                const Step S = ldc(I.steps + cs);
+                if (S.kb < 0) {
+                    ++cs;
+                    continue;
+                }
+                const KbWork W = ldc(I.kbw + S.kb);
+                if (ft.cen < W.cen_base + W.n_cen) {
+                    while (ic <= cs) {
+                        const Step T = ldc(I.steps + ic);
+                        if (ld_agent64(slot(I.ing_cnt, (size_t)dslot(q) * n_steps + ic)) <
+                            par_target(I, q, (uint64_t)T.ing_n))
+                            break;
+                        ++ic;
+                    }
+                    if (ic <= cs) break;
+                    uint32_t cnt = 0;
+                    centroid_tasks(I, q, W, nw, lane, so, false, ft.cen, cnt);
+                    drain();
+                    (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt,
+                                     lane);
+                    tr.stamp(RTC_TRACE_CENTROIDS, lane);
+                    progressed = true;
+                }
+                ++cs;
+            }
+            // one MVM task of the oldest block with this worker's tasks left
+            while (ms < n_steps) {
+                const Step S = ldc(I.steps + ms);
+                if (S.kb < 0) {
+                    ++ms;
+                    continue;
+                }
+                const KbWork W = ldc(I.kbw + S.kb);
+                const int end = W.mvm_base + W.nseg * n_tiles;
+                if (ft.mvm >= end) {
+                    ++ms;
+                    continue;
+                }
+                if (block_ready(I, q, W, S.kb)) {
+                    mvm_tasks(I, q, W, S.kb, nw, lane, lds, ft.mvm, tr, 1);
+                    if (ft.mvm >= end) ++ms;
+                    progressed = true;
+                }
+                break;
+            }
+            if (progressed) {
+                idle = 0;
+            } else {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++idle & 31) == 0 && stopping(A)) return;
             }
         }
         if (I.polc && !polc_tasks(I, A, q, rank, nw, lane, lds, tr)) return;
@@ -737,7 +822,7 @@ __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, 
 
 // Batch: this worker's centroid tasks of frame q (every block; one barrier
 // for the frame).  False when the loop must exit.
-__device__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane,
+__device__ __forceinline__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane,
                                 Trace &tr) {
     tr.stamp(RTC_TRACE_FRAME_START, lane);
     if (!gate(I, A, q)) return false;
@@ -759,19 +844,27 @@ __device__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q, int rank, int 
 // Batch worker: every pixel is already in device memory, so the loop is
 // software-pipelined over frames.  Iteration q forms the slopes of frame
 // q + 1, multiplies frame q (whose slopes were finished one iteration
-// earlier, so its barrier is normally already passed) and forms the POLC
-// term of frame q from a_{q-1}.  Every wait of iteration q is on work that
-// each worker did in an earlier iteration.
+// earlier) and forms the POLC term of frame q from a_{q-1}.  The gate of frame
+// q + 1 is frame q + 1 - kDepth, multiplied kDepth - 1 iterations earlier, so
+// workers may drift apart by about an iteration without waiting (slopes two
+// frames ahead would gate on the frame multiplied just before, which measured
+// slower).  Every wait of iteration q is on work each worker did in an earlier
+// iteration, so the loop cannot deadlock.
 __device__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                              RTC_LDS float *lds) {
-    Trace tc = trace_of(I, A, I.q_begin, wid);
-    if (!batch_centroids(I, A, I.q_begin, rank, nw, lane, tc)) return;
-    for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
+    constexpr int kAhead = 1;
+    const uint64_t q0 = I.q_begin, q1 = I.q_end;
+    for (uint64_t c = q0; c < q0 + kAhead && c < q1; ++c) {
+        Trace tc = trace_of(I, A, c, wid);
+        if (!batch_centroids(I, A, c, rank, nw, lane, tc)) return;
+    }
+    Trace tp;
+    for (uint64_t q = q0; q < q1; ++q) {
         if (stopping(A)) return;
         Trace tr = trace_of(I, A, q, wid);
-        if (q + 1 < I.q_end) {
-            Trace tn = trace_of(I, A, q + 1, wid);
-            if (!batch_centroids(I, A, q + 1, rank, nw, lane, tn)) return;
+        if (q + kAhead < q1) {
+            Trace tn = trace_of(I, A, q + kAhead, wid);
+            if (!batch_centroids(I, A, q + kAhead, rank, nw, lane, tn)) return;
         }
         if (!wait_geq(fan_top(fan_grp(I.cen_fan, q, I.n_kb, 0)), fan_target(I, q, I.n_cen_all), A,
                       A.dep_watchdog))
@@ -780,10 +873,10 @@ __device__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, in
         const int n_kb = I.n_kb, n_all = I.n_seg * I.n_tiles;
         for (int kb = 0; kb < n_kb && m < n_all; ++kb)
             mvm_tasks(I, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr);
-        if (I.polc && q > I.q_begin && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
+        if (I.polc && q > q0 && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
         trace_end(tr, lane);
     }
-    if (I.polc && !polc_tasks(I, A, I.q_end - 1, rank, nw, lane, lds, tc)) return;
+    if (I.polc && !polc_tasks(I, A, q1 - 1, rank, nw, lane, lds, tp)) return;
 }
 
 }  // namespace
@@ -815,30 +908,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
 // Counters of one instance at the start of a launch: zero, except the joins
 // of the first frame (copy par), which find their (A) part, and with POLC
 // their (P) part, already counted.
-__global__ void k_seed_counters(uint64_t *ctr, size_t n, size_t join_off, int n_kb, int n_tiles,
-                                int par, int polc, int serving) {
-    const size_t join_end = join_off + (size_t)kDepth * n_kb * n_tiles * kCtrSlot;
+__global__ void k_seed_counters(uint64_t *ctr, size_t n, size_t join_off, int n_tiles, int par,
+                                int polc) {
+    const size_t join_end = join_off + (size_t)kDepth * n_tiles * kCtrSlot;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
         uint64_t v = 0;
-        if (i >= join_off && i < join_end && (i - join_off) % kCtrSlot == 0) {
-            const size_t sl = (i - join_off) / kCtrSlot;
-            const int p = (int)(sl / ((size_t)n_kb * n_tiles));
-            const int kb = (int)((sl / n_tiles) % n_kb);
-            if (p == par) {
-                if (kb == 0) v += 1;
-                if (polc && kb == (serving ? n_kb - 1 : 0)) v += 1;
-            }
-        }
+        if (i >= join_off && i < join_end && (i - join_off) % kCtrSlot == 0 &&
+            (int)((i - join_off) / kCtrSlot / n_tiles) == par)
+            v = polc ? 2 : 1;
         gbl(ctr)[i] = v;
     }
 }
 
-void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_kb,
-                          int n_tiles, int par, int polc, int serving) {
+void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_tiles,
+                          int par, int polc) {
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_seed_counters, dim3(blocks), dim3(256), 0, st, ctr, n, join_off, n_kb,
-                       n_tiles, par, polc, serving);
+    hipLaunchKernelGGL(k_seed_counters, dim3(blocks), dim3(256), 0, st, ctr, n, join_off, n_tiles,
+                       par, polc);
 }
 
 void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args) {

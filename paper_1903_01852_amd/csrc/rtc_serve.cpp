@@ -53,6 +53,8 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.steps = nullptr;
     d.n_kb = (int)I->kb.size();
     d.n_cen_all = P.n_cen_all;
+    d.n_ing_all = P.n_ing_all;
+    d.ing_cnt = P.ing_cnt;
     d.n_seg = (int)I->seg.size();
     d.n_steps = (int)I->steps.size();
     d.n_wfs = (int)I->wfs.size();
@@ -86,7 +88,8 @@ PersistInst describe(rtc_engine *e, Instance *I) {
         d.y_part[k] = P.ypart_x[k - 1];
         d.p_part[k] = P.ppart_x[k - 1];
     }
-    d.y_acc = P.yacc;
+    d.bsum = P.bsum;
+    d.blk_cnt = P.blk_cnt;
     d.p = I->d_p;
     d.a = I->d_a;
     d.a_stride = I->a_len;
@@ -129,9 +132,8 @@ rtc_status upload_and_launch(rtc_engine *e, const std::vector<Instance *> &insts
     // every launch counts from its first frame
     for (size_t i = 0; i < insts.size(); ++i) {
         const PersistInstState &P = insts[i]->ps;
-        launch_seed_counters(st, P.ctr, P.n_ctr, (size_t)(P.join - P.ctr), (int)insts[i]->kb.size(),
-                             insts[i]->n_tiles, (int)(descs[i].q_begin % kDepth), insts[i]->d.polc,
-                             descs[i].serving);
+        launch_seed_counters(st, P.ctr, P.n_ctr, (size_t)(P.join - P.ctr), insts[i]->n_tiles,
+                             (int)(descs[i].q_begin % kDepth), insts[i]->d.polc);
     }
     PersistInst *dev = pe.d_inst;
     if (!batch) {
@@ -213,8 +215,12 @@ rtc_status launch_serving(rtc_engine *e) {
         d.steps = steps_dev(I);
         d.serving = 1;
         for (size_t s = 0; s < I->wfs.size(); ++s) {
-            d.src[s] = I->wfs[s].h_stage;
-            d.src_stride[s] = (int64_t)I->wfs[s].d.frame_h * I->wfs[s].d.frame_w;
+            const WfsState &S = I->wfs[s];
+            d.src[s] = S.d_ring;
+            d.src_stride[s] = (int64_t)S.slot16;
+            d.src_pitch[s] = S.pitch16;
+            d.ring_host[s] = S.h_stage;
+            d.ring_bytes[s] = (uint64_t)S.ring_elems * 2;
         }
         d.q_begin = load_acquire(I->ps.cmd_seq);   // first frame not yet published
         d.q_end = ~0ull;
@@ -267,12 +273,13 @@ rtc_status persist_alloc(rtc_engine *e) {
             TRY(dev_alloc(e, &P.ppart_x[k],
                           std::max<size_t>(I->segm.size(), 1) * (size_t)I->n_act));
         }
-        TRY(dev_alloc(e, &P.yacc, I->n_act));
+        TRY(dev_alloc(e, &P.bsum, (size_t)kDepth * I->kb.size() * I->n_act));
         // counters, each in a slot of its own; arrival counters kDepth times:
         // fan-in barriers cen [D][nkb], tile [D], pol [D]; kbt_cnt and join
         // [D][nkb][nt]; pol_cnt [D][nt]; p_done [nt] once
-        const size_t fan = kFanSlots, D = kDepth;
-        const size_t n_slots = D * nkb * fan + 2 * D * fan + 2 * D * nkb * nt + D * nt + nt;
+        const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size();
+        const size_t n_slots =
+            D * nkb * fan + 2 * D * fan + D * nkb * nt + D * nt + D * nt + nt + D * nst + D * nt;
         P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_fan = P.ctr;
@@ -280,8 +287,25 @@ rtc_status persist_alloc(rtc_engine *e) {
         P.pol_fan = P.tile_fan + D * fan * kCtrSlot;
         P.kbt_cnt = P.pol_fan + D * fan * kCtrSlot;
         P.join = P.kbt_cnt + D * nkb * nt * kCtrSlot;
-        P.pol_cnt = P.join + D * nkb * nt * kCtrSlot;
+        P.pol_cnt = P.join + D * nt * kCtrSlot;
         P.p_done = P.pol_cnt + D * nt * kCtrSlot;
+        P.ing_cnt = P.p_done + nt * kCtrSlot;
+        P.blk_cnt = P.ing_cnt + D * nst * kCtrSlot;
+        // serving ingest: each readout step's rows as 16-byte units of a ring
+        // slot, in pieces, numbered in readout order; the buffer accesses take
+        // 32-bit byte offsets
+        for (const WfsState &S : I->wfs)
+            if (S.ring_elems * 2 >= (size_t)1 << 31) return RTC_E_INVAL;
+        int ing = 0;
+        for (Step &st : I->steps) {
+            const WfsState &S = I->wfs[st.wfs];
+            st.u0 = S.row0[st.chunk] * S.pitch16 / 8;
+            st.n16 = (S.row0[st.chunk + 1] - S.row0[st.chunk]) * S.pitch16 / 8;
+            st.ing0 = ing;
+            st.ing_n = (st.n16 + kIngestUnits - 1) / kIngestUnits;
+            ing += st.ing_n;
+        }
+        P.n_ing_all = ing;
         TRY(dev_alloc(e, &P.db_mirror, I->wfs.size()));
         TRY(dev_alloc(e, &P.drop_mirror, e->ring_depth));
         TRY(dev_alloc(e, &P.param_mirror, 1));
@@ -498,10 +522,12 @@ rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int
     }
     if (chunk != S.next_chunk) return RTC_E_INVAL;
     const uint64_t q = P.q_cur;
-    const size_t fpx = (size_t)S.d.frame_h * S.d.frame_w;
     const int r0 = S.row0[chunk], r1 = S.row0[chunk + 1];
-    const size_t off = (size_t)(q % (uint64_t)e->ring_depth) * fpx + (size_t)r0 * S.d.frame_w;
-    std::memcpy(S.h_stage + off, rows, (size_t)(r1 - r0) * S.d.frame_w * 2);
+    // rows at the ring's 16-byte pitch
+    uint16_t *dst = S.h_stage + (size_t)(q % (uint64_t)e->ring_depth) * S.slot16;
+    for (int r = r0; r < r1; ++r)
+        std::memcpy(dst + (size_t)r * S.pitch16, rows + (size_t)(r - r0) * S.d.frame_w,
+                    (size_t)S.d.frame_w * 2);
     store_release(P.doorbell + w, db_word(q, (uint64_t)chunk + 1));
     S.next_chunk++;
     I->cur_started = true;
@@ -579,6 +605,7 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
     for (size_t s = 0; s < I->wfs.size(); ++s) {
         d.src[s] = frames[s];
         d.src_stride[s] = frame_stride[s];
+        d.src_pitch[s] = I->wfs[s].d.frame_w;
     }
     d.q_begin = P.seq;
     d.q_end = P.seq + (uint64_t)n_frames;

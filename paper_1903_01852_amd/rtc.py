@@ -29,7 +29,7 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_load_matrices", "rtc_load_calibration", "rtc_set_params", "rtc_get_state",
            "rtc_set_state", "rtc_submit_pixel_chunk", "rtc_wait_commands",
            "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
-           "rtc_trace_enable", "rtc_trace_read")
+           "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -104,6 +104,8 @@ def lib() -> C.CDLL:
         L.rtc_read_slopes.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_read_matrix.argtypes = [vp, i32, vp, vp]
         L.rtc_run_mvm.argtypes = [vp, i32, i32, vp]
+        L.rtc_mvm_timing.argtypes = [vp, i32, i32, i32]
+        L.rtc_mvm_timing_read.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double)]
         L.rtc_trace_enable.argtypes = [vp, i32]
         L.rtc_trace_read.argtypes = [vp, vp, i64, C.POINTER(i32), C.POINTER(i32)]
         for name in EXPORTS:
@@ -213,6 +215,10 @@ class Engine:
         _ok(lib().rtc_get_info(self._h, inst, C.byref(s)), "rtc_get_info")
         return {k: getattr(s, k) for k, _ in InstanceInfoC._fields_}
 
+    def n_chunks(self, inst: int, wfs: int) -> int:
+        """Row chunks per frame of sensor wfs, as configured."""
+        return int(self.specs[inst][0].wfs[wfs].n_chunks)
+
     def chunk_rows(self, inst: int, wfs: int, chunk: int):
         a, b = C.c_int32(), C.c_int32()
         _ok(lib().rtc_chunk_rows(self._h, inst, wfs, chunk, C.byref(a), C.byref(b)),
@@ -293,6 +299,18 @@ class Engine:
 
     def run_mvm(self, inst: int, n_iter: int, stream=None):
         _ok(lib().rtc_run_mvm(self._h, inst, n_iter, _stream_ptr(stream)), "rtc_run_mvm")
+
+    def mvm_timing(self, inst: int, capacity: int, every: int = 1):
+        """Time the MVM launch of every `every`-th later per-launch frame, up to
+        `capacity` launches, with HIP events on its stream (0 turns it off)."""
+        _ok(lib().rtc_mvm_timing(self._h, inst, capacity, every), "rtc_mvm_timing")
+
+    def mvm_timing_read(self, inst: int = 0):
+        """(number of timed MVM launches, their total duration in seconds); clears."""
+        n, ms = C.c_int32(0), C.c_double(0.0)
+        _ok(lib().rtc_mvm_timing_read(self._h, inst, C.byref(n), C.byref(ms)),
+            "rtc_mvm_timing_read")
+        return n.value, ms.value / 1e3
 
     def trace_enable(self, n_frames: int):
         """Record the frame loop's per-wavefront timeline for the first n_frames
