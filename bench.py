@@ -62,30 +62,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("rtc_device.h", "rtc_internal.h", "rtc_kernels.hip", "rtc_persist.hip")
+# Sources each measured kernel is built from; a counter summary applies only
+# while they are unchanged.
+KERNEL_SOURCES = {"k_mvm": ("rtc_device.h", "rtc_internal.h", "rtc_kernels.hip"),
+                  "k_frame_loop": ("rtc_device.h", "rtc_internal.h", "rtc_persist.hip")}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kernel]:
         h.update(open(os.path.join(ROOT, "paper_1903_01852_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, dtype: str, kernel: str = "k_mvm"):
+def measured_traffic(workload: str, dtype: str, kernel: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    p = os.path.join(ROOT, "profiles", "mvm_traffic.json")
-    if not os.path.exists(p):
+    summary (profiles/kernel_traffic.json), if it was taken on the kernel's
+    current sources; else None."""
+    p = os.path.join(ROOT, "profiles", "kernel_traffic.json")
+    name = kernel.split("<")[0]
+    if not os.path.exists(p) or name not in KERNEL_SOURCES:
         return None
     try:
         d = json.load(open(p))
     except ValueError:
         return None
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    ent = d.get("entries", {}).get(f"{workload}:{dtype}:{name}")
+    if ent is None or ent.get("source_sha256_16") != kernel_source_hash(name):
         return None
-    ent = d.get("entries", {}).get(f"{workload}:{dtype}:{kernel.split('<')[0]}")
-    return None if ent is None else ent.get("hbm_bytes_per_launch")
+    return ent.get("hbm_bytes_per_launch")
 
 
 def build_inputs(workload: str, bank: int):
@@ -320,6 +325,44 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
     return res
 
 
+# matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
+LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"))
+
+
+def mvm_large(torch, rtc, log):
+    """The standalone MVM on the MCAO and LTAO matrices (each beyond the Infinity
+    Cache), warm (back to back) and after a 1 GiB read-only cache flush."""
+    import numpy as np
+    import synth
+    res = {}
+    done = {}
+    for name, dtype in LARGE_MVM:
+        wl = synth.get_workload(name)
+        inst = wl.instances[0]
+        if name not in done:
+            done.clear()
+            done[name] = synth.control_matrix(wl, 0)
+        R = done[name]
+        na = inst.n_act
+        M = (synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na), synth.seed_for(wl.index, 0, 99, 5),
+                                   np.float32) if inst.polc else None)
+        eng = rtc.Engine([(inst, dtype)], mode="stream")
+        eng.load_matrices(0, R, M=M)
+        info = eng.infos[0]
+        warm = mvm_timing(torch, eng, n_iter=100)
+        cold = mvm_timing(torch, eng, n_iter=100, cold=True)
+        eng.close()
+        alg = (na * info["n_slopes"] * ELEM[dtype] + 4 * info["n_slopes"] + 4 * na
+               + (4 * na if dtype == "fp8" else 0))
+        r = {"n_act": na, "n_slopes": info["n_slopes"], "alg_bytes": alg,
+             "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9, "warm_frac": alg / warm / 1e9 / HBM_PEAK_GBS,
+             "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9, "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS}
+        res[f"{name}:{dtype}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+        log(f"bench: mvm {name} {dtype}: {alg / 1e6:.0f} MB, warm {warm * 1e6:.1f} us "
+            f"({r['warm_gbs']:.0f} GB/s), cold {cold * 1e6:.1f} us ({r['cold_gbs']:.0f} GB/s)")
+    return res
+
+
 def box_reference(torch, reps=10):
     """HBM reference of this particular box: a plain 512 MiB device-to-device
     copy (read + write bytes per second, median of `reps`).  MI355X boxes in one
@@ -384,6 +427,10 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-latency-suite", action="store_true",
                     help="skip the MCAO / LTAO+SCAO serving cases")
+    ap.add_argument("--no-mvm-large", action="store_true",
+                    help="skip the standalone MVM on the MCAO / LTAO matrices")
+    ap.add_argument("--mvm-large-only", action="store_true",
+                    help="only the standalone MVM on the MCAO / LTAO matrices (for profiling)")
     ap.add_argument("--quick", action="store_true",
                     help="the chosen path and storage type only (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -444,6 +491,9 @@ def main():
 
     ref = box_reference(torch)
     log(f"bench: box reference {ref}")
+    if args.mvm_large_only:
+        print(json.dumps({"box_reference": ref, "mvm_large": mvm_large(torch, rtc, log)}), flush=True)
+        return
 
     dtypes = [args.dtype] + ([] if args.quick else
                              [v for v in args.variants.split(",") if v and v != args.dtype])
@@ -464,6 +514,10 @@ def main():
                 latency[dtype] = serving_latency(eng, [(0, frames)], args.latency_frames)[0]
                 log(f"bench: {dtype} latency: {latency[dtype]}")
             eng.close()
+
+    large = None
+    if not args.quick and not args.no_mvm_large:
+        large = mvm_large(torch, rtc, log)
 
     suite = None
     if not args.quick and not args.no_latency and not args.no_latency_suite:
@@ -505,6 +559,7 @@ def main():
         "latency_suite_us": ({**suite, "what": SERVING_NOTE} if suite else None),
         "paths": {p: {k: rnd(v) for k, v in d.items()} for p, d in paths.items() if d},
         "mvm": {k: rnd(v) for k, v in mvm.items()},
+        "mvm_beyond_infinity_cache": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -351,4 +351,37 @@ __device__ __forceinline__ float sum_parts(const float *__restrict__ part, int s
     return y;
 }
 
+// Sum of one row over a tile's column blocks, in block order, each block's
+// values in order: y = ((B_0 + B_1) + B_2) + ..., B_k = ((0 + v_a) + v_b) + ...
+// for vals[j * n_rows + r], j in [0, n); block k ends before index
+// end_of(k).  Up to BATCH loads are in flight however short the blocks are (a
+// per-block loop would wait for memory once per block: ~100 round trips for
+// six laser guide stars).
+template <int BATCH, class EndOf>
+__device__ __forceinline__ float sum_in_blocks(const float *vals, int n, int n_kb, int n_rows,
+                                               int r, EndOf end_of) {
+    float y = 0.0f, blk = 0.0f;
+    int kb = 0;
+    int blk_end = n_kb > 0 ? end_of(0) : n;
+    for (int s0 = 0; s0 < n; s0 += BATCH) {
+        float v[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+            v[u] = s0 + u < n ? load_agent(vals + (size_t)(s0 + u) * n_rows + r) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int j = s0 + u;
+            if (j < n) {
+                blk += v[u];
+                if (j + 1 == blk_end) {
+                    y = kb == 0 ? blk : y + blk;
+                    blk = 0.0f;
+                    if (++kb < n_kb) blk_end = end_of(kb);
+                }
+            }
+        }
+    }
+    return y;
+}
+
 }  // namespace rtc

@@ -59,11 +59,11 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
                                               int n_rows, int t, int lane, int nr) {
     const int r = t * kTileRows + lane;
     if (lane >= nr) return;
-    float y = 0.0f;
-    for (int b = 0; b < E.n_kb; ++b) {
-        const int2 sb = E.kb_segs[b];
-        y += sum_parts(part, sb.x, sb.y, n_rows, r);
-    }
+    const int2 *kb_segs = E.kb_segs;
+    float y = sum_in_blocks<32>(part, E.n_parts, E.n_kb, n_rows, r, [&](int b) {
+        const int2 sb = kb_segs[b];
+        return sb.x + sb.y;
+    });
     if (E.mode == EPI_REDUCE) {
         E.y[r] = y;
         return;

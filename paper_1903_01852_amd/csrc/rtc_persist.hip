@@ -425,50 +425,19 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
     }
 }
 
-// Values [0, n) of row r of a [value][row] array, summed in that order with
-// up to kSumBatch loads in flight, as the blocks of a tile: a value ends block
-// kb when its index + 1 is the block's end (blk_end(kb)), and blocks are added
-// in order.  Batch: the values are segment partials; serving: block sums (one
-// value per block).
+// The tile's reconstruction sum for row r: batch adds the segment partials
+// block by block, serving the block sums (one value per block).
 constexpr int kSumBatch = 16;
-template <bool BLOCKS>
-__device__ float sum_tile(InstRef I, const float *vals, int r) {
+__device__ float tile_sum(InstRef I, uint64_t q, int r) {
     const int n_kb = I.n_kb, n_act = I.n_act;
-    const int n = BLOCKS ? n_kb : (int)I.n_seg;
+    if (I.serving)
+        return sum_in_blocks<kSumBatch>(I.bsum + (size_t)dslot(q) * n_kb * n_act, n_kb, n_kb,
+                                        n_act, r, [](int b) { return b + 1; });
     const int2 *kb_segs = I.kb_segs;
-    float y = 0.0f, blk = 0.0f;
-    int kb = 0;
-    int blk_end = 1;
-    if (!BLOCKS) {
-        const int2 sb = ldc(kb_segs);
-        blk_end = sb.x + sb.y;
-    }
-    for (int s0 = 0; s0 < n; s0 += kSumBatch) {
-        float v[kSumBatch];
-#pragma unroll
-        for (int u = 0; u < kSumBatch; ++u)
-            v[u] = s0 + u < n ? load_agent(vals + (size_t)(s0 + u) * n_act + r) : 0.0f;
-#pragma unroll
-        for (int u = 0; u < kSumBatch; ++u) {
-            const int sg = s0 + u;
-            if (sg < n) {
-                blk += v[u];
-                if (sg + 1 == blk_end) {
-                    y = kb == 0 ? blk : y + blk;
-                    blk = 0.0f;
-                    if (++kb < n_kb) {
-                        if (BLOCKS) {
-                            blk_end = kb + 1;
-                        } else {
-                            const int2 sb = ldc(kb_segs + kb);
-                            blk_end = sb.x + sb.y;
-                        }
-                    }
-                }
-            }
-        }
-    }
-    return y;
+    return sum_in_blocks<kSumBatch>(I.y_part[dslot(q)], I.n_seg, n_kb, n_act, r, [&](int b) {
+        const int2 sb = ldc(kb_segs + b);
+        return sb.x + sb.y;
+    });
 }
 
 // Commands of tile t for frame q, then of every following frame whose join
@@ -477,10 +446,7 @@ __device__ int finish_chain(InstRef I, uint64_t q, int t, int lane) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
     for (int done = 1;; ++done) {
-        float y = 0.0f;
-        if (lane < nr)
-            y = I.serving ? sum_tile<true>(I, I.bsum + (size_t)dslot(q) * I.n_kb * I.n_act, r)
-                          : sum_tile<false>(I, I.y_part[dslot(q)], r);
+        const float y = lane < nr ? tile_sum(I, q, r) : 0.0f;
         tile_commands(I, q, t, r, lane < nr, y, lane);
         ++q;
         if (q >= I.q_end || !join(I, q, t, lane)) return done;
