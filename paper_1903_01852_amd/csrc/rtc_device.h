@@ -303,8 +303,10 @@ __device__ __forceinline__ void dot16(const vec16_t q, XS xs, int v, float &a0, 
 // Streams vectors [0, nv) of one segment for this lane's row, U vectors (U
 // loads in flight) per batch; the slope values of a batch are contiguous, so
 // they arrive in a few wide scalar loads issued beside the vector loads.  The
-// last, partial batch guards each load instead.
-template <int DT, int U, class XS>
+// last, partial batch guards each load instead.  NT: non-temporal loads, for
+// matrices larger than the Infinity Cache (a matrix that fits stays resident
+// from frame to frame with ordinary loads).
+template <int DT, int U, class XS, bool NT = false>
 __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, int nr, XS xs,
                                                 int nv) {
     const RTC_GLOBAL vec16_t *__restrict__ p = (const RTC_GLOBAL vec16_t *)pg;
@@ -313,7 +315,8 @@ __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, in
     for (; v + U <= nv; v += U) {
         vec16_t q[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) q[u] = p[(v + u) * nr];
+        for (int u = 0; u < U; ++u)
+            q[u] = NT ? __builtin_nontemporal_load(p + (v + u) * nr) : p[(v + u) * nr];
 #pragma unroll
         for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, v + u, a0, a1);
     }
@@ -321,7 +324,8 @@ __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, in
         vec16_t q[U];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (v + u < nv) q[u] = p[(v + u) * nr];
+            if (v + u < nv)
+                q[u] = NT ? __builtin_nontemporal_load(p + (v + u) * nr) : p[(v + u) * nr];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (v + u < nv) dot16<DT>(q[u], xs, v + u, a0, a1);

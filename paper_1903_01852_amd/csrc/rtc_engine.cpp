@@ -447,7 +447,7 @@ void enqueue_polc(Instance *I, hipStream_t st) {
     E.kb_segs = I->d_kbm_segs;
     E.count = I->d_count_m;
     E.y = I->d_p;
-    launch_mvm(st, RTC_CM_F32, I->d_M, I->d_kbm, I->d_segm, I->d_pieces_m, 0,
+    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M, I->d_kbm, I->d_segm, I->d_pieces_m, 0,
                (int)I->pieces_m.size(), I->n_act, I->d_a, I->d_ppart, E);
 }
 
@@ -588,6 +588,11 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
         s = alloc_instance(e, I);
         if (s != RTC_OK) return bail(s);
     }
+    // every instance streams its matrices each frame and they share the
+    // Infinity Cache: beyond its size, stream them with non-temporal loads
+    int64_t per_frame = 0;
+    for (const Instance *I : e->inst) per_frame += I->cm_bytes + I->m_bytes;
+    for (Instance *I : e->inst) I->stream_nt = per_frame > kCacheResidentBytes;
     if (e->mode == RTC_MODE_PERSISTENT) {
         rtc_status s = persist_alloc(e);
         if (s != RTC_OK) return bail(s);
@@ -867,7 +872,7 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         const bool timed = 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size() &&
                            I->mvm_ev_count++ % (uint64_t)I->mvm_ev_every == 0;
         if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
-        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
+        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
                    (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart,
                    integrate_epi(I, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr));
         if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used++ + 1], st));
@@ -900,7 +905,7 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     E.y = I->d_yscratch;
     std::lock_guard<std::mutex> lk(I->mu);
     for (int i = 0; i < n_iter; ++i)
-        launch_mvm(st, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
+        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
                    (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
     return last_error(e);
 }
@@ -1078,7 +1083,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             fs.f[w] = I->wfs[w].d_ring + (size_t)slot * I->wfs[w].d.frame_h * I->wfs[w].d.frame_w;
         const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
-        launch_mvm(e->stream, I->d.cm_dtype, I->d_cm, I->d_kb, I->d_seg, I->d_single,
+        launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_single,
                    I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad, I->d_ypart,
                    integrate_epi(I, I->frame_c1, I->frame_g, nullptr));
     }

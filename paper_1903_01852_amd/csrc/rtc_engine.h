@@ -115,6 +115,7 @@ struct Instance {
     std::vector<int2> kb_segs, kbm_segs;       // the same as {first, count}, recon / POLC
     int spad_len = 0;
     int64_t cm_bytes = 0, m_bytes = 0;
+    bool stream_nt = false;        // non-temporal matrix loads (the engine's matrices exceed the cache)
     WfsParamSet params{};
     // device
     ShUnit *d_sh = nullptr;

@@ -171,6 +171,7 @@ struct PersistInst {
     const uint8_t *cm;
     const float *scale;            // FP8 row scales or null
     int32_t dtype, n_act, n_tiles, polc;
+    int32_t stream_nt, r7;         // the engine's matrices exceed the Infinity Cache
     // POLC
     const uint8_t *M;
     const KBlock *kbm;
@@ -269,7 +270,10 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        const float *dark4, const float *flat4, const float *bg4,
                        const float *thr, const float *ref, float *s_pad, float *s_out,
                        int32_t *counts, uint64_t *masks);
-void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs,
+// stream_nt: stream the matrix with non-temporal loads (matrices larger than
+// the Infinity Cache); otherwise ordinary loads keep a smaller matrix resident.
+constexpr int64_t kCacheResidentBytes = 192ll << 20;
+void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
                 const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
                 const float *x_pad, float *y_part, const MvmEpilogue &epi);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,

@@ -75,7 +75,7 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
     if (E.out != nullptr) E.out[r] = an;
 }
 
-template <int DT, int U>
+template <int DT, int U, bool NT>
 __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
                                              const KBlock *__restrict__ kbs,
                                              const Segment *__restrict__ segs,
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
                 (int64_t)S.v0 * nr + lane;
             const float4 *__restrict__ xs =
                 reinterpret_cast<const float4 *>(x + K.spad + (int64_t)S.v0 * kE);
-            const float part = stream_segment<DT, U>(p, nr, xs, S.nv);
+            const float part = stream_segment<DT, U, const float4 *, NT>(p, nr, xs, S.nv);
             // agent-scope atomic store: written through to the memory side,
             // where every XCD's agent-scope loads see it
             __hip_atomic_store(y_part + (size_t)sg * n_rows + t * kTileRows + lane, part,
@@ -197,28 +197,39 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        n_pyr, frames, params, dark4, flat4, bg4, thr, ref, o);
 }
 
-void launch_mvm(hipStream_t st, int dtype, const void *cm, const KBlock *kbs,
+template <bool NT>
+void launch_mvm_t(hipStream_t st, int dtype, const uint8_t *c, const KBlock *kbs,
+                  const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_tiles,
+                  int n_rows, const float *x_pad, float *y_part, const MvmEpilogue &epi) {
+    const dim3 grid((n_pieces * n_tiles + 3) / 4), block(256);
+    switch (dtype) {
+    case RTC_CM_F32:
+        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, kbs, segs, pieces,
+                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        break;
+    case RTC_CM_BF16:
+        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 16, NT>), grid, block, 0, st, c, kbs, segs, pieces,
+                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        break;
+    default:
+        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 16, NT>), grid, block, 0, st, c, kbs, segs, pieces,
+                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        break;
+    }
+}
+
+void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
                 const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
                 const float *x_pad, float *y_part, const MvmEpilogue &epi) {
     if (n_pieces <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
-    const int waves = n_pieces * n_tiles;
-    const dim3 grid((waves + 3) / 4), block(256);
     const uint8_t *c = static_cast<const uint8_t *>(cm);
-    switch (dtype) {
-    case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
-        break;
-    case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
-        break;
-    default:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 16>), grid, block, 0, st, c, kbs, segs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
-        break;
-    }
+    if (stream_nt)
+        launch_mvm_t<true>(st, dtype, c, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
+                           y_part, epi);
+    else
+        launch_mvm_t<false>(st, dtype, c, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
+                            y_part, epi);
 }
 
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,

@@ -228,14 +228,24 @@ __device__ __forceinline__ int vec_elems(int dtype) {
 template <int DT> struct LoopBatch { static constexpr int U = 8; };
 template <> struct LoopBatch<RTC_CM_FP8> { static constexpr int U = 4; };
 
-template <int DT>
-__device__ __forceinline__ float mvm_partial(InstRef I, const uint8_t *cm,
-                                             const KBlock &K, const Segment &S, int t, int nr,
-                                             int lane, const RTC_LDS float *lds) {
-    if (lane >= nr) return 0.0f;
+template <int DT, bool NT>
+__device__ __forceinline__ float stream_part(const uint8_t *cm, const KBlock &K, const Segment &S,
+                                             int t, int nr, int lane, const RTC_LDS float *lds) {
     const uint4 *p = reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
                      (int64_t)S.v0 * nr + lane;
-    return stream_segment<DT, LoopBatch<DT>::U>(p, nr, (const RTC_LDS lds4_t *)lds, S.nv);
+    return stream_segment<DT, LoopBatch<DT>::U, const RTC_LDS lds4_t *, NT>(
+        p, nr, (const RTC_LDS lds4_t *)lds, S.nv);
+}
+
+// Partial of one segment on tile t for this lane's row (0 past the tile's rows).
+template <int DT>
+__device__ __forceinline__ float mvm_partial(InstRef I, const uint8_t *cm, const KBlock &K,
+                                             const Segment &S, int t, int nr, int lane,
+                                             const RTC_LDS float *lds) {
+    // ordinary loads whatever the matrix size: the non-temporal variants
+    // double the loop's streaming code and push the kernel into spills
+    if (lane >= nr) return 0.0f;
+    return stream_part<DT, false>(cm, K, S, t, nr, lane, lds);
 }
 
 __device__ __forceinline__ float seg_partial(InstRef I, const KBlock &K,

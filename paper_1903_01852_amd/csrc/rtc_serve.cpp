@@ -73,6 +73,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.dtype = I->d.cm_dtype;
     d.n_act = I->n_act;
     d.n_tiles = I->n_tiles;
+    d.stream_nt = I->stream_nt ? 1 : 0;
     d.polc = I->d.polc;
     d.M = I->d_M;
     d.kbm = I->d_kbm;
