@@ -21,7 +21,9 @@ Also reported on the same JSON line:
   latency_us   serving latency of the persistent loop per storage type (last
                chunk submitted from host memory -> commands seen on the host),
                frames paced at 500 Hz with the chunks spread over a 1.5 ms
-               readout; p50 / p99 / RMS jitter; includes PCIe;
+               readout; p50 / p99 / RMS jitter; includes PCIe; ``zero_copy``
+               the same with the chunks written in place into the lent ring
+               slot (latency from the commit);
   mvm          the standalone MVM kernel per storage type, warm (back to back)
                and after a 1 GiB read-only flush of the caches;
   cpu_baseline the CPU oracle on a bounded sample of the same frames.
@@ -216,7 +218,7 @@ def _pct(v):
 
 
 def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s=1.5e-3,
-                    switch=None):
+                    switch=None, zero_copy=False):
     """Paced serving loop from host memory for one or more instances of one
     engine, every sensor read out in parallel: chunk c of each sensor of an
     instance with n chunks is delivered (c + 1) * readout / n after the frame
@@ -224,7 +226,9 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     (instance index, frame, gain, leak) applied through the API before that
     frame.  Returns per instance: host latency (last chunk submitted -> commands
     seen on the host) and the device part (the loop's own clock from the
-    sentinel seeing the last chunk to the commands being published)."""
+    sentinel seeing the last chunk to the commands being published).
+    zero_copy: chunks written in place into the lent ring slot (rtc_acquire_chunk,
+    rtc_commit_chunk) instead of copied in by rtc_submit_pixel_chunk."""
     plan = []
     for idx, banks in streams:
         info = eng.infos[idx]
@@ -247,7 +251,11 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
             while time.perf_counter() < t_frame + t_c:
                 pass
             bank = banks[idx][w]
-            eng.submit_chunk(idx, w, f, c, bank[f % bank.shape[0]][r0:r1])
+            if zero_copy:
+                eng.acquire_chunk(idx, w, f, c)[...] = bank[f % bank.shape[0]][r0:r1]
+                eng.commit_chunk(idx, w, f, c)
+            else:
+                eng.submit_chunk(idx, w, f, c, bank[f % bank.shape[0]][r0:r1])
         for idx, _ in streams:
             _, info = eng.wait_commands(idx, f, timeout_s=5.0)
             if f >= warmup:
@@ -512,6 +520,8 @@ def main():
             elif not args.quick and not args.no_latency:
                 eng.set_state(0, None, None, 0)
                 latency[dtype] = serving_latency(eng, [(0, frames)], args.latency_frames)[0]
+                latency[dtype]["zero_copy"] = serving_latency(
+                    eng, [(0, frames)], args.latency_frames, zero_copy=True)[0]
                 log(f"bench: {dtype} latency: {latency[dtype]}")
             eng.close()
 
@@ -539,7 +549,8 @@ def main():
             "algorithmic_bytes_per_launch": main_res["kernel_alg_bytes"]}
 
     def rnd(d):
-        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+        return {k: (round(v, 3) if isinstance(v, float) else rnd(v) if isinstance(v, dict)
+                    else v) for k, v in d.items()}
 
     out = {
         "metric": METRIC, "value": round(main_res["frames_per_s"], 1), "unit": "frames/s",

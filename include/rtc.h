@@ -172,6 +172,22 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
  * instance has been submitted. */
 rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
                                   int32_t chunk, const uint16_t *rows);
+/* Zero-copy form of rtc_submit_pixel_chunk (persistent mode only, else
+ * RTC_E_STATE): rtc_acquire_chunk opens the chunk under the same frame and
+ * order rules and lends the caller the pinned host ring slot that the loop
+ * reads it from: *rows points at the chunk's first row, *pitch receives the
+ * row pitch in uint16 (frame_w rounded up to 8).  The caller writes the
+ * chunk's rows there, frame_w values per row, then calls rtc_commit_chunk
+ * with the same (wfs, frame, chunk), which hands the rows to the loop; the
+ * frame's arrival time is taken at commit.  One chunk per sensor may be lent
+ * at a time (acquiring another before the commit gives RTC_E_INVAL; so does a
+ * commit that names another chunk).  A commit after a newer frame of the
+ * instance was started meanwhile gives RTC_E_FRAME_DROPPED.  The pointer is
+ * owned by the library and valid until the commit. */
+rtc_status rtc_acquire_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                             int32_t chunk, uint16_t **rows, int32_t *pitch);
+rtc_status rtc_commit_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                            int32_t chunk);
 /* Wait up to timeout_ns for the commands of `frame` and copy them to cmds
  * (host, n_act FP32).  info (nullable) receives the frame's timestamps. */
 rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float *cmds,

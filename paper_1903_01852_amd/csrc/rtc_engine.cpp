@@ -830,7 +830,10 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
         sl.complete = false;
         sl.dropped = false;
     }
-    for (auto &W : I->wfs) W.next_chunk = 0;
+    for (auto &W : I->wfs) {
+        W.next_chunk = 0;
+        W.acquired = -1;
+    }
     return RTC_OK;
 }
 
@@ -1023,6 +1026,28 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
 }
 
 // ------------------------------------------------------------- serving (stream mode)
+rtc_status rtc_acquire_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                             int32_t chunk, uint16_t **rows, int32_t *pitch) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (e->mode != RTC_MODE_PERSISTENT || !I->loaded) return RTC_E_STATE;
+    if (wfs < 0 || wfs >= (int)I->wfs.size() || !rows || !pitch) return RTC_E_INVAL;
+    if (chunk < 0 || chunk >= I->wfs[wfs].d.n_chunks) return RTC_E_INVAL;
+    std::lock_guard<std::mutex> lk(I->mu);
+    return persist_acquire(e, I, wfs, frame, chunk, rows, pitch);
+}
+
+rtc_status rtc_commit_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
+                            int32_t chunk) {
+    const int64_t t_in = now_ns();
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (e->mode != RTC_MODE_PERSISTENT || !I->loaded) return RTC_E_STATE;
+    if (wfs < 0 || wfs >= (int)I->wfs.size()) return RTC_E_INVAL;
+    std::lock_guard<std::mutex> lk(I->mu);
+    return persist_commit(e, I, wfs, frame, chunk, t_in);
+}
+
 rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
                                   int32_t chunk, const uint16_t *rows) {
     const int64_t t_in = now_ns();

@@ -45,6 +45,8 @@ struct WfsState {
     uint16_t *h_stage = nullptr;   // pinned staging ring (ring_depth frames)
     size_t ring_elems = 0;         // uint16 in each ring
     int pitch16 = 0;               // persistent serving: row pitch (uint16), rows padded to 16 B
+    int acquired = -1;             // chunk lent by rtc_acquire_chunk, not yet committed
+    uint64_t acq_frame = 0;
     size_t slot16 = 0;             // persistent serving: uint16 per ring slot
 };
 
@@ -262,6 +264,10 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
                          float *slopes, int32_t *counts, hipStream_t st);
 rtc_status persist_params(rtc_engine *e, Instance *I);
 rtc_status persist_quiesce(rtc_engine *e);
+rtc_status persist_acquire(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                           uint16_t **rows, int32_t *pitch);
+rtc_status persist_commit(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                          int64_t t_in);
 // Timeline record of the frame loop: frames per launch (0 = off).
 constexpr int kMaxTraceFrames = 4096;
 rtc_status persist_trace(rtc_engine *e, int n_frames);

@@ -479,12 +479,17 @@ rtc_status persist_params(rtc_engine *e, Instance *I) {
     return RTC_OK;
 }
 
-rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
-                          const uint16_t *rows, int64_t t_in) {
+namespace {
+
+// Opens chunk `chunk` of sensor w of frame `frame`: starts the frame when it is
+// a new one (delivering an incomplete predecessor as dropped) and launches the
+// loop when it is not running.
+rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk) {
     PersistInstState &P = I->ps;
     PersistEngine &pe = e->pe;
     WfsState &S = I->wfs[w];
     if (pe.running && !pe.serving) return RTC_E_STATE;
+    if (S.acquired >= 0) return RTC_E_INVAL;     // a lent chunk is not committed yet
     if (I->cur_frame != ~0ull && frame < I->cur_frame) return RTC_E_FRAME_DROPPED;
     if (frame < I->next_frame) return RTC_E_FRAME_DROPPED;
     if (I->cur_frame == ~0ull || frame > I->cur_frame) {
@@ -522,13 +527,21 @@ rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int
         if (!pe.running) TRY(launch_serving(e));
     }
     if (chunk != S.next_chunk) return RTC_E_INVAL;
+    return RTC_OK;
+}
+
+// The ring slot row where chunk rows start (rows at the ring's 16-byte pitch).
+uint16_t *chunk_dst(rtc_engine *e, Instance *I, int w, int chunk) {
+    const WfsState &S = I->wfs[w];
+    return S.h_stage + (size_t)(I->ps.q_cur % (uint64_t)e->ring_depth) * S.slot16 +
+           (size_t)S.row0[chunk] * S.pitch16;
+}
+
+// Hands the chunk's rows in the ring to the loop (its doorbell).
+void end_chunk(Instance *I, int w, uint64_t frame, int chunk, int64_t t_in) {
+    PersistInstState &P = I->ps;
+    WfsState &S = I->wfs[w];
     const uint64_t q = P.q_cur;
-    const int r0 = S.row0[chunk], r1 = S.row0[chunk + 1];
-    // rows at the ring's 16-byte pitch
-    uint16_t *dst = S.h_stage + (size_t)(q % (uint64_t)e->ring_depth) * S.slot16;
-    for (int r = r0; r < r1; ++r)
-        std::memcpy(dst + (size_t)r * S.pitch16, rows + (size_t)(r - r0) * S.d.frame_w,
-                    (size_t)S.d.frame_w * 2);
     store_release(P.doorbell + w, db_word(q, (uint64_t)chunk + 1));
     S.next_chunk++;
     I->cur_started = true;
@@ -540,6 +553,41 @@ rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int
         I->cur_frame = ~0ull;
         I->cur_started = false;
     }
+}
+
+}  // namespace
+
+rtc_status persist_submit(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                          const uint16_t *rows, int64_t t_in) {
+    TRY(begin_chunk(e, I, w, frame, chunk));
+    const WfsState &S = I->wfs[w];
+    uint16_t *dst = chunk_dst(e, I, w, chunk);
+    for (int r = 0; r < S.row0[chunk + 1] - S.row0[chunk]; ++r)
+        std::memcpy(dst + (size_t)r * S.pitch16, rows + (size_t)r * S.d.frame_w,
+                    (size_t)S.d.frame_w * 2);
+    end_chunk(I, w, frame, chunk, t_in);
+    return RTC_OK;
+}
+
+rtc_status persist_acquire(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                           uint16_t **rows, int32_t *pitch) {
+    TRY(begin_chunk(e, I, w, frame, chunk));
+    WfsState &S = I->wfs[w];
+    S.acquired = chunk;
+    S.acq_frame = frame;
+    *rows = chunk_dst(e, I, w, chunk);
+    *pitch = S.pitch16;
+    return RTC_OK;
+}
+
+rtc_status persist_commit(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
+                          int64_t t_in) {
+    (void)e;
+    WfsState &S = I->wfs[w];
+    if (S.acquired != chunk || S.acq_frame != frame) return RTC_E_INVAL;
+    S.acquired = -1;
+    if (I->cur_frame != frame) return RTC_E_FRAME_DROPPED;   // superseded meanwhile
+    end_chunk(I, w, frame, chunk, t_in);
     return RTC_OK;
 }
 

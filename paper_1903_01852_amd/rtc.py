@@ -29,7 +29,8 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_load_matrices", "rtc_load_calibration", "rtc_set_params", "rtc_get_state",
            "rtc_set_state", "rtc_submit_pixel_chunk", "rtc_wait_commands",
            "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
-           "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read")
+           "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read",
+           "rtc_acquire_chunk", "rtc_commit_chunk")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -99,6 +100,9 @@ def lib() -> C.CDLL:
         L.rtc_set_state.argtypes = [vp, i32, vp, vp, u64]
         L.rtc_submit_pixel_chunk.argtypes = [vp, i32, i32, u64, i32, vp]
         L.rtc_wait_commands.argtypes = [vp, i32, u64, vp, i64, C.POINTER(FrameInfoC)]
+        L.rtc_acquire_chunk.argtypes = [vp, i32, i32, u64, i32, C.POINTER(C.c_void_p),
+                                        C.POINTER(i32)]
+        L.rtc_commit_chunk.argtypes = [vp, i32, i32, u64, i32]
         L.rtc_process_frames.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64), i32, vp, vp,
                                          vp, vp]
         L.rtc_read_slopes.argtypes = [vp, i32, vp, vp, vp]
@@ -266,6 +270,25 @@ class Engine:
     def submit_status(self, inst: int, wfs: int, frame: int, chunk: int, rows: np.ndarray) -> int:
         rows = np.ascontiguousarray(rows, np.uint16)
         return lib().rtc_submit_pixel_chunk(self._h, inst, wfs, frame, chunk, _ptr(rows))
+
+    def acquire_chunk(self, inst: int, wfs: int, frame: int, chunk: int) -> np.ndarray:
+        """Zero-copy submit, first half: a (rows, frame_w) uint16 view of the pinned
+        ring slot the chunk goes to.  Fill it, then call commit_chunk."""
+        p, pitch = C.c_void_p(), C.c_int32()
+        _ok(lib().rtc_acquire_chunk(self._h, inst, wfs, frame, chunk, C.byref(p),
+                                    C.byref(pitch)), "rtc_acquire_chunk")
+        r0, r1 = self.chunk_rows(inst, wfs, chunk)
+        w = int(self.specs[inst][0].wfs[wfs].frame_w)
+        n = (r1 - r0 - 1) * pitch.value + w if r1 > r0 else 0
+        buf = np.ctypeslib.as_array(C.cast(p, C.POINTER(C.c_uint16)), shape=(max(n, 1),))
+        return np.lib.stride_tricks.as_strided(buf, shape=(r1 - r0, w),
+                                               strides=(pitch.value * 2, 2))
+
+    def commit_chunk(self, inst: int, wfs: int, frame: int, chunk: int):
+        _ok(lib().rtc_commit_chunk(self._h, inst, wfs, frame, chunk), "rtc_commit_chunk")
+
+    def commit_status(self, inst: int, wfs: int, frame: int, chunk: int) -> int:
+        return lib().rtc_commit_chunk(self._h, inst, wfs, frame, chunk)
 
     def wait_commands(self, inst: int, frame: int, timeout_s: float = 5.0):
         n = self.infos[inst]["n_act"]

@@ -196,3 +196,114 @@ def test_serving_dropped_frame(rtc):
     frames = [case.frames[0][kept]]
     ref = oracle.run(case.inst, frames, case.cals, case.R, 7)
     assert rel_l2(np.stack(got), ref["commands"]).max() <= TOL["f32"]
+
+
+def _odd_width_case(n_frames: int = 10):
+    """Two sensors whose frame widths are not multiples of 8 (ring rows padded)."""
+    a = synth.ShWfs(nsub=12, px=9, obs=0.3, frame_h=111, frame_w=115, origin=(2, 5), n_chunks=5)
+    b = synth.ShWfs(nsub=6, px=10, obs=0.28, frame_h=60, frame_w=61, n_chunks=3)
+    inst = synth.Instance("odd93", (a, b), 260, ("f32",), gain=0.5, leak=0.02)
+    wl = synth.Workload(93, "odd93", (inst,), n_frames=n_frames, bank=n_frames)
+    synth.workloads.WORKLOADS[wl.name] = wl
+    try:
+        return Case(wl.name, n_frames=n_frames)
+    finally:
+        del synth.workloads.WORKLOADS[wl.name]
+
+
+def _run_zero_copy(eng, idx, case, n=None):
+    """Serving path through rtc_acquire_chunk / rtc_commit_chunk."""
+    out = []
+    for f in range(case.n if n is None else n):
+        for w, bank in enumerate(case.frames):
+            img = bank[f % bank.shape[0]]
+            for c in range(case.inst.wfs[w].n_chunks):
+                r0, r1 = eng.chunk_rows(idx, w, c)
+                view = eng.acquire_chunk(idx, w, f, c)
+                assert view.shape == (r1 - r0, img.shape[1])
+                view[...] = img[r0:r1]
+                eng.commit_chunk(idx, w, f, c)
+        out.append(eng.wait_commands(idx, f, timeout_s=10.0)[0].astype(np.float64))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("name", ["scao_sh_small", "odd"])
+def test_serving_zero_copy_equals_copy_form(rtc, name):
+    """Chunks written in place into the lent ring slot give the copy-form commands
+    bit for bit, also where ring rows are padded past the frame width."""
+    case = _odd_width_case() if name == "odd" else Case(name, n_frames=12)
+    log(f"case {name} serving zero-copy chunk hand-off")
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        copied, _ = run_stream(eng, 0, case)
+        eng.set_state(0, None, None, 0)
+        lent = _run_zero_copy(eng, 0, case)
+    assert np.array_equal(lent, copied)
+    ref = case.run_oracle("f32")
+    assert rel_l2(lent, ref["commands"]).max() <= TOL["f32"]
+
+
+def test_zero_copy_rules(rtc):
+    """One lent chunk per sensor; commits must name it; stream mode refuses; a
+    newer frame started meanwhile makes the commit report the drop."""
+    case = Case("scao_sh_small", n_frames=4)
+    img = case.frames[0]
+    with rtc.Engine([(case.inst, "f32")], mode="stream") as eng:
+        case.load(eng)
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.acquire_chunk(0, 0, 0, 0)
+        assert ei.value.status == -5
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        r0, r1 = eng.chunk_rows(0, 0, 0)
+        v = eng.acquire_chunk(0, 0, 0, 0)
+        v[...] = img[0][r0:r1]
+        assert eng.submit_status(0, 0, 0, 1, img[0][r0:r1]) == -1   # chunk 0 still lent
+        assert eng.commit_status(0, 0, 0, 1) == -1                   # names another chunk
+        eng.commit_chunk(0, 0, 0, 0)
+        assert eng.commit_status(0, 0, 0, 0) == -1                   # nothing lent now
+        for c in range(1, case.inst.wfs[0].n_chunks):
+            a, b = eng.chunk_rows(0, 0, c)
+            eng.submit_chunk(0, 0, 0, c, img[0][a:b])
+        first = eng.wait_commands(0, 0)[0]
+        # frame 1: chunk 0 lent, then frame 2 starts through the copy form
+        v = eng.acquire_chunk(0, 0, 1, 0)
+        assert eng.submit_status(0, 0, 2, 0, img[2][r0:r1]) == -1    # lent chunk blocks
+        v[...] = img[1][r0:r1]
+        eng.commit_chunk(0, 0, 1, 0)
+        for c in range(case.inst.wfs[0].n_chunks):
+            a, b = eng.chunk_rows(0, 0, c)
+            eng.submit_chunk(0, 0, 2, c, img[2][a:b])
+        assert eng.wait_status(0, 1, 0.1) == -7
+        third = eng.wait_commands(0, 2)[0]
+    ref = oracle.run(case.inst, [img[[0, 2]]], case.cals, case.R, 2)
+    assert rel_l2(np.stack([first, third]).astype(np.float64), ref["commands"]).max() <= TOL["f32"]
+
+
+def test_zero_copy_commit_after_newer_frame(rtc):
+    """A chunk lent on one sensor while another sensor starts a newer frame: the
+    commit reports the drop, and the newer frame's commands are the oracle's."""
+    case = _odd_width_case(n_frames=3)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        got = []
+        for f in (0, 2):
+            if f == 2:
+                r0, r1 = eng.chunk_rows(0, 0, 0)
+                v = eng.acquire_chunk(0, 0, 1, 0)            # frame 1, sensor 0, lent
+                v[...] = case.frames[0][1][r0:r1]
+                a, b = eng.chunk_rows(0, 1, 0)
+                eng.submit_chunk(0, 1, 1, 0, case.frames[1][1][a:b])
+                eng.submit_chunk(0, 1, 2, 0, case.frames[1][2][a:b])   # supersedes frame 1
+                assert eng.commit_status(0, 0, 1, 0) == -7
+                assert eng.wait_status(0, 1, 0.1) == -7
+            for w in (0, 1):
+                for c in range(case.inst.wfs[w].n_chunks):
+                    if f == 2 and w == 1 and c == 0:
+                        continue
+                    a, b = eng.chunk_rows(0, w, c)
+                    eng.submit_chunk(0, w, f, c, case.frames[w][f][a:b])
+            got.append(eng.wait_commands(0, f)[0].astype(np.float64))
+    frames = [fr[[0, 2]] for fr in case.frames]
+    ref = oracle.run(case.inst, frames, case.cals, case.R, 2)
+    assert rel_l2(np.stack(got), ref["commands"]).max() <= TOL["f32"]
