@@ -520,6 +520,7 @@ def main():
             elif not args.quick and not args.no_latency:
                 eng.set_state(0, None, None, 0)
                 latency[dtype] = serving_latency(eng, [(0, frames)], args.latency_frames)[0]
+                eng.set_state(0, None, None, 0)
                 latency[dtype]["zero_copy"] = serving_latency(
                     eng, [(0, frames)], args.latency_frames, zero_copy=True)[0]
                 log(f"bench: {dtype} latency: {latency[dtype]}")
