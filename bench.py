@@ -364,7 +364,9 @@ def mvm_large(torch, rtc, log):
                + (4 * na if dtype == "fp8" else 0))
         r = {"n_act": na, "n_slopes": info["n_slopes"], "alg_bytes": alg,
              "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9, "warm_frac": alg / warm / 1e9 / HBM_PEAK_GBS,
-             "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9, "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS}
+             "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9, "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS,
+             # HBM bytes of one warm launch from the committed counter summary
+             "traffic": measured_traffic(name, dtype, "k_mvm")}
         res[f"{name}:{dtype}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
         log(f"bench: mvm {name} {dtype}: {alg / 1e6:.0f} MB, warm {warm * 1e6:.1f} us "
             f"({r['warm_gbs']:.0f} GB/s), cold {cold * 1e6:.1f} us ({r['cold_gbs']:.0f} GB/s)")
