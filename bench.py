@@ -5,13 +5,15 @@ sensor, the split-K control-matrix MVM, the in-order accumulation +
 integrator (and the POLC product when the workload has it).  Frames are
 resident in HBM before the timed region.  ``value`` is frames per second of
 the batch path named by ``--path``:
-  stream      per-launch kernels (centroids, then the split-K MVM whose last
-              wavefront per row tile runs the integrator), one frame after the
-              other on one stream; the default, and the faster batch form;
+  stream      per-launch kernels on one stream: frame f's split-K MVM (whose
+              last wavefront per row tile runs the integrator) in one grid with
+              frame f + 1's calibration + slopes (into the other slope buffer);
+              the default, and the faster batch form;
   persistent  the persistent frame loop, ``--bank`` frames per launch.
 
 Also reported on the same JSON line:
-  roofline     the dominant kernel of the chosen path (k_mvm, or k_frame_loop):
+  roofline     the dominant kernel of the chosen path (k_mvm_next: frame f's MVM
+               with frame f + 1's slopes in one grid; or k_frame_loop):
                algorithmic bytes per launch / its average duration, from HIP
                events recorded on its own stream around every launch of the
                timed region; ``traffic`` from the committed rocprofv3 counter
@@ -67,6 +69,7 @@ def log(*a):
 # Sources each measured kernel is built from; a counter summary applies only
 # while they are unchanged.
 KERNEL_SOURCES = {"k_mvm": ("rtc_device.h", "rtc_internal.h", "rtc_kernels.hip"),
+                  "k_mvm_next": ("rtc_device.h", "rtc_internal.h", "rtc_kernels.hip"),
                   "k_frame_loop": ("rtc_device.h", "rtc_internal.h", "rtc_persist.hip")}
 
 
@@ -125,6 +128,14 @@ def alg_bytes_per_frame(inst, info, dtype):
     if inst.polc:
         b += 4 * inst.n_act * inst.n_act
     return b + 14 * px + 4 * info["n_slopes"] + 8 * inst.n_act
+
+
+def mvm_next_alg_bytes(inst, info, dtype):
+    """Bytes of one k_mvm_next launch: frame f's MVM (matrix, slopes read,
+    commands read and written) and frame f + 1's slopes (pixels, calibration,
+    slopes written): a frame's bytes less the POLC product, a launch of its own."""
+    b = alg_bytes_per_frame(inst, info, dtype)
+    return b - (4 * inst.n_act * inst.n_act if inst.polc else 0)
 
 
 def make_engine(rtc, inst, dtype, cals, R, M, mode="persistent"):
@@ -483,8 +494,10 @@ def main():
         res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
                "alg_bytes_per_frame": per_frame}
         if kern_s:
-            kb = per_frame * per if path == "persistent" else mvm_alg_bytes(info, dtype)
-            res.update({"kernel": "k_frame_loop" if path == "persistent" else f"k_mvm<{dtype}>",
+            kb = (per_frame * per if path == "persistent"
+                  else mvm_next_alg_bytes(inst, info, dtype))
+            res.update({"kernel": ("k_frame_loop" if path == "persistent"
+                                   else f"k_mvm_next<{dtype}>"),
                         "kernel_us": kern_s * 1e6, "kernel_launches_timed": n_timed,
                         "kernel_alg_bytes": kb, "kernel_gbs": kb / kern_s / 1e9})
         log(f"bench: {dtype} {path}: {res}")

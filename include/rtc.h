@@ -221,8 +221,9 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
 
 /* MVM kernel timer (RTC_MODE_STREAM diagnostics).  With capacity > 0, every
- * `every`-th later rtc_process_frames frame records a pair of HIP events on
- * its stream around the reconstruction MVM launch, up to capacity pairs (each
+ * `every`-th later rtc_process_frames frame that has a successor in its batch
+ * records a pair of HIP events on its stream around its reconstruction MVM
+ * launch (which also forms the successor's slopes), up to capacity pairs (each
  * pair adds two queue packets, so sampling keeps the timed run close to an
  * untimed one); capacity 0 turns the timer off.  rtc_mvm_timing_read
  * synchronises on the last recorded pair, returns the number of timed

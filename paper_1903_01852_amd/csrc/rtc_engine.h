@@ -130,6 +130,7 @@ struct Instance {
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
     float *d_ref = nullptr;
     float *d_spad = nullptr, *d_sout = nullptr;
+    float *d_spad2 = nullptr;      // per-launch batch: slopes of the next frame
     int32_t *d_counts = nullptr;
     uint64_t *d_masks = nullptr;
     uint8_t *d_cm = nullptr;

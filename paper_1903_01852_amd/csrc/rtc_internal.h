@@ -276,6 +276,26 @@ constexpr int64_t kCacheResidentBytes = 192ll << 20;
 void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
                 const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
                 const float *x_pad, float *y_part, const MvmEpilogue &epi);
+// Slopes of the next frame, formed by extra workgroups of the current frame's
+// MVM launch (every SH unit, then every pyramid unit of the instance).
+struct NextSlopes {
+    const ShUnit *sh;
+    const PyrUnit *py;
+    int32_t n_sh, n_pyr;
+    FrameSet frames;
+    const float *sh_dark, *sh_flat, *sh_bg, *sh_thr;
+    const float *py_dark, *py_flat, *py_bg, *py_thr;
+    const float *ref;
+    float *s_pad, *s_out;
+    int32_t *counts;
+    uint64_t *masks;
+};
+// launch_mvm (reading x_pad) plus, in the same grid, the slopes of the next
+// frame into next.s_pad (a different buffer than x_pad).
+void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
+                     const Segment *segs, const Piece *pieces, int n_pieces, int n_rows,
+                     const float *x_pad, float *y_part, const MvmEpilogue &epi,
+                     const NextSlopes &next, const WfsParamSet &params);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
                      int n_s);
 

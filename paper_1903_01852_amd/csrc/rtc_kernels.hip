@@ -12,6 +12,9 @@
 //                  partials in fixed block order and applies the FP8 row scale,
 //                  the implicit POLC term and the leaky integrator
 //                  (sections 1.1, 3.4), or forms the POLC term itself.
+//  k_mvm_next<DT>  k_mvm of frame f with, in extra workgroups of the same
+//                  grid, the slopes of frame f + 1 (batch of device-resident
+//                  frames: the slopes' latency hides under the MVM's stream)
 //  k_dgemm_rd      one-off FP64 product M = R.D for implicit POLC
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -75,17 +78,15 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
     if (E.out != nullptr) E.out[r] = an;
 }
 
+// One wavefront of the split-K MVM: piece wv / n_tiles of tile wv % n_tiles.
 template <int DT, int U, bool NT>
-__global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
-                                             const KBlock *__restrict__ kbs,
-                                             const Segment *__restrict__ segs,
-                                             const Piece *__restrict__ pieces, int p0,
-                                             int n_pieces, int n_tiles, int n_rows,
-                                             const float *__restrict__ x,
-                                             float *__restrict__ y_part, MvmEpilogue E) {
+__device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__restrict__ cm,
+                                         const KBlock *__restrict__ kbs,
+                                         const Segment *__restrict__ segs,
+                                         const Piece *__restrict__ pieces, int p0, int n_pieces,
+                                         int n_tiles, int n_rows, const float *__restrict__ x,
+                                         float *__restrict__ y_part, const MvmEpilogue &E) {
     constexpr int kE = Elem<DT>::E;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (wv >= n_pieces * n_tiles) return;
     const int pi = wv / n_tiles;
     const int t = wv - pi * n_tiles;
@@ -125,6 +126,58 @@ __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
     if (old + (uint32_t)P.nseg != (uint32_t)E.n_parts) return;
     if (lane == 0) __hip_atomic_store(&E.count[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     tile_epilogue(E, y_part, n_rows, t, lane, nr);
+}
+
+template <int DT, int U, bool NT>
+__global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
+                                             const KBlock *__restrict__ kbs,
+                                             const Segment *__restrict__ segs,
+                                             const Piece *__restrict__ pieces, int p0,
+                                             int n_pieces, int n_tiles, int n_rows,
+                                             const float *__restrict__ x,
+                                             float *__restrict__ y_part, MvmEpilogue E) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    mvm_wave<DT, U, NT>(wv, lane, cm, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x, y_part,
+                        E);
+}
+
+// The MVM's workgroups come first, so they are dispatched first and stream
+// from the start; the slope workgroups fill the remaining wavefront slots.
+template <int DT, int U, bool NT>
+__global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm,
+                                                  const KBlock *__restrict__ kbs,
+                                                  const Segment *__restrict__ segs,
+                                                  const Piece *__restrict__ pieces, int n_pieces,
+                                                  int n_tiles, int n_rows,
+                                                  const float *__restrict__ x,
+                                                  float *__restrict__ y_part, MvmEpilogue E,
+                                                  int mvm_blocks, NextSlopes N,
+                                                  WfsParamSet params) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x);
+    if (blk < mvm_blocks) {
+        mvm_wave<DT, U, NT>(blk * 4 + wave, lane, cm, kbs, segs, pieces, 0, n_pieces, n_tiles,
+                            n_rows, x, y_part, E);
+        return;
+    }
+    const SlopeOut o{N.s_pad, N.s_out, N.counts, N.masks};
+    const int b = blk - mvm_blocks;
+    const int sh_blocks = (N.n_sh + 3) / 4;
+    if (b < sh_blocks) {
+        const int u = b * 4 + wave;
+        if (u >= N.n_sh) return;
+        const ShUnit d = N.sh[u];
+        sh_unit<STORE_PLAIN>(d, N.sh_thr[u], N.frames.f[d.wfs], params.w[d.wfs], N.sh_dark,
+                             N.sh_flat, N.sh_bg, N.ref, o, lane);
+    } else {
+        const int k = (b - sh_blocks) * 256 + (int)threadIdx.x;
+        if (k >= N.n_pyr) return;
+        const PyrUnit d = N.py[k];
+        pyr_unit<STORE_PLAIN>(d, k, N.n_pyr, N.py_thr[k], N.frames.f[d.wfs], params.w[d.wfs],
+                              N.py_dark, N.py_flat, N.py_bg, N.ref, o);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -233,6 +286,47 @@ void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const
     else
         launch_mvm_t<false>(st, dtype, c, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
                             y_part, epi);
+}
+
+template <bool NT>
+void launch_mvm_next_t(hipStream_t st, int dtype, const uint8_t *c, const KBlock *kbs,
+                       const Segment *segs, const Piece *pieces, int n_pieces, int n_tiles,
+                       int n_rows, const float *x_pad, float *y_part, const MvmEpilogue &epi,
+                       const NextSlopes &next, const WfsParamSet &params) {
+    const int mvm_blocks = (n_pieces * n_tiles + 3) / 4;
+    const dim3 grid(mvm_blocks + (next.n_sh + 3) / 4 + (next.n_pyr + 255) / 256), block(256);
+    switch (dtype) {
+    case RTC_CM_F32:
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, kbs, segs,
+                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
+                           next, params);
+        break;
+    case RTC_CM_BF16:
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, kbs, segs,
+                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
+                           next, params);
+        break;
+    default:
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, kbs, segs,
+                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
+                           next, params);
+        break;
+    }
+}
+
+void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
+                     const Segment *segs, const Piece *pieces, int n_pieces, int n_rows,
+                     const float *x_pad, float *y_part, const MvmEpilogue &epi,
+                     const NextSlopes &next, const WfsParamSet &params) {
+    if (n_pieces <= 0 || n_rows <= 0) return;
+    const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
+    const uint8_t *c = static_cast<const uint8_t *>(cm);
+    if (stream_nt)
+        launch_mvm_next_t<true>(st, dtype, c, kbs, segs, pieces, n_pieces, n_tiles, n_rows, x_pad,
+                                y_part, epi, next, params);
+    else
+        launch_mvm_next_t<false>(st, dtype, c, kbs, segs, pieces, n_pieces, n_tiles, n_rows,
+                                 x_pad, y_part, epi, next, params);
 }
 
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
