@@ -229,7 +229,7 @@ def _pct(v):
 
 
 def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s=1.5e-3,
-                    switch=None, zero_copy=False):
+                    switch=None, zero_copy=False, swap=None):
     """Paced serving loop from host memory for one or more instances of one
     engine, every sensor read out in parallel: chunk c of each sensor of an
     instance with n chunks is delivered (c + 1) * readout / n after the frame
@@ -239,7 +239,12 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     seen on the host) and the device part (the loop's own clock from the
     sentinel seeing the last chunk to the commands being published).
     zero_copy: chunks written in place into the lent ring slot (rtc_acquire_chunk,
-    rtc_commit_chunk) instead of copied in by rtc_submit_pixel_chunk."""
+    rtc_commit_chunk) instead of copied in by rtc_submit_pixel_chunk.
+    swap: (instance index, frame, R, M): a second matrix set staged by another
+    host thread from that frame on (rtc_stage_matrices, while frames run) and
+    swapped in (rtc_swap_matrices) at the first frame start after the staging
+    returned; adds per-phase latency statistics of that instance."""
+    import threading
     plan = []
     for idx, banks in streams:
         info = eng.infos[idx]
@@ -252,11 +257,23 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     plan.sort(key=lambda x: (x[0], x[1], x[2]))
     host = {idx: [] for idx, _ in streams}
     dev = {idx: [] for idx, _ in streams}
+    fno = []
     banks = dict(streams)
+    sw = {}
     t_next = time.perf_counter()
     for f in range(n_frames + warmup):
         if switch is not None and f == switch[1]:
             eng.set_params(switch[0], switch[2], switch[3])
+        if swap is not None and f == swap[1]:
+            def stage():
+                t0 = time.perf_counter()
+                eng.stage_matrices(swap[0], swap[2], M=swap[3])
+                sw["stage_s"] = time.perf_counter() - t0
+            th = threading.Thread(target=stage)
+            th.start()
+        if swap is not None and f > swap[1] and "f_eff" not in sw and not th.is_alive():
+            th.join()
+            sw["f_eff"] = eng.swap_matrices(swap[0])
         t_frame = t_next
         for t_c, idx, w, c, r0, r1 in plan:
             while time.perf_counter() < t_frame + t_c:
@@ -272,12 +289,30 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
             if f >= warmup:
                 host[idx].append((info["t_ready_ns"] - info["t_last_chunk_ns"]) / 1e3)
                 dev[idx].append((info["dev_ticks_cmd"] - info["dev_ticks_start"]) * 0.01)
+        if f >= warmup:
+            fno.append(f)
         t_next = t_frame + period_s
+    if swap is not None and "f_eff" not in sw:
+        th.join()
+        raise RuntimeError("the staged matrices were not swapped in before the last frame")
     out = {}
     for idx, _ in streams:
         r = _pct(host[idx])
         r["frames"] = len(host[idx])
         r["device"] = _pct(dev[idx])
+        if swap is not None and swap[0] == idx:
+            import numpy as np
+            fa, h, d = np.asarray(fno), np.asarray(host[idx]), np.asarray(dev[idx])
+            fe = sw["f_eff"]
+            phases = {"before_stage": fa < swap[1],
+                      "during_stage": (fa >= swap[1]) & (fa < fe),
+                      "first_20_after_swap": (fa >= fe) & (fa < fe + 20),
+                      "after_swap": fa >= fe}
+            r["swap"] = {"stage_s": sw["stage_s"], "stage_frame": swap[1], "f_eff": fe}
+            for k, m in phases.items():
+                if m.any():
+                    r["swap"][k] = {"frames": int(m.sum()), "host": _pct(h[m]),
+                                    "device": _pct(d[m])}
         out[idx] = r
     return out
 
@@ -538,6 +573,19 @@ def main():
                 eng.set_state(0, None, None, 0)
                 latency[dtype]["zero_copy"] = serving_latency(
                     eng, [(0, frames)], args.latency_frames, zero_copy=True)[0]
+                if dtype == args.dtype:
+                    # a second control matrix staged and swapped in while frames run
+                    import numpy as np
+                    import synth
+                    eng.set_state(0, None, None, 0)
+                    R2 = synth.gaussian_matrix(inst.n_act, R.shape[1], 1.0 / np.sqrt(R.shape[1]),
+                                               synth.seed_for(wl.index, 0, 77, 1), np.float32)
+                    M2 = None if M is None else synth.gaussian_matrix(
+                        inst.n_act, inst.n_act, 0.5 / np.sqrt(inst.n_act),
+                        synth.seed_for(wl.index, 0, 77, 2), np.float32)
+                    latency[dtype]["matrix_swap"] = serving_latency(
+                        eng, [(0, frames)], args.latency_frames,
+                        swap=(0, 100 + args.latency_frames // 5, R2, M2))[0]["swap"]
                 log(f"bench: {dtype} latency: {latency[dtype]}")
             eng.close()
 

@@ -143,6 +143,34 @@ rtc_status rtc_chunk_rows(rtc_engine *e, int32_t inst, int32_t wfs, int32_t chun
 rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R,
                              const double *D, const float *M);
 
+/* Control-matrix swap without stopping the loop (the paper's reconstructor
+ * change, section 3.2, without the blocking swap of the CPU prototype and
+ * without the latency spike it reports).  Every instance holds two slots of
+ * its matrices (R in the storage type, FP8 row scales, POLC M); frames use the
+ * active slot.
+ *
+ * rtc_stage_matrices encodes R, and M or D exactly as rtc_load_matrices does,
+ * into the inactive slot while frames keep running: the upload is a DMA copy
+ * through pinned staging memory owned by the engine, on a stream of its own.
+ * It first waits until no frame still uses the inactive slot (frames before
+ * the previous swap), and returns once the staged matrices are resident.
+ * Errors: RTC_E_STATE before rtc_load_matrices, while a swap is pending, and
+ * when D (not M) is given while the persistent serving loop runs (the FP64
+ * product allocates and synchronises the device); RTC_E_TIMEOUT if frames
+ * before the previous swap are not published within 5 s (e.g. a frame left
+ * half delivered); the command state is unchanged.
+ *
+ * rtc_swap_matrices makes the staged slot active from frame *f_eff_out, the
+ * first frame whose processing has not started (the rule of rtc_set_params);
+ * no frame is blocked and the command state carries over.  Frame f uses one
+ * slot for its reconstruction matrix and FP8 scales and for the POLC product
+ * on its commands, so the POLC term of frame f_eff is still formed with the
+ * previous M: p_f = M_(slot of f - 1) a_(f - 1).  RTC_E_STATE if nothing is
+ * staged or a swap is already pending.  One caller at a time per instance. */
+rtc_status rtc_stage_matrices(rtc_engine *e, int32_t inst, const float *R,
+                              const double *D, const float *M);
+rtc_status rtc_swap_matrices(rtc_engine *e, int32_t inst, uint64_t *f_eff_out);
+
 /* Detector calibration of one sensor (host FP32 arrays, each nullable):
  * dark, flat, bg: frame_h x frame_w (defaults 0, 1, 0); thr: one value per
  * subaperture (SH) or one value (pyramid) (default 0); ref: reference slopes,
@@ -211,8 +239,9 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
  * word whose bits 0..3 are I1..I4.  Synchronises the engine stream. */
 rtc_status rtc_read_slopes(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
                            uint64_t *masks);
-/* Stored control matrix in logical order (host): codes n_act x n_slopes of
- * 4, 2 or 1 bytes per element, and for FP8 the n_act row scales. */
+/* Stored control matrix of the active slot in logical order (host): codes
+ * n_act x n_slopes of 4, 2 or 1 bytes per element, and for FP8 the n_act row
+ * scales. */
 rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scales);
 
 /* Timing aid: enqueue the reconstruction MVM alone (every column block, on

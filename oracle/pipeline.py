@@ -281,7 +281,8 @@ def params_at(inst, f: int):
 
 def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
         M: np.ndarray | None = None, dequantized: bool = False,
-        keep_masks: bool = False, a0: np.ndarray | None = None):
+        keep_masks: bool = False, a0: np.ndarray | None = None,
+        p0: np.ndarray | None = None, f0: int = 0):
     """Run ``n_frames`` frames of one controller instance.
 
     frames[w] is a (B, H, W) uint16 bank for sensor w; frame f uses
@@ -289,6 +290,10 @@ def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
     ``dequantized=True`` reconstructs with the dequantised storage matrix
     (checks the kernel independently of quantisation error); otherwise with
     the float32 reference matrix.
+    ``a0`` is the command vector before the first frame (default zero);
+    ``p0`` the POLC term of the first frame (default M a0: the product on the
+    previous commands); frames are numbered from ``f0`` (bank index and
+    parameter switch), so that a run can continue another one.
     Returns a dict with commands (n_frames, n_act), slopes, counts and,
     optionally, masks.
     """
@@ -301,7 +306,7 @@ def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
     a = np.zeros(n_act) if a0 is None else np.asarray(a0, np.float64).copy()
     cmds = np.empty((n_frames, n_act))
     slopes_all, counts_all, masks_all = [], [], []
-    for f in range(n_frames):
+    for f in range(f0, f0 + n_frames):
         parts_s, parts_c, parts_m = [], [], []
         for w, wfs in enumerate(inst.wfs):
             bank = frames[w]
@@ -312,9 +317,11 @@ def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
         s = np.concatenate(parts_s)
         y = Rm @ s
         g, lam = params_at(inst, f)
-        p = (M @ a) if (inst.polc and M is not None) else None
+        p = None
+        if inst.polc and M is not None:
+            p = np.asarray(p0, np.float64) if (f == f0 and p0 is not None) else M @ a
         a = integrate(a, y, g, lam, p)
-        cmds[f] = a
+        cmds[f - f0] = a
         slopes_all.append(s)
         counts_all.append(np.concatenate(parts_c))
         if keep_masks:

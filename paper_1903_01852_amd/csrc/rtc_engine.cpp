@@ -329,12 +329,14 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_sout, I->n_slopes));
     TRY(dev_alloc(e, &I->d_counts, I->n_units));
     TRY(dev_alloc(e, &I->d_masks, I->mask_words));
-    TRY(dev_alloc(e, &I->d_cm, (size_t)I->cm_bytes));
-    TRY(dev_alloc(e, &I->d_scale, I->n_act));
-    if (I->d.polc) {
-        TRY(dev_alloc(e, &I->d_M, (size_t)I->m_bytes));
-        TRY(dev_alloc(e, &I->d_ppart, I->segm.size() * (size_t)I->n_act));
+    // two slots of every matrix: frames stream one while a staged set waits
+    // in the other (rtc_stage_matrices / rtc_swap_matrices)
+    for (int s = 0; s < 2; ++s) {
+        TRY(dev_alloc(e, &I->d_cm_s[s], (size_t)I->cm_bytes));
+        TRY(dev_alloc(e, &I->d_scale_s[s], I->n_act));
+        if (I->d.polc) TRY(dev_alloc(e, &I->d_M_s[s], (size_t)I->m_bytes));
     }
+    if (I->d.polc) TRY(dev_alloc(e, &I->d_ppart, I->segm.size() * (size_t)I->n_act));
     TRY(dev_alloc(e, &I->d_ypart, I->seg.size() * (size_t)I->n_act));
     TRY(dev_alloc(e, &I->d_a, 2 * (size_t)I->a_len));   // buffer 1: frame-loop parity
     TRY(dev_alloc(e, &I->d_p, I->n_act));
@@ -364,7 +366,8 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     HIP_TRY(hipMemcpy(I->d_sh_flat, ones.data(), sh_px * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(I->d_py_flat, ones.data(), 4 * I->py.size() * 4, hipMemcpyHostToDevice));
     std::vector<float> one_scale(I->n_act, 1.0f);
-    HIP_TRY(hipMemcpy(I->d_scale, one_scale.data(), I->n_act * 4, hipMemcpyHostToDevice));
+    for (int s = 0; s < 2; ++s)
+        HIP_TRY(hipMemcpy(I->d_scale_s[s], one_scale.data(), I->n_act * 4, hipMemcpyHostToDevice));
     // serving buffers
     for (auto &S : I->wfs) {
         // the persistent serving loop pads rows to 16 bytes so that every chunk
@@ -397,6 +400,19 @@ void settle_params(Instance *I, uint64_t f) {
     }
 }
 
+// Matrix slot of frame f: its reconstruction matrix and FP8 scales, and the
+// POLC matrix applied to its commands (forming frame f + 1's POLC term).
+int mat_slot(const Instance *I, uint64_t f) {
+    return (I->m_pending && f >= I->m_switch) ? 1 - I->m_active : I->m_active;
+}
+void settle_matrices(Instance *I, uint64_t f) {
+    if (I->m_pending && f >= I->m_switch) {
+        I->m_active = 1 - I->m_active;
+        I->m_pending = false;
+        I->m_staged = false;
+    }
+}
+
 // Coefficients of a_f = c1 a_{f-1} + g (y + p).
 void coeffs(const Instance *I, uint64_t f, float *c1, float *g) {
     const double gd = active_gain(I, f), ld = active_leak(I, f);
@@ -420,8 +436,9 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
     }
 }
 
-// Epilogue of the reconstruction MVM: integrate frame f's commands.
-MvmEpilogue integrate_epi(Instance *I, float c1, float g, float *out) {
+// Epilogue of the reconstruction MVM: integrate frame f's commands (matrix
+// slot ms: its FP8 row scales).
+MvmEpilogue integrate_epi(Instance *I, int ms, float c1, float g, float *out) {
     MvmEpilogue E{};
     E.mode = EPI_INTEGRATE;
     E.n_parts = (int)I->seg.size();
@@ -429,7 +446,7 @@ MvmEpilogue integrate_epi(Instance *I, float c1, float g, float *out) {
     E.kb_segs = I->d_kb_segs;
     E.count = I->d_count;
     E.p = I->d.polc ? I->d_p : nullptr;
-    E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr;
+    E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale_s[ms] : nullptr;
     E.a = I->d_a;
     E.out = out;
     E.c1 = c1;
@@ -438,8 +455,9 @@ MvmEpilogue integrate_epi(Instance *I, float c1, float g, float *out) {
 }
 
 // POLC term for the next frame: p = M a (section 3.4: formed after the
-// command is ready, off the latency path of the next frame).
-void enqueue_polc(Instance *I, hipStream_t st) {
+// command is ready, off the latency path of the next frame), with the POLC
+// matrix of slot ms (the slot of the frame whose commands a holds).
+void enqueue_polc(Instance *I, hipStream_t st, int ms) {
     if (!I->d.polc) return;
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
@@ -448,7 +466,7 @@ void enqueue_polc(Instance *I, hipStream_t st) {
     E.kb_segs = I->d_kbm_segs;
     E.count = I->d_count_m;
     E.y = I->d_p;
-    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M, I->d_kbm, I->d_segm, I->d_pieces_m, 0,
+    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_kbm, I->d_segm, I->d_pieces_m, 0,
                (int)I->pieces_m.size(), I->n_act, I->d_a, I->d_ppart, E);
 }
 
@@ -516,6 +534,95 @@ void encode_matrix(const Instance *I, const float *R, int dt, const float *inv_s
 }
 
 
+// Waits for a HIP event, at most kUploadTimeoutNs.
+constexpr int64_t kUploadTimeoutNs = 30'000'000'000LL;
+rtc_status wait_event(rtc_engine *e, hipEvent_t ev) {
+    const int64_t t0 = now_ns();
+    for (;;) {
+        const hipError_t q = hipEventQuery(ev);
+        if (q == hipSuccess) return RTC_OK;
+        if (q != hipErrorNotReady) return fail(e, RTC_E_DEVICE);
+        if (now_ns() - t0 > kUploadTimeoutNs) {
+            std::fprintf(stderr, "rtc: matrix upload did not complete\n");
+            return fail(e, RTC_E_DEVICE);
+        }
+        std::this_thread::yield();
+    }
+}
+
+// Copies n bytes from host memory to device memory through the two pinned
+// staging halves on the upload stream (DMA beside any frames in flight);
+// returns once the copy has landed.
+rtc_status upload(rtc_engine *e, void *dst, const void *src, size_t n) {
+    uint8_t *d = static_cast<uint8_t *>(dst);
+    const uint8_t *h = static_cast<const uint8_t *>(src);
+    size_t i = 0;
+    for (size_t off = 0; off < n; off += kUploadHalf, ++i) {
+        const int k = (int)(i & 1);
+        TRY(wait_event(e, e->up_done[k]));
+        const size_t m = std::min(kUploadHalf, n - off);
+        std::memcpy(e->h_up + k * kUploadHalf, h + off, m);
+        HIP_TRY(hipMemcpyAsync(d + off, e->h_up + k * kUploadHalf, m, hipMemcpyHostToDevice,
+                               e->up_stream));
+        HIP_TRY(hipEventRecord(e->up_done[k], e->up_stream));
+    }
+    TRY(wait_event(e, e->up_done[0]));
+    TRY(wait_event(e, e->up_done[1]));
+    return RTC_OK;
+}
+
+// Encodes R (and M, or M = R.D formed once in FP64 on the device) into matrix
+// slot `slot`.
+rtc_status put_matrices(rtc_engine *e, Instance *I, int slot, const float *R, const double *D,
+                        const float *M) {
+    const int na = I->n_act, ns = I->n_slopes;
+    const int dt = I->d.cm_dtype;
+    std::vector<float> scale(na, 1.0f);
+    if (dt == RTC_CM_FP8) {
+        for (int r = 0; r < na; ++r) {
+            float amax = 0.0f;
+            const float *row = R + (size_t)r * ns;
+            for (int c = 0; c < ns; ++c) amax = std::max(amax, std::fabs(row[c]));
+            if (!std::isfinite(amax)) return RTC_E_INVAL;
+            scale[r] = amax > 0.0f ? amax / 448.0f : 1.0f;
+        }
+    }
+    std::vector<uint8_t> enc;
+    encode_matrix(I, R, dt, nullptr, scale, enc, I->kb, ns, I->cm_bytes);
+    TRY(upload(e, I->d_cm_s[slot], enc.data(), enc.size()));
+    TRY(upload(e, I->d_scale_s[slot], scale.data(), (size_t)na * 4));
+    enc.clear();
+    enc.shrink_to_fit();
+    if (I->d.polc) {
+        std::vector<float> Mf((size_t)na * na);
+        if (M) {
+            std::memcpy(Mf.data(), M, Mf.size() * 4);
+        } else {
+            // M = R.D in FP64 on the device, rounded once to FP32
+            float *dR = nullptr;
+            double *dD = nullptr, *dM = nullptr;
+            HIP_TRY(hipMalloc(&dR, (size_t)na * ns * 4));
+            HIP_TRY(hipMalloc(&dD, (size_t)ns * na * 8));
+            HIP_TRY(hipMalloc(&dM, (size_t)na * na * 8));
+            HIP_TRY(hipMemcpy(dR, R, (size_t)na * ns * 4, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(dD, D, (size_t)ns * na * 8, hipMemcpyHostToDevice));
+            launch_dgemm_rd(e->stream, dR, dD, dM, na, ns);
+            TRY(last_error(e));
+            HIP_TRY(hipStreamSynchronize(e->stream));
+            std::vector<double> Md((size_t)na * na);
+            HIP_TRY(hipMemcpy(Md.data(), dM, Md.size() * 8, hipMemcpyDeviceToHost));
+            (void)hipFree(dR);
+            (void)hipFree(dD);
+            (void)hipFree(dM);
+            for (size_t i = 0; i < Md.size(); ++i) Mf[i] = (float)Md[i];
+        }
+        std::vector<float> one(na, 1.0f);
+        encode_matrix(I, Mf.data(), RTC_CM_F32, nullptr, one, enc, I->kbm, na, I->m_bytes);
+        TRY(upload(e, I->d_M_s[slot], enc.data(), enc.size()));
+    }
+    return RTC_OK;
+}
+
 // =========================================================================
 extern "C" {
 
@@ -562,6 +669,18 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
     if (hipSetDevice(e->device) != hipSuccess) return bail(RTC_E_DEVICE);
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(RTC_E_DEVICE);
+    if (hipStreamCreateWithFlags(&e->up_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(RTC_E_DEVICE);
+    for (int k = 0; k < 2; ++k)
+        if (hipEventCreateWithFlags(&e->up_done[k], hipEventDisableTiming) != hipSuccess)
+            return bail(RTC_E_DEVICE);
+    {
+        void *q = nullptr;
+        if (hipHostMalloc(&q, 2 * kUploadHalf, hipHostMallocDefault) != hipSuccess)
+            return bail(RTC_E_NOMEM);
+        e->pinned.push_back(q);
+        e->h_up = static_cast<uint8_t *>(q);
+    }
     for (int i = 0; i < desc->n_inst; ++i) {
         Instance *I = new (std::nothrow) Instance();
         if (!I) return bail(RTC_E_NOMEM);
@@ -617,8 +736,12 @@ rtc_status rtc_destroy(rtc_engine *e) {
         for (hipEvent_t ev : I->mvm_ev) (void)hipEventDestroy(ev);
         delete I;
     }
+    if (e->up_stream) (void)hipStreamSynchronize(e->up_stream);
     for (auto &b : e->allocs) (void)hipFree(b.p);
     for (void *p : e->pinned) (void)hipHostFree(p);
+    for (hipEvent_t ev : e->up_done)
+        if (ev) (void)hipEventDestroy(ev);
+    if (e->up_stream) (void)hipStreamDestroy(e->up_stream);
     if (e->stream) (void)hipStreamDestroy(e->stream);
     delete e;
     return RTC_OK;
@@ -662,51 +785,11 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     HIP_TRY(hipSetDevice(e->device));
     if (e->mode == RTC_MODE_PERSISTENT) TRY(persist_quiesce(e));
     HIP_TRY(hipDeviceSynchronize());
-    const int na = I->n_act, ns = I->n_slopes;
-    const int dt = I->d.cm_dtype;
-    std::vector<float> scale(na, 1.0f);
-    if (dt == RTC_CM_FP8) {
-        for (int r = 0; r < na; ++r) {
-            float amax = 0.0f;
-            const float *row = R + (size_t)r * ns;
-            for (int c = 0; c < ns; ++c) amax = std::max(amax, std::fabs(row[c]));
-            if (!std::isfinite(amax)) return RTC_E_INVAL;
-            scale[r] = amax > 0.0f ? amax / 448.0f : 1.0f;
-        }
-    }
-    std::vector<uint8_t> enc;
-    encode_matrix(I, R, dt, nullptr, scale, enc, I->kb, ns, I->cm_bytes);
-    HIP_TRY(hipMemcpy(I->d_cm, enc.data(), enc.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(I->d_scale, scale.data(), na * 4, hipMemcpyHostToDevice));
-    enc.clear();
-    enc.shrink_to_fit();
-    if (I->d.polc) {
-        std::vector<float> Mf((size_t)na * na);
-        if (M) {
-            std::memcpy(Mf.data(), M, Mf.size() * 4);
-        } else {
-            // M = R.D in FP64 on the device, rounded once to FP32
-            float *dR = nullptr;
-            double *dD = nullptr, *dM = nullptr;
-            HIP_TRY(hipMalloc(&dR, (size_t)na * ns * 4));
-            HIP_TRY(hipMalloc(&dD, (size_t)ns * na * 8));
-            HIP_TRY(hipMalloc(&dM, (size_t)na * na * 8));
-            HIP_TRY(hipMemcpy(dR, R, (size_t)na * ns * 4, hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(dD, D, (size_t)ns * na * 8, hipMemcpyHostToDevice));
-            launch_dgemm_rd(e->stream, dR, dD, dM, na, ns);
-            TRY(last_error(e));
-            HIP_TRY(hipStreamSynchronize(e->stream));
-            std::vector<double> Md((size_t)na * na);
-            HIP_TRY(hipMemcpy(Md.data(), dM, Md.size() * 8, hipMemcpyDeviceToHost));
-            (void)hipFree(dR);
-            (void)hipFree(dD);
-            (void)hipFree(dM);
-            for (size_t i = 0; i < Md.size(); ++i) Mf[i] = (float)Md[i];
-        }
-        std::vector<float> one(na, 1.0f);
-        encode_matrix(I, Mf.data(), RTC_CM_F32, nullptr, one, enc, I->kbm, na, I->m_bytes);
-        HIP_TRY(hipMemcpy(I->d_M, enc.data(), enc.size(), hipMemcpyHostToDevice));
-    }
+    // any staged or pending swap is dropped; the matrices go to the active slot
+    I->m_staged = false;
+    I->m_pending = false;
+    TRY(put_matrices(e, I, I->m_active, R, D, M));
+    const int na = I->n_act;
     HIP_TRY(hipMemset(I->d_p, 0, (size_t)na * 4));
     HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
@@ -717,6 +800,52 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     I->cur_started = false;
     if (e->mode == RTC_MODE_PERSISTENT) persist_reset(I);
     I->loaded = true;
+    return RTC_OK;
+}
+
+rtc_status rtc_stage_matrices(rtc_engine *e, int32_t inst, const float *R, const double *D,
+                              const float *M) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!R) return RTC_E_INVAL;
+    if (I->d.polc && !D && !M) return RTC_E_INVAL;
+    HIP_TRY(hipSetDevice(e->device));
+    int slot;
+    {
+        std::lock_guard<std::mutex> lk(I->mu);
+        if (!I->loaded || I->m_pending) return RTC_E_STATE;
+        slot = 1 - I->m_active;
+        I->m_staged = false;
+    }
+    const bool serving = e->mode == RTC_MODE_PERSISTENT && e->pe.running && e->pe.serving;
+    // the FP64 product M = R.D allocates and synchronises the device
+    if (I->d.polc && !M && serving) return RTC_E_STATE;
+    // frames still streaming the inactive slot (those before the last swap)
+    // must be done before it is overwritten
+    if (e->mode == RTC_MODE_PERSISTENT)
+        TRY(persist_wait_matrix_free(e, I));
+    else
+        HIP_TRY(hipDeviceSynchronize());
+    TRY(put_matrices(e, I, slot, R, M ? nullptr : D, M));
+    std::lock_guard<std::mutex> lk(I->mu);
+    I->m_staged = true;
+    return RTC_OK;
+}
+
+rtc_status rtc_swap_matrices(rtc_engine *e, int32_t inst, uint64_t *f_eff_out) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    std::lock_guard<std::mutex> lk(I->mu);
+    if (!I->m_staged || I->m_pending) return RTC_E_STATE;
+    uint64_t f = I->next_frame;
+    if (I->cur_frame != ~0ull && I->cur_started) f = std::max(f, I->cur_frame + 1);
+    I->m_switch = f;
+    I->m_pending = true;
+    if (f_eff_out) *f_eff_out = f;
+    if (e->mode == RTC_MODE_PERSISTENT) {
+        PersistInstState &P = I->ps;
+        persist_mswap(I, I->cur_started ? P.q_cur + 1 : P.seq, 1 - I->m_active);
+    }
     return RTC_OK;
 }
 
@@ -893,8 +1022,10 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         float c1, g;
         coeffs(I, I->next_frame, &c1, &g);
         settle_params(I, I->next_frame);
+        const int ms = mat_slot(I, I->next_frame);
+        settle_matrices(I, I->next_frame);
         const MvmEpilogue E =
-            integrate_epi(I, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr);
+            integrate_epi(I, ms, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr);
         if (f + 1 < n_frames) {
             NextSlopes N{};
             N.sh = I->d_sh;
@@ -919,15 +1050,15 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             const bool timed = 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size() &&
                                I->mvm_ev_count++ % (uint64_t)I->mvm_ev_every == 0;
             if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
-            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg,
+            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
                             I->d_pieces, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E, N,
                             I->params);
             if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used++ + 1], st));
         } else {
-            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_pieces,
-                       0, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E);
+            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
+                       I->d_pieces, 0, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E);
         }
-        enqueue_polc(I, st);
+        enqueue_polc(I, st, ms);
         if (f + 1 < n_frames) TRY(copy_out(f + 1));
         I->next_frame++;
     }
@@ -951,8 +1082,8 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     E.y = I->d_yscratch;
     std::lock_guard<std::mutex> lk(I->mu);
     for (int i = 0; i < n_iter; ++i)
-        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_pieces, 0,
-                   (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
+        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->m_active], I->d_kb, I->d_seg,
+                   I->d_pieces, 0, (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
     return last_error(e);
 }
 
@@ -1044,7 +1175,7 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
     HIP_TRY(hipStreamSynchronize(e->stream));
     if (codes) {
         std::vector<uint8_t> enc((size_t)I->cm_bytes);
-        HIP_TRY(hipMemcpy(enc.data(), I->d_cm, enc.size(), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(enc.data(), I->d_cm_s[I->m_active], enc.size(), hipMemcpyDeviceToHost));
         const int es = elem_size(I->d.cm_dtype), E = 16 / es;
         const int ns = I->n_slopes;
         uint8_t *dst = static_cast<uint8_t *>(codes);
@@ -1064,7 +1195,8 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
             }
         }
     }
-    if (scales) HIP_TRY(hipMemcpy(scales, I->d_scale, I->n_act * 4, hipMemcpyDeviceToHost));
+    if (scales)
+        HIP_TRY(hipMemcpy(scales, I->d_scale_s[I->m_active], I->n_act * 4, hipMemcpyDeviceToHost));
     return RTC_OK;
 }
 
@@ -1128,6 +1260,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         I->cur_started = false;
         for (auto &W : I->wfs) W.next_chunk = 0;
         coeffs(I, frame, &I->frame_c1, &I->frame_g);
+        I->frame_mslot = mat_slot(I, frame);
         sl.frame = frame;
         sl.complete = false;
         sl.dropped = false;
@@ -1151,9 +1284,9 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             fs.f[w] = I->wfs[w].d_ring + (size_t)slot * I->wfs[w].d.frame_h * I->wfs[w].d.frame_w;
         const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
-        launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm, I->d_kb, I->d_seg, I->d_single,
-                   I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad, I->d_ypart,
-                   integrate_epi(I, I->frame_c1, I->frame_g, nullptr));
+        launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_kb,
+                   I->d_seg, I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
+                   I->d_ypart, integrate_epi(I, I->frame_mslot, I->frame_c1, I->frame_g, nullptr));
     }
     S.next_chunk++;
     bool all = true;
@@ -1162,9 +1295,10 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         FrameSlot &sl = I->slots[frame % I->slots.size()];
         float *mail = I->h_mail + (size_t)slot * I->n_act;
         settle_params(I, frame);
+        settle_matrices(I, frame);
         HIP_TRY(hipMemcpyAsync(mail, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost, e->stream));
         HIP_TRY(hipEventRecord(sl.done, e->stream));
-        enqueue_polc(I, e->stream);
+        enqueue_polc(I, e->stream, I->frame_mslot);
         sl.t_last_chunk = t_in;
         sl.complete = true;
         I->next_frame = frame + 1;

@@ -93,6 +93,8 @@ struct PersistInstState {
     std::vector<int64_t> slot_t_last;   // host clock at its last chunk
     std::vector<uint8_t> slot_dropped;
     uint64_t param_word = 0;       // (q_switch << 1) | staged slot, as last written
+    uint64_t mword = 0;            // (q_mswitch << 1) | slot, as last written
+    uint64_t mq_last = 0;          // frames before this sequence number may use the inactive matrix slot
     int w0 = 0, w1 = 0;            // worker range of the running loop
 };
 
@@ -133,9 +135,16 @@ struct Instance {
     float *d_spad2 = nullptr;      // per-launch batch: slopes of the next frame
     int32_t *d_counts = nullptr;
     uint64_t *d_masks = nullptr;
-    uint8_t *d_cm = nullptr;
-    float *d_scale = nullptr;
-    uint8_t *d_M = nullptr;
+    // matrices, two slots: frames use slot m_active; a staged matrix set in
+    // the other slot becomes active at frame m_switch (rtc_swap_matrices)
+    uint8_t *d_cm_s[2] = {nullptr, nullptr};
+    float *d_scale_s[2] = {nullptr, nullptr};
+    uint8_t *d_M_s[2] = {nullptr, nullptr};
+    int m_active = 0;
+    bool m_staged = false;         // the inactive slot holds matrices not yet swapped in
+    bool m_pending = false;        // a swap takes effect at frame m_switch
+    uint64_t m_switch = 0;
+    int frame_mslot = 0;           // slot of the frame in progress (per-launch serving)
     float *d_ypart = nullptr, *d_ppart = nullptr;
     float *d_a = nullptr;          // command state, padded to the POLC block size
     float *d_p = nullptr;          // POLC term for the next frame, M a
@@ -187,6 +196,9 @@ struct rtc_engine {
     int ring_depth = 2;
     int mode = RTC_MODE_STREAM;
     hipStream_t stream = nullptr;
+    hipStream_t up_stream = nullptr;   // matrix uploads beside running frames
+    uint8_t *h_up = nullptr;           // pinned staging of those uploads (2 halves)
+    hipEvent_t up_done[2] = {nullptr, nullptr};
     std::vector<Instance *> inst;
     std::vector<DevBuf> allocs;
     std::vector<void *> pinned;
@@ -244,12 +256,16 @@ inline int64_t now_ns() {
     clock_gettime(CLOCK_MONOTONIC, &ts);
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
+// Matrix uploads go through two pinned staging halves of this size.
+constexpr size_t kUploadHalf = 32u << 20;
 inline int elem_size(int dt) { return dt == RTC_CM_F32 ? 4 : dt == RTC_CM_BF16 ? 2 : 1; }
 inline int elems_per_vec(int dt) { return 16 / elem_size(dt); }
 
 // rtc_engine.cpp
 void coeffs(const Instance *I, uint64_t f, float *c1, float *g);
 void settle_params(Instance *I, uint64_t f);
+int mat_slot(const Instance *I, uint64_t f);
+void settle_matrices(Instance *I, uint64_t f);
 rtc_status check(rtc_engine *e, int32_t inst, Instance **out);
 
 // rtc_serve.cpp (persistent frame loop)
@@ -264,6 +280,8 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
                          const int64_t *frame_stride, int32_t n_frames, float *cmds,
                          float *slopes, int32_t *counts, hipStream_t st);
 rtc_status persist_params(rtc_engine *e, Instance *I);
+void persist_mswap(Instance *I, uint64_t q_switch, int slot);
+rtc_status persist_wait_matrix_free(rtc_engine *e, Instance *I);
 rtc_status persist_quiesce(rtc_engine *e);
 rtc_status persist_acquire(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,
                            uint16_t **rows, int32_t *pitch);

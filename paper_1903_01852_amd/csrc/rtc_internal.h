@@ -128,17 +128,23 @@ struct KbWork {
 };
 
 // Frame coefficients a = c1 a + g (y + p): slot A for frames < q_switch,
-// slot B from q_switch on.
+// slot B from q_switch on.  Matrices: slot mslot[0] for frames < q_mswitch,
+// mslot[1] from q_mswitch on.
 struct Coef {
     float c1[2], g[2];
     uint64_t q_switch;
+    uint64_t q_mswitch;
+    int32_t mslot[2];
 };
 
 // Host-visible parameter block of a serving instance (pinned).  The host
 // writes the staged slot's values, then `word` = (q_switch << 1) | staged.
+// `mword` = (q_mswitch << 1) | s: frames from q_mswitch on use matrix slot s,
+// earlier frames slot 1 - s.
 struct ParamBlock {
     float c1[2], g[2];
     uint64_t word;
+    uint64_t mword;
 };
 
 struct FrameTel {
@@ -167,13 +173,14 @@ struct PersistInst {
     const float *sh_dark, *sh_flat, *sh_bg, *sh_thr;
     const float *py_dark, *py_flat, *py_bg, *py_thr;
     const float *ref;
-    // reconstruction matrix
-    const uint8_t *cm;
-    const float *scale;            // FP8 row scales or null
+    // reconstruction matrix, two slots (a staged matrix becomes active at a
+    // frame boundary)
+    const uint8_t *cm[2];
+    const float *scale[2];         // FP8 row scales or null
     int32_t dtype, n_act, n_tiles, polc;
     int32_t stream_nt, r7;         // the engine's matrices exceed the Infinity Cache
     // POLC
-    const uint8_t *M;
+    const uint8_t *M[2];           // slot s pairs with cm[s]
     const KBlock *kbm;
     const Segment *segm;
     const int2 *kbm_segs;

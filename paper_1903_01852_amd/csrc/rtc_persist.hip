@@ -248,14 +248,30 @@ __device__ __forceinline__ float mvm_partial(InstRef I, const uint8_t *cm, const
     return stream_part<DT, false>(cm, K, S, t, nr, lane, lds);
 }
 
-__device__ __forceinline__ float seg_partial(InstRef I, const KBlock &K,
+__device__ __forceinline__ float seg_partial(InstRef I, int ms, const KBlock &K,
                                              const Segment &S, int t, int nr, int lane,
                                              const RTC_LDS float *lds) {
+    const uint8_t *cm = I.cm[ms];   // read from the descriptor at use: no registers held
     switch (I.dtype) {
-    case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(I, I.cm, K, S, t, nr, lane, lds);
-    case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(I, I.cm, K, S, t, nr, lane, lds);
-    default: return mvm_partial<RTC_CM_FP8>(I, I.cm, K, S, t, nr, lane, lds);
+    case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(I, cm, K, S, t, nr, lane, lds);
+    case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(I, cm, K, S, t, nr, lane, lds);
+    default: return mvm_partial<RTC_CM_FP8>(I, cm, K, S, t, nr, lane, lds);
     }
+}
+
+// Matrix slot of frame q: its reconstruction matrix and FP8 scales, and the
+// POLC matrix applied to its commands (forming frame q + 1's POLC term).
+// Serving reads the device mirror of
+// the host's switch word, which the sentinel refreshes before it mirrors any
+// doorbell that follows a swap.
+__device__ __forceinline__ int mat_slot(InstRef I, uint64_t q) {
+    if (I.serving) {
+        const ParamBlock *pb = I.param_mirror;
+        const uint64_t w = ld_agent64(&pb->mword);
+        const int s = (int)(w & 1);
+        return q >= (w >> 1) ? s : 1 - s;
+    }
+    return q >= I.coef.q_mswitch ? I.coef.mslot[1] : I.coef.mslot[0];
 }
 
 // Frame coefficients for frame q.
@@ -289,7 +305,7 @@ __device__ void sentinel(InstRef I, ArgsRef A, int lane) {
         if (S.wfs == lane) nch = max(nch, S.chunk + 1);
     }
     uint64_t last = ~0ull;
-    uint64_t last_word = ~0ull;
+    uint64_t last_word = ~0ull, last_mword = ~0ull;
     uint64_t last_drop = ~0ull;
     uint64_t seen_q = I.q_begin;   // next frame whose last chunk has not been stamped
     uint64_t t_change = wall_clock64();
@@ -299,7 +315,8 @@ __device__ void sentinel(InstRef I, ArgsRef A, int lane) {
         // parameters are read after the doorbells and mirrored before them:
         // a doorbell seen here was rung after any parameter change it follows
         const uint64_t word = ld_sys64(&I.params->word);
-        if (word != last_word) {
+        const uint64_t mword = ld_sys64(&I.params->mword);
+        if (word != last_word || mword != last_mword) {
             if (lane < 2) {
                 const float c1 = __hip_atomic_load(gbl(&I.params->c1[lane]), __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_SYSTEM);
@@ -311,8 +328,12 @@ __device__ void sentinel(InstRef I, ArgsRef A, int lane) {
                                    __HIP_MEMORY_SCOPE_AGENT);
             }
             drain();
-            if (lane == 0) st_agent64(&I.param_mirror->word, word);
+            if (lane == 0) {
+                st_agent64(&I.param_mirror->word, word);
+                st_agent64(&I.param_mirror->mword, mword);
+            }
             last_word = word;
+            last_mword = mword;
         }
         // drop marks likewise: the host writes a frame's mark before the
         // doorbells that complete it
@@ -412,7 +433,8 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
     if (row) {
         float c1, g;
         frame_coef(I, q, c1, g);
-        if (I.scale != nullptr) y *= gbl(I.scale)[r];
+        const float *scale = I.dtype == RTC_CM_FP8 ? I.scale[mat_slot(I, q)] : nullptr;
+        if (scale != nullptr) y *= gbl(scale)[r];
         if (I.polc) y += load_agent(I.p + r);
         const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
         bool dropped = false;
@@ -485,6 +507,8 @@ __device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
         return false;
     const float *aq = a_buf(I, q);
     float *part = I.p_part[dslot(q)];
+    // the POLC matrix of frame q's slot: the product completes frame q
+    const int ms = mat_slot(I, q);
     for (; j < n_tasks; j += nw) {
         const int sg = j / I.n_tiles;
         const int t = j - sg * I.n_tiles;
@@ -497,7 +521,7 @@ __device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
             !wait_geq(slot(I.p_done, t), q - kDepth + 1, A, A.dep_watchdog))
             return false;
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = mvm_partial<RTC_CM_F32>(I, I.M, K, S, t, nr, lane, lds);
+        const float v = mvm_partial<RTC_CM_F32>(I, I.M[ms], K, S, t, nr, lane, lds);
         if (lane < nr) st_agent(part + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         lds_done();
         drain();
@@ -591,6 +615,7 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
     const float *spad = I.s_pad[dslot(q)];
     const int E = vec_elems(I.dtype);
     const KBlock K = ldc(I.kbs + kb);
+    const int ms = mat_slot(I, q);
     int staged = -1;
     for (; m < end && budget > 0; m += nw, --budget) {
         const int jm = m - W.mvm_base;
@@ -604,7 +629,7 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
             staged = sg;
         }
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = seg_partial(I, K, Sg, t, nr, lane, lds);
+        const float v = seg_partial(I, ms, K, Sg, t, nr, lane, lds);
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
         const int jkb = I.serving ? kb : 0;

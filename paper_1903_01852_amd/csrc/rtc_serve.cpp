@@ -68,14 +68,16 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.py_bg = I->d_py_bg;
     d.py_thr = I->d_py_thr;
     d.ref = I->d_ref;
-    d.cm = I->d_cm;
-    d.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale : nullptr;
+    for (int k = 0; k < 2; ++k) {
+        d.cm[k] = I->d_cm_s[k];
+        d.scale[k] = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale_s[k] : nullptr;
+        d.M[k] = I->d_M_s[k];
+    }
     d.dtype = I->d.cm_dtype;
     d.n_act = I->n_act;
     d.n_tiles = I->n_tiles;
     d.stream_nt = I->stream_nt ? 1 : 0;
     d.polc = I->d.polc;
-    d.M = I->d_M;
     d.kbm = I->d_kbm;
     d.segm = I->d_segm;
     d.kbm_segs = I->d_kbm_segs;
@@ -454,6 +456,35 @@ void persist_reset(Instance *I) {
     std::fill(P.slot_frame.begin(), P.slot_frame.end(), ~0ull);
     std::fill(P.slot_dropped.begin(), P.slot_dropped.end(), 0);
     (void)persist_params(nullptr, I);
+    persist_mswap(I, ~0ull >> 2, 1 - I->m_active);   // every frame on the active slot
+    P.mq_last = 0;
+}
+
+// Matrix slot switch word: frames from sequence number q_switch on use `slot`,
+// earlier ones the other slot.
+void persist_mswap(Instance *I, uint64_t q_switch, int slot) {
+    PersistInstState &P = I->ps;
+    P.mword = (q_switch << 1) | (uint64_t)slot;
+    if (q_switch < (~0ull >> 2)) P.mq_last = q_switch;
+    store_release(&P.params->mword, P.mword);
+}
+
+// Waits until no frame streams the inactive matrix slot: every frame before
+// the last swap published and, with POLC, its POLC product formed.
+rtc_status persist_wait_matrix_free(rtc_engine *e, Instance *I) {
+    PersistEngine &pe = e->pe;
+    if (!(pe.running && pe.serving)) {
+        HIP_TRY(hipDeviceSynchronize());
+        return RTC_OK;
+    }
+    PersistInstState &P = I->ps;
+    const int64_t t0 = now_ns();
+    while (load_acquire(P.cmd_seq) < P.mq_last ||
+           (I->d.polc && load_acquire(P.pol_seq) < P.mq_last)) {
+        if (now_ns() - t0 > kStopTimeoutNs) return RTC_E_TIMEOUT;
+        std::this_thread::yield();
+    }
+    return RTC_OK;
 }
 
 // Coefficients of both parameter slots into the pinned block, switching at
@@ -508,6 +539,7 @@ rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int ch
                     store_release(P.doorbell + s, db_word(qd, I->wfs[s].d.n_chunks));
         }
         if (I->pending && frame >= I->f_switch) settle_params(I, frame);
+        settle_matrices(I, frame);
         P.q_cur = q;
         P.seq = q + 1;
         const size_t slot = q % P.slot_frame.size();
@@ -674,6 +706,18 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
         if (fs < f0 + (uint64_t)n_frames) {
             d.coef.q_switch = d.q_begin + (fs - f0);
             settle_params(I, fs);
+        }
+    }
+    // matrices: the active slot, then the staged one from a pending swap's
+    // frame on, if that frame is in the batch
+    d.coef.mslot[0] = I->m_active;
+    d.coef.mslot[1] = 1 - I->m_active;
+    d.coef.q_mswitch = ~0ull;
+    if (I->m_pending) {
+        const uint64_t fs = std::max(I->m_switch, f0);
+        if (fs < f0 + (uint64_t)n_frames) {
+            d.coef.q_mswitch = d.q_begin + (fs - f0);
+            settle_matrices(I, fs);
         }
     }
     d.cmds_out = cmds;

@@ -30,7 +30,8 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_set_state", "rtc_submit_pixel_chunk", "rtc_wait_commands",
            "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
            "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read",
-           "rtc_acquire_chunk", "rtc_commit_chunk")
+           "rtc_acquire_chunk", "rtc_commit_chunk", "rtc_stage_matrices",
+           "rtc_swap_matrices")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -94,6 +95,8 @@ def lib() -> C.CDLL:
         L.rtc_get_info.argtypes = [vp, i32, C.POINTER(InstanceInfoC)]
         L.rtc_chunk_rows.argtypes = [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
         L.rtc_load_matrices.argtypes = [vp, i32, vp, vp, vp]
+        L.rtc_stage_matrices.argtypes = [vp, i32, vp, vp, vp]
+        L.rtc_swap_matrices.argtypes = [vp, i32, C.POINTER(u64)]
         L.rtc_load_calibration.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.rtc_set_params.argtypes = [vp, i32, C.c_float, C.c_float, C.POINTER(u64)]
         L.rtc_get_state.argtypes = [vp, i32, vp, vp, C.POINTER(u64)]
@@ -236,6 +239,18 @@ class Engine:
         M = None if M is None else np.ascontiguousarray(M, np.float32)
         _ok(lib().rtc_load_matrices(self._h, inst, _ptr(R), _ptr(D), _ptr(M)),
             "rtc_load_matrices")
+
+    def stage_matrices(self, inst: int, R, D=None, M=None):
+        R = np.ascontiguousarray(R, np.float32)
+        D = None if D is None else np.ascontiguousarray(D, np.float64)
+        M = None if M is None else np.ascontiguousarray(M, np.float32)
+        _ok(lib().rtc_stage_matrices(self._h, inst, _ptr(R), _ptr(D), _ptr(M)),
+            "rtc_stage_matrices")
+
+    def swap_matrices(self, inst: int) -> int:
+        f = C.c_uint64()
+        _ok(lib().rtc_swap_matrices(self._h, inst, C.byref(f)), "rtc_swap_matrices")
+        return f.value
 
     def load_calibration(self, inst: int, wfs: int, dark=None, flat=None, bg=None, thr=None,
                          ref=None):

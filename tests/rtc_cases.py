@@ -67,12 +67,27 @@ class Case:
                           keep_masks=keep_masks)
 
 
-def run_batch(eng, idx: int, case: Case, n: int | None = None):
-    """Device-resident batch through rtc_process_frames; returns numpy arrays."""
+def mid_case(polc: bool, n_frames: int = 30, polc_m: str = "from_D", index: int = 92) -> Case:
+    """A mid-size instance: one 24x24 Shack-Hartmann sensor (10 px, 240x240
+    frame in 6 chunks), 700 actuators."""
+    wfs = synth.ShWfs(nsub=24, px=10, obs=0.28, frame_h=240, frame_w=240, n_chunks=6)
+    inst = synth.Instance(f"mid{index}", (wfs,), 700, ("f32",), polc=polc, gain=0.4, leak=0.01)
+    wl = synth.Workload(index, f"mid{index}", (inst,), n_frames=n_frames, bank=n_frames)
+    synth.workloads.WORKLOADS[wl.name] = wl
+    try:
+        return Case(wl.name, n_frames=n_frames, polc_m=polc_m)
+    finally:
+        del synth.workloads.WORKLOADS[wl.name]
+
+
+def run_batch(eng, idx: int, case: Case, n: int | None = None, first: int = 0):
+    """Device-resident batch through rtc_process_frames of bank frames
+    [first, first + n); returns numpy arrays."""
     import torch
-    n = case.n if n is None else n
+    n = case.n - first if n is None else n
     info = eng.infos[idx]
-    dfr = [torch.from_numpy(np.ascontiguousarray(f[:n])).cuda() for f in case.frames]
+    dfr = [torch.from_numpy(np.ascontiguousarray(f[first:first + n])).cuda()
+           for f in case.frames]
     cmds = torch.zeros((n, info["n_act"]), dtype=torch.float32, device="cuda")
     slopes = torch.zeros((n, info["n_slopes"]), dtype=torch.float32, device="cuda")
     counts = torch.zeros((n, info["n_units"]), dtype=torch.int32, device="cuda")

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from rtc_cases import TOL, Case, log, rel_l2, run_batch, run_stream
+from rtc_cases import TOL, Case, log, mid_case, rel_l2, run_batch, run_stream
 
 pytestmark = pytest.mark.gpu
 
@@ -25,14 +25,7 @@ def rtc():
 
 
 def _mid_case(polc: bool, n_frames: int = 30, polc_m: str = "from_D", index: int = 92):
-    wfs = synth.ShWfs(nsub=24, px=10, obs=0.28, frame_h=240, frame_w=240, n_chunks=6)
-    inst = synth.Instance(f"mid{index}", (wfs,), 700, ("f32",), polc=polc, gain=0.4, leak=0.01)
-    wl = synth.Workload(index, f"mid{index}", (inst,), n_frames=n_frames, bank=n_frames)
-    synth.workloads.WORKLOADS[wl.name] = wl
-    try:
-        return Case(wl.name, n_frames=n_frames, polc_m=polc_m)
-    finally:
-        del synth.workloads.WORKLOADS[wl.name]
+    return mid_case(polc, n_frames, polc_m, index)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])

@@ -1,0 +1,191 @@
+"""GPU tests of the control-matrix swap (rtc_stage_matrices / rtc_swap_matrices).
+
+A swap at frame k must give, frame for frame, the oracle run with the first
+matrices for frames < k continued with the second ones from frame k (its
+commands and POLC term carried over: the POLC term of frame k is the first
+POLC matrix applied to the commands of frame k - 1), in every mode: the
+per-launch path, the frame loop over device-resident frames and the serving
+frame loop; the three give identical commands.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from rtc_cases import DEQ_TOL, TOL, log, mid_case, rel_l2, run_batch, run_stream
+
+pytestmark = pytest.mark.gpu
+
+N_FRAMES, K1, K2 = 24, 9, 17
+
+
+@pytest.fixture(scope="module")
+def rtc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01852_amd import rtc as mod
+    mod.lib()
+    return mod
+
+
+def second_matrices(case, key: int):
+    """Another seeded matrix set of the same shapes (R2, and D2 or M2)."""
+    inst = case.inst
+    R2 = synth.gaussian_matrix(inst.n_act, inst.n_slopes, 1.0 / np.sqrt(inst.n_slopes),
+                               synth.seed_for(case.wl.index, 0, 77, key), np.float32)
+    D2 = M2 = None
+    if inst.polc:
+        if case.D is not None:
+            D2 = synth.gaussian_matrix(inst.n_slopes, inst.n_act, 0.5 / np.sqrt(inst.n_act),
+                                       synth.seed_for(case.wl.index, 0, 77, key + 1))
+        else:
+            M2 = synth.gaussian_matrix(inst.n_act, inst.n_act, 0.5 / np.sqrt(inst.n_act),
+                                       synth.seed_for(case.wl.index, 0, 77, key + 1),
+                                       np.float32)
+    return R2, D2, M2
+
+
+def oracle_M(R, D, M):
+    if M is not None:
+        return M.astype(np.float64)
+    if D is not None:
+        return oracle.polc_matrix(R, D)
+    return None
+
+
+def oracle_switched(case, sets, switches, n, dtype="f32", dequantized=False):
+    """Oracle commands with matrix set sets[i] from frame switches[i - 1] on."""
+    bounds = [0] + list(switches) + [n]
+    out, a, p = [], None, None
+    for i in range(len(bounds) - 1):
+        R, D, M = sets[i]
+        Mo = oracle_M(R, D, M)
+        f0, f1 = bounds[i], bounds[i + 1]
+        r = oracle.run(case.inst, case.frames, case.cals, R, f1 - f0, cm_dtype=dtype, M=Mo,
+                       dequantized=dequantized, a0=a, p0=p, f0=f0)
+        out.append(r["commands"])
+        a = r["commands"][-1]
+        p = None if Mo is None else Mo @ a     # this set's POLC product on frame f1 - 1
+    return np.concatenate(out)
+
+
+def batch_with_swaps(eng, case, sets, switches, n):
+    """Batches on one engine: set 0 loaded, then each later set staged and
+    swapped in at its frame."""
+    R, D, M = sets[0]
+    eng.load_matrices(0, R, D=D, M=M)
+    for w, cal in enumerate(case.cals):
+        eng.load_calibration(0, w, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
+    bounds = [0] + list(switches) + [n]
+    outs = []
+    for i in range(len(bounds) - 1):
+        if i > 0:
+            R, D, M = sets[i]
+            eng.stage_matrices(0, R, D=D, M=M)
+            assert eng.swap_matrices(0) == bounds[i]
+        outs.append(run_batch(eng, 0, case, n=bounds[i + 1] - bounds[i], first=bounds[i])[0])
+    return np.concatenate(outs)
+
+
+@pytest.mark.parametrize("mode", ["stream", "persistent"])
+def test_swap_batch_vs_oracle(rtc, mode):
+    """POLC on, M formed from D on the device for both sets; two swaps (back to
+    the first slot on the second)."""
+    case = mid_case(True, n_frames=N_FRAMES, index=94)
+    sets = [(case.R, case.D, None), second_matrices(case, 40), second_matrices(case, 50)]
+    log(f"case mid POLC {mode}: swaps at {K1} and {K2}")
+    with rtc.Engine([(case.inst, "f32")], mode=mode) as eng:
+        got = batch_with_swaps(eng, case, sets, (K1, K2), N_FRAMES)
+    ref = oracle_switched(case, sets, (K1, K2), N_FRAMES)
+    rel = rel_l2(got, ref)
+    log(f"  max rel L2 {rel.max():.3e}")
+    assert rel.max() <= TOL["f32"]
+    # without the swap the commands after frame K1 differ by far more than the bar
+    plain = oracle_switched(case, sets[:1], (), N_FRAMES)
+    assert rel_l2(plain[K1:], ref[K1:]).min() > 100 * TOL["f32"]
+
+
+def test_swap_paths_identical(rtc):
+    """Per-launch path, frame loop and serving loop give the same commands
+    bit for bit through two swaps (M given directly: staging during serving)."""
+    case = mid_case(True, n_frames=N_FRAMES, polc_m="direct", index=95)
+    sets = [(case.R, None, case.M), second_matrices(case, 60), second_matrices(case, 70)]
+    log("case mid POLC (M direct): stream / persistent batch / serving")
+    with rtc.Engine([(case.inst, "f32")], mode="stream") as eng:
+        a = batch_with_swaps(eng, case, sets, (K1, K2), N_FRAMES)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        b = batch_with_swaps(eng, case, sets, (K1, K2), N_FRAMES)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        R, D, M = sets[0]
+        eng.load_matrices(0, R, D=D, M=M)
+        for w, cal in enumerate(case.cals):
+            eng.load_calibration(0, w, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
+        parts = [run_stream(eng, 0, case, n=K1)[0]]
+        # the loop runs: D would need the device-wide FP64 product
+        R2, _, M2 = sets[1]
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.stage_matrices(0, R2, D=case.D if case.D is not None else
+                               np.zeros((case.inst.n_slopes, case.inst.n_act)))
+        assert ei.value.status == -5
+        eng.stage_matrices(0, R2, M=M2)
+        assert eng.swap_matrices(0) == K1
+        parts.append(run_stream(eng, 0, case, n=K2 - K1, first_frame=K1)[0])
+        R3, _, M3 = sets[2]
+        eng.stage_matrices(0, R3, M=M3)     # waits for frames before K1 (done)
+        assert eng.swap_matrices(0) == K2
+        parts.append(run_stream(eng, 0, case, n=N_FRAMES - K2, first_frame=K2)[0])
+        c = np.concatenate(parts)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+    ref = oracle_switched(case, sets, (K1, K2), N_FRAMES)
+    assert rel_l2(c, ref).max() <= TOL["f32"]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_swap_quantized(rtc, dtype):
+    """Storage types: the staged slot carries its own codes and FP8 row scales;
+    read-back returns the active slot."""
+    case = mid_case(False, n_frames=N_FRAMES, index=96)
+    sets = [(case.R, None, None), second_matrices(case, 80)]
+    log(f"case mid {dtype}: swap at {K1}")
+    with rtc.Engine([(case.inst, dtype)], mode="stream") as eng:
+        got = batch_with_swaps(eng, case, sets, (K1,), N_FRAMES)
+        codes, scales = eng.read_matrix(0)
+    ref = oracle_switched(case, sets, (K1,), N_FRAMES, dtype=dtype, dequantized=True)
+    rel = rel_l2(got, ref)
+    log(f"  max rel L2 vs dequantised oracle {rel.max():.3e}")
+    assert rel.max() <= DEQ_TOL
+    want_codes, want_scale = oracle.quantize(sets[1][0], dtype)
+    assert np.array_equal(codes, want_codes)
+    if dtype == "fp8":
+        assert np.array_equal(scales, np.asarray(want_scale, np.float32))
+
+
+def test_swap_rules(rtc):
+    case = mid_case(False, n_frames=4, index=97)
+    R2, _, _ = second_matrices(case, 90)
+    with rtc.Engine([(case.inst, "f32")], mode="stream") as eng:
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.stage_matrices(0, R2)              # nothing loaded yet
+        assert ei.value.status == -5
+        case.load(eng)
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.swap_matrices(0)                   # nothing staged
+        assert ei.value.status == -5
+        eng.stage_matrices(0, R2)
+        eng.stage_matrices(0, R2)                  # restaging replaces the staged set
+        assert eng.swap_matrices(0) == 0
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.swap_matrices(0)                   # a swap is pending
+        assert ei.value.status == -5
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.stage_matrices(0, case.R)          # its slot is about to become active
+        assert ei.value.status == -5
+        run_batch(eng, 0, case, n=2)               # frame 0 takes the swap
+        eng.stage_matrices(0, case.R)
+        # a full reload drops the staged set
+        case.load(eng)
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.swap_matrices(0)
+        assert ei.value.status == -5

@@ -382,3 +382,59 @@ def test_polc_with_identity_equals_plain_integrator():
     a = oracle.run(inst_p, [frames], [cal], R, 50, M=np.eye(R.shape[0]))["commands"]
     b = oracle.run(inst_o, [frames], [cal], R, 50)["commands"]
     assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_run_continues_another_run():
+    """A run split at frame k and continued from its state (commands a_{k-1},
+    POLC term M a_{k-1}, frame numbers from k) is the unsplit run."""
+    k, n = 17, 45
+    for polc in (False, True):
+        inst, frames, cal, R = _tiny_instance(polc=polc, switch=(30, 0.3, 0.02))
+        bank = np.concatenate([frames] * 3)                  # three identical frames
+        rng = np.random.default_rng(5)
+        M = (rng.standard_normal((R.shape[0], R.shape[0])) * 0.4 / np.sqrt(R.shape[0])
+             if polc else None)
+        whole = oracle.run(inst, [bank], [cal], R, n, M=M)["commands"]
+        head = oracle.run(inst, [bank], [cal], R, k, M=M)["commands"]
+        p0 = None if M is None else M @ head[-1]
+        tail = oracle.run(inst, [bank], [cal], R, n - k, M=M, a0=head[-1], p0=p0,
+                          f0=k)["commands"]
+        assert np.array_equal(np.concatenate([head, tail]), whole)
+
+
+def test_matrix_switch_closed_form():
+    """POLC off, identical frames, reconstructor R1 for frames < k and R2 from
+    k on: a_n = (1-leak)^(n-k+1) a_{k-1} + (1 - (1-leak)^(n-k+1)) (gain/leak) R2 s."""
+    k, n = 25, 90
+    inst, frames, cal, R1 = _tiny_instance()
+    rng = np.random.default_rng(8)
+    R2 = (rng.standard_normal(R1.shape) / np.sqrt(R1.shape[1])).astype(np.float32)
+    head = oracle.run(inst, [frames], [cal], R1, k)
+    tail = oracle.run(inst, [frames], [cal], R2, n - k, a0=head["commands"][-1], f0=k)
+    y2 = R2.astype(np.float64) @ head["slopes"][0]
+    g, lam = float(np.float32(0.4)), float(np.float32(0.01))
+    a_prev = head["commands"][-1]
+    for f in (k, k + 1, k + 9, n - 1):
+        m = f - k + 1
+        expect = (1 - lam) ** m * a_prev + (1 - (1 - lam) ** m) * (g / lam) * y2
+        assert np.abs(tail["commands"][f - k] - expect).max() <= 1e-12 * np.abs(expect).max()
+
+
+def test_polc_term_given_for_first_frame():
+    """With POLC matrix I the recurrence is the plain integrator, so a first
+    POLC term p0 = a0 continues the plain integrator exactly; any other p0
+    enters the first frame as gain * p0 and decays through the same recurrence."""
+    inst_p, frames, cal, R = _tiny_instance(polc=True)
+    inst_o, _, _, _ = _tiny_instance(polc=False)
+    rng = np.random.default_rng(21)
+    a0 = rng.standard_normal(R.shape[0])
+    eye = np.eye(R.shape[0])
+    a = oracle.run(inst_p, [frames], [cal], R, 30, M=eye, a0=a0, p0=a0)["commands"]
+    b = oracle.run(inst_o, [frames], [cal], R, 30, a0=a0)["commands"]
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+    d = rng.standard_normal(R.shape[0])
+    c = oracle.run(inst_p, [frames], [cal], R, 30, M=eye, a0=a0, p0=a0 + d)["commands"]
+    g, lam = float(np.float32(0.4)), float(np.float32(0.01))
+    for m in (1, 2, 30):
+        expect = (1 - lam) ** (m - 1) * g * d
+        assert np.abs((c - a)[m - 1] - expect).max() <= 1e-12 * np.abs(d).max()
