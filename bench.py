@@ -229,7 +229,7 @@ def _pct(v):
 
 
 def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s=1.5e-3,
-                    switch=None, zero_copy=False, swap=None):
+                    switch=None, zero_copy=False, swap=None, telemetry=None):
     """Paced serving loop from host memory for one or more instances of one
     engine, every sensor read out in parallel: chunk c of each sensor of an
     instance with n chunks is delivered (c + 1) * readout / n after the frame
@@ -243,7 +243,10 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     swap: (instance index, frame, R, M): a second matrix set staged by another
     host thread from that frame on (rtc_stage_matrices, while frames run) and
     swapped in (rtc_swap_matrices) at the first frame start after the staging
-    returned; adds per-phase latency statistics of that instance."""
+    returned; adds per-phase latency statistics of that instance.
+    telemetry: (decimation, slots): every instance streams slopes, counts and
+    commands into its telemetry ring, drained by a reader thread per instance
+    (rtc_telemetry_next) while frames run."""
     import threading
     plan = []
     for idx, banks in streams:
@@ -260,6 +263,23 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     fno = []
     banks = dict(streams)
     sw = {}
+    readers, tel_stop, tel_got = [], threading.Event(), {}
+    if telemetry is not None:
+        for idx, _ in streams:
+            eng.telemetry_enable(idx, telemetry[0], telemetry[1])
+            tel_got[idx] = [0, 0]
+
+            def drain_tel(idx=idx):
+                while not tel_stop.is_set():
+                    try:
+                        _, _, _, ti = eng.telemetry_next(idx, timeout_s=0.05)
+                    except Exception:
+                        continue
+                    tel_got[idx][0] += 1
+                    tel_got[idx][1] += ti["lost"]
+            th_t = threading.Thread(target=drain_tel)
+            th_t.start()
+            readers.append(th_t)
     t_next = time.perf_counter()
     for f in range(n_frames + warmup):
         if switch is not None and f == switch[1]:
@@ -295,11 +315,21 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
     if swap is not None and "f_eff" not in sw:
         th.join()
         raise RuntimeError("the staged matrices were not swapped in before the last frame")
+    if telemetry is not None:
+        time.sleep(0.1)
+        tel_stop.set()
+        for th_t in readers:
+            th_t.join()
+        for idx, _ in streams:
+            eng.telemetry_enable(idx, 1, 0)
     out = {}
     for idx, _ in streams:
         r = _pct(host[idx])
         r["frames"] = len(host[idx])
         r["device"] = _pct(dev[idx])
+        if telemetry is not None:
+            r["telemetry"] = {"decimation": telemetry[0], "slots": telemetry[1],
+                              "records_read": tel_got[idx][0], "records_lost": tel_got[idx][1]}
         if swap is not None and swap[0] == idx:
             import numpy as np
             fa, h, d = np.asarray(fno), np.asarray(host[idx]), np.asarray(dev[idx])
@@ -331,7 +361,7 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
     import numpy as np
     import synth
     res = {}
-    for name in ("mcao_74", "ltao_68"):
+    for name in ("mcao_74", "ltao_68", "mcao_80"):
         wl = synth.get_workload(name)
         mats, banks = [], []
         for i, inst in enumerate(wl.instances):
@@ -348,7 +378,8 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
                 cal.append(c_w)
             mats.append((R, M, cal))
             banks.append(fr)
-        for dtype in dtypes:
+        # the paper-size MCAO's FP32 matrix (1.4 GB) is not one of its storage choices
+        for dtype in [d for d in dtypes if name != "mcao_80" or d != "f32"]:
             log(f"bench: serving {name} {dtype}")
             eng = rtc.Engine([(inst, dtype) for inst in wl.instances], ring_depth=4,
                              mode="persistent")
@@ -364,6 +395,14 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
                           wl.instances[i].switch[2])
             lat = serving_latency(eng, [(i, banks[i]) for i in range(len(wl.instances))],
                                   n_frames, switch=switch)
+            if name == "mcao_74" and dtype == dtypes[0]:
+                # the same with slopes, counts and commands of every frame streamed
+                eng.set_state(0, None, None, 0)
+                tel = serving_latency(eng, [(0, banks[0])], n_frames, telemetry=(1, 256))[0]
+                res[f"{name}:{wl.instances[0].name}:{dtype}:telemetry_every_frame"] = {
+                    k: (round(v, 3) if isinstance(v, float) else v) for k, v in tel.items()}
+                log(f"bench: {name} {dtype} with telemetry: p50 {tel['p50']:.1f} "
+                    f"p99 {tel['p99']:.1f} us")
             eng.close()
             for i, inst in enumerate(wl.instances):
                 key = f"{name}:{inst.name}:{dtype}"
@@ -380,7 +419,8 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
 
 
 # matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
-LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"))
+LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"),
+             ("mcao_80", "bf16"), ("mcao_80", "fp8"))
 
 
 def mvm_large(torch, rtc, log):
@@ -574,6 +614,10 @@ def main():
                 latency[dtype]["zero_copy"] = serving_latency(
                     eng, [(0, frames)], args.latency_frames, zero_copy=True)[0]
                 if dtype == args.dtype:
+                    # slopes, counts and commands of every frame streamed to the host
+                    eng.set_state(0, None, None, 0)
+                    latency[dtype]["telemetry_every_frame"] = serving_latency(
+                        eng, [(0, frames)], args.latency_frames, telemetry=(1, 256))[0]
                     # a second control matrix staged and swapped in while frames run
                     import numpy as np
                     import synth

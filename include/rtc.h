@@ -221,6 +221,35 @@ rtc_status rtc_commit_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t f
 rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float *cmds,
                              int64_t timeout_ns, rtc_frame_info *info);
 
+/* Telemetry stream (the paper's circular telemetry buffers of slopes and DM
+ * commands, streamed while the loop runs; section on streaming telemetry).
+ * Persistent mode only (RTC_E_STATE otherwise).  rtc_telemetry_enable makes
+ * every `decimation`-th frame started on the instance (frames counted from
+ * the last rtc_load_matrices or rtc_set_state) write its slopes, its counts
+ * of thresholded pixels and its commands into a ring of n_slots records in
+ * pinned host memory owned by the engine; decimation and n_slots are powers
+ * of two up to 65536, n_slots 0 turns telemetry off.  It stops the serving
+ * loop between frames (RTC_E_STATE while a frame is half delivered) and
+ * discards the previous ring.  The first record is the next frame to start.
+ *
+ * rtc_telemetry_next copies the next record in frame order (host arrays,
+ * each nullable: slopes n_slopes FP32 as rtc_read_slopes orders them, counts
+ * n_units int32, cmds n_act FP32) once its frame is published, waiting at
+ * most timeout_ns (RTC_E_TIMEOUT).  A record is overwritten when the frame
+ * decimation * n_slots later starts; records overwritten before being read
+ * are skipped and counted in info->lost.  A dropped frame's record has
+ * info->dropped = 1, its slopes and counts are partial and its commands are
+ * the previous frame's.  One reader per instance. */
+typedef struct {
+    uint64_t frame;               /* frame number of the record */
+    uint32_t dropped;             /* 1: the frame was dropped */
+    uint32_t lost;                /* records skipped (overwritten) before this one */
+} rtc_telemetry_info;
+rtc_status rtc_telemetry_enable(rtc_engine *e, int32_t inst, int32_t decimation,
+                                int32_t n_slots);
+rtc_status rtc_telemetry_next(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
+                              float *cmds, int64_t timeout_ns, rtc_telemetry_info *info);
+
 /* Batch path over device-resident frames: runs n_frames consecutive frames
  * through the whole hot path, in order, updating the command state exactly as
  * the serving path would.  frames[w] (device) points at n_frames frames of

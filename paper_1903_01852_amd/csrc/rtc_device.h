@@ -136,7 +136,18 @@ struct SlopeOut {
     float *s_out;          // compact slopes (nullable)
     int32_t *counts;       // thresholded pixels per unit (nullable)
     uint64_t *masks;       // thresholded-pixel masks (nullable)
+    int32_t out_agent;     // s_out and counts are read while the kernel runs
 };
+
+// Compact outputs: read after the kernel, or (out_agent) copied out while it
+// runs, so written through the XCD's L2 to the memory side.
+template <class T>
+__device__ __forceinline__ void put_out(const SlopeOut &o, T *p, T v) {
+    if (o.out_agent)
+        __hip_atomic_store(gbl(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        *gbl(p) = v;
+}
 
 // Shack-Hartmann unit: one wavefront.  Lane l handles pixels l, l+64, ... of
 // the subaperture (raster order), so the ballot of pass j is mask word j.
@@ -202,10 +213,10 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
         put<SP>(o.s_pad + d.pad, ox);
         put<SP>(o.s_pad + d.pad + 1, oy);
         if (o.s_out != nullptr) {
-            gbl(o.s_out)[2 * d.unit] = ox;
-            gbl(o.s_out)[2 * d.unit + 1] = oy;
+            put_out(o, o.s_out + 2 * d.unit, ox);
+            put_out(o, o.s_out + 2 * d.unit + 1, oy);
         }
-        if (o.counts != nullptr) gbl(o.counts)[d.unit] = cnt;
+        if (o.counts != nullptr) put_out(o, o.counts + d.unit, (int32_t)cnt);
     }
 }
 
@@ -241,10 +252,10 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
     put<SP>(o.s_pad + d.pad, sx);
     put<SP>(o.s_pad + d.pad + 1, sy);
     if (o.s_out != nullptr) {
-        gbl(o.s_out)[2 * d.unit] = sx;
-        gbl(o.s_out)[2 * d.unit + 1] = sy;
+        put_out(o, o.s_out + 2 * d.unit, sx);
+        put_out(o, o.s_out + 2 * d.unit + 1, sy);
     }
-    if (o.counts != nullptr) gbl(o.counts)[d.unit] = __popcll(bits);
+    if (o.counts != nullptr) put_out(o, o.counts + d.unit, (int32_t)__popcll(bits));
     if (o.masks != nullptr) gbl(o.masks)[d.mask] = bits;
 }
 

@@ -849,6 +849,29 @@ rtc_status rtc_swap_matrices(rtc_engine *e, int32_t inst, uint64_t *f_eff_out) {
     return RTC_OK;
 }
 
+rtc_status rtc_telemetry_enable(rtc_engine *e, int32_t inst, int32_t decimation,
+                                int32_t n_slots) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    auto pow2 = [](int32_t v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (!pow2(decimation) || decimation > 65536 || n_slots < 0 || n_slots > 65536 ||
+        (n_slots > 0 && !pow2(n_slots)))
+        return RTC_E_INVAL;
+    if (e->mode != RTC_MODE_PERSISTENT) return RTC_E_STATE;
+    HIP_TRY(hipSetDevice(e->device));
+    TRY(persist_quiesce(e));
+    std::lock_guard<std::mutex> lk(I->mu);
+    return persist_telemetry(e, I, decimation, n_slots);
+}
+
+rtc_status rtc_telemetry_next(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
+                              float *cmds, int64_t timeout_ns, rtc_telemetry_info *info) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (e->mode != RTC_MODE_PERSISTENT) return RTC_E_STATE;
+    return persist_telemetry_next(e, I, slopes, counts, cmds, timeout_ns, info);
+}
+
 rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs, const float *dark,
                                 const float *flat, const float *bg, const float *thr,
                                 const float *ref) {

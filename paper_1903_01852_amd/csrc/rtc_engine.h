@@ -95,6 +95,17 @@ struct PersistInstState {
     uint64_t param_word = 0;       // (q_switch << 1) | staged slot, as last written
     uint64_t mword = 0;            // (q_mswitch << 1) | slot, as last written
     uint64_t mq_last = 0;          // frames before this sequence number may use the inactive matrix slot
+    // telemetry: the serving loop forms records in a device ring and copies
+    // each into the pinned host ring once its frame is published
+    float *tel_ring = nullptr;     // device, [slots][rec]: slopes, counts, commands
+    float *tel_host = nullptr;     // pinned, the same layout
+    uint64_t *tel_flags = nullptr; // pinned, [slots][kTelMaxTasks]: q + 1 per copied part
+    int tel_rec = 0;               // 4-byte words per record (a multiple of 4)
+    int tel_dshift = 0;            // decimation 2^tel_dshift
+    int tel_slots = 0;             // 0: telemetry off
+    uint64_t tel_next = 0;         // sequence number of the next record to read
+    std::vector<uint64_t> tel_frame;    // frame number of each slot's record
+    std::vector<uint8_t> tel_dropped;   // the record's frame was dropped
     int w0 = 0, w1 = 0;            // worker range of the running loop
 };
 
@@ -281,6 +292,10 @@ rtc_status persist_batch(rtc_engine *e, Instance *I, const uint16_t *const *fram
                          float *slopes, int32_t *counts, hipStream_t st);
 rtc_status persist_params(rtc_engine *e, Instance *I);
 void persist_mswap(Instance *I, uint64_t q_switch, int slot);
+void persist_telemetry_free(Instance *I);
+rtc_status persist_telemetry(rtc_engine *e, Instance *I, int decimation, int n_slots);
+rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int32_t *counts,
+                                  float *cmds, int64_t timeout_ns, rtc_telemetry_info *info);
 rtc_status persist_wait_matrix_free(rtc_engine *e, Instance *I);
 rtc_status persist_quiesce(rtc_engine *e);
 rtc_status persist_acquire(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,

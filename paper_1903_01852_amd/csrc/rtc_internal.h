@@ -219,6 +219,17 @@ struct PersistInst {
     const ParamBlock *params;              // serving (pinned)
     ParamBlock *param_mirror;              // serving (device)
     Coef coef;                             // batch
+    // telemetry (serving): frames q with q % 2^tel_dshift == 0 write their
+    // slopes, counts and commands into device ring slot (q >> tel_dshift) &
+    // tel_smask, one record of tel_rec words (a multiple of 4): slopes, then
+    // counts, then commands; once the frame is published, workers copy the
+    // record into the same slot of the pinned host ring, task j setting
+    // tel_flags[slot][j] = q + 1 after its part
+    float *tel_ring;                       // null: off
+    float *tel_host;
+    uint64_t *tel_flags;                   // pinned, [slots][kTelMaxTasks]
+    int32_t tel_rec;
+    int32_t tel_dshift, tel_smask;
     // outputs
     float *mail;                           // pinned, ring_depth x n_act (serving)
     uint64_t *cmd_seq;                     // pinned: q + 1 of the last published frame
@@ -249,6 +260,10 @@ struct PersistArgs {
 };
 
 enum { PERSIST_OK = 0, PERSIST_WATCHDOG = 1 };
+// Telemetry copy: 16-byte units per task, and the most tasks a record takes
+// (records up to 2 MiB).
+constexpr int kTelUnits = 1024;
+constexpr int kTelMaxTasks = 128;
 constexpr uint64_t kDbChunkMask = (1ull << 20) - 1;
 constexpr int kDbShift = 20;
 constexpr int kMaxSegVectors = kPieceVectors;   // longest segment (slopes staged in LDS)

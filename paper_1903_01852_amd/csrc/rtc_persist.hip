@@ -274,6 +274,16 @@ __device__ __forceinline__ int mat_slot(InstRef I, uint64_t q) {
     return q >= I.coef.q_mswitch ? I.coef.mslot[1] : I.coef.mslot[0];
 }
 
+// Telemetry: frame q is recorded when q is a multiple of the decimation, in
+// ring slot (q / decimation) mod slots (both powers of two).
+__device__ __forceinline__ bool tel_frame(InstRef I, uint64_t q) {
+    return I.tel_ring != nullptr && (q & ((1ull << I.tel_dshift) - 1)) == 0;
+}
+// The record of frame q (slopes first).
+__device__ __forceinline__ float *tel_rec(InstRef I, uint64_t q) {
+    return I.tel_ring + ((q >> I.tel_dshift) & (uint64_t)I.tel_smask) * (uint64_t)I.tel_rec;
+}
+
 // Frame coefficients for frame q.
 __device__ __forceinline__ void frame_coef(InstRef I, uint64_t q, float &c1, float &g) {
     if (I.serving) {
@@ -441,8 +451,10 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
         if (I.serving) dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
         const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
         st_agent(a_buf(I, q) + r, an);
-        if (I.serving)
+        if (I.serving) {
             st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
+            if (tel_frame(I, q)) st_agent(tel_rec(I, q) + I.n_slopes + I.n_units + r, an);
+        }
         else if (I.cmds_out != nullptr)
             gbl(I.cmds_out)[(size_t)(q - I.q_begin) * I.n_act + r] = an;
     }
@@ -721,6 +733,48 @@ __device__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int n
     if (lane == 0) add_agent64(slot(I.ing_cnt, (size_t)dslot(q) * I.n_steps + st), cnt);
 }
 
+// Telemetry copy of recorded frame q: once the frame is published, task j
+// copies 16-byte units [j kTelUnits, (j + 1) kTelUnits) of its record from the
+// device ring to the pinned host ring (agent-coherent loads, system-coherent
+// stores), then sets its flag.  Off the frame's latency path.
+__device__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane) {
+    const int n16 = I.tel_rec / 4;
+    const int n_tasks = (n16 + kTelUnits - 1) / kTelUnits;
+    int j = first_task(rank, nw, rot(q, n_tasks, nw));
+    if (j >= n_tasks) return true;
+    if (!wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q, I.n_tiles), A,
+                  A.dep_watchdog))
+        return false;
+    const uint64_t ts = (q >> I.tel_dshift) & (uint64_t)I.tel_smask;
+    const int bytes = n16 * 16;
+    __amdgpu_buffer_rsrc_t src = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(I.tel_ring + ts * (uint64_t)I.tel_rec), (short)0, bytes, 0x00020000);
+    __amdgpu_buffer_rsrc_t dst = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(I.tel_host + ts * (uint64_t)I.tel_rec), (short)0, bytes, 0x00020000);
+    constexpr int kSys = 1 | 16, kAgent = 16;   // cache policy: sc0 sc1, sc1
+    for (; j < n_tasks; j += nw) {
+        const int u1 = min(n16, (j + 1) * kTelUnits);
+        for (int u0 = j * kTelUnits; u0 < u1; u0 += 4 * kWave) {
+            vec16_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int u = u0 + k * kWave + lane;
+                if (u < u1) v[k] = __builtin_amdgcn_raw_buffer_load_b128(src, u * 16, 0, kAgent);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int u = u0 + k * kWave + lane;
+                if (u < u1) __builtin_amdgcn_raw_buffer_store_b128(v[k], dst, u * 16, 0, kSys);
+            }
+        }
+        drain();
+        if (lane == 0)
+            __hip_atomic_store(gbl(I.tel_flags + ts * kTelMaxTasks + j), q + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return true;
+}
+
 // Serving worker: a small scheduler over the frame's readout steps with one
 // cursor per kind of work, in priority order.  Ingest: copy its pieces of
 // every chunk whose doorbell has rung.  Slopes: form its slopes of every step
@@ -743,7 +797,11 @@ __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, 
         tr.stamp(RTC_TRACE_FRAME_START, lane);
         if (!gate(I, A, q)) return;
         tr.stamp(RTC_TRACE_GATE, lane);
-        const SlopeOut so{I.s_pad[dslot(q)], nullptr, nullptr, nullptr};
+        SlopeOut so{I.s_pad[dslot(q)], nullptr, nullptr, nullptr, 1};
+        if (tel_frame(I, q)) {
+            so.s_out = tel_rec(I, q);
+            so.counts = reinterpret_cast<int32_t *>(so.s_out + I.n_slopes);
+        }
         FrameTasks ft = frame_tasks(I, q, rank, nw);
         int ing = first_task(rank, nw, rot(q, I.n_ing_all, nw));
         const int n_steps = I.n_steps, n_tiles = I.n_tiles;
@@ -817,6 +875,7 @@ __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, 
             }
         }
         if (I.polc && !polc_tasks(I, A, q, rank, nw, lane, lds, tr)) return;
+        if (tel_frame(I, q) && !tel_copy_tasks(I, A, q, rank, nw, lane)) return;
         trace_end(tr, lane);
     }
 }

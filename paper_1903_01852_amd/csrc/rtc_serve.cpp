@@ -110,6 +110,14 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.drop_host = P.drop_host;
     d.params = P.params;
     d.param_mirror = P.param_mirror;
+    if (P.tel_slots > 0) {
+        d.tel_ring = P.tel_ring;
+        d.tel_host = P.tel_host;
+        d.tel_flags = P.tel_flags;
+        d.tel_rec = P.tel_rec;
+        d.tel_dshift = P.tel_dshift;
+        d.tel_smask = P.tel_slots - 1;
+    }
     d.mail = I->h_mail;
     d.cmd_seq = P.cmd_seq;
     d.pol_seq = P.pol_seq;
@@ -435,6 +443,7 @@ rtc_status persist_trace(rtc_engine *e, int n_frames) {
 
 void persist_free(rtc_engine *e) {
     PersistEngine &pe = e->pe;
+    for (Instance *I : e->inst) persist_telemetry_free(I);
     if (pe.trace) (void)hipFree(pe.trace);
     for (int k = 0; k < 2; ++k)
         if (pe.batch_copied[k]) (void)hipEventDestroy(pe.batch_copied[k]);
@@ -456,8 +465,121 @@ void persist_reset(Instance *I) {
     std::fill(P.slot_frame.begin(), P.slot_frame.end(), ~0ull);
     std::fill(P.slot_dropped.begin(), P.slot_dropped.end(), 0);
     (void)persist_params(nullptr, I);
+    // a pending swap is cancelled (its matrices stay staged)
+    if (I->m_pending) {
+        I->m_pending = false;
+        I->m_staged = true;
+    }
     persist_mswap(I, ~0ull >> 2, 1 - I->m_active);   // every frame on the active slot
     P.mq_last = 0;
+    P.tel_next = 0;
+}
+
+void persist_telemetry_free(Instance *I) {
+    PersistInstState &P = I->ps;
+    if (P.tel_ring) (void)hipFree(P.tel_ring);
+    if (P.tel_host) (void)hipHostFree(P.tel_host);
+    if (P.tel_flags) (void)hipHostFree(P.tel_flags);
+    P.tel_ring = nullptr;
+    P.tel_host = nullptr;
+    P.tel_flags = nullptr;
+    P.tel_slots = 0;
+}
+
+int tel_tasks(const Instance *I) {
+    return (I->ps.tel_rec / 4 + kTelUnits - 1) / kTelUnits;
+}
+
+// Telemetry ring of 2^k slots recording every 2^j-th frame (n_slots 0: off).
+// Records are formed in device memory (the slope and command stores stay at
+// HBM speed) and copied to the pinned host ring with 16-byte stores, off the
+// frame's latency path.
+rtc_status persist_telemetry(rtc_engine *e, Instance *I, int decimation, int n_slots) {
+    PersistInstState &P = I->ps;
+    HIP_TRY(hipDeviceSynchronize());
+    persist_telemetry_free(I);
+    if (n_slots == 0) return RTC_OK;
+    P.tel_rec = (I->n_slopes + I->n_units + I->n_act + 3) & ~3;
+    if (tel_tasks(I) > kTelMaxTasks) return RTC_E_INVAL;
+    const size_t ring_bytes = (size_t)P.tel_rec * 4 * n_slots;
+    const size_t flag_bytes = (size_t)n_slots * kTelMaxTasks * 8;
+    if (hipMalloc(&P.tel_ring, ring_bytes) != hipSuccess) {
+        P.tel_ring = nullptr;
+        return RTC_E_NOMEM;
+    }
+    if (hipHostMalloc(&P.tel_host, ring_bytes, hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&P.tel_flags, flag_bytes, hipHostMallocCoherent) != hipSuccess) {
+        persist_telemetry_free(I);
+        return RTC_E_NOMEM;
+    }
+    HIP_TRY(hipMemset(P.tel_ring, 0, ring_bytes));
+    std::memset(P.tel_host, 0, ring_bytes);
+    std::memset(P.tel_flags, 0, flag_bytes);
+    int sh = 0;
+    while ((1 << sh) < decimation) ++sh;
+    P.tel_dshift = sh;
+    P.tel_slots = n_slots;
+    P.tel_frame.assign((size_t)n_slots, ~0ull);
+    P.tel_dropped.assign((size_t)n_slots, 0);
+    // the first record read is the next frame to start
+    P.tel_next = ((P.seq + (uint64_t)decimation - 1) >> sh) << sh;
+    (void)e;
+    return RTC_OK;
+}
+
+// The next telemetry record, in frame order: waits for its frame to be
+// published; records overwritten before they were read are skipped (counted).
+rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int32_t *counts,
+                                  float *cmds, int64_t timeout_ns, rtc_telemetry_info *info) {
+    PersistInstState &P = I->ps;
+    const int64_t t0 = now_ns();
+    uint32_t lost = 0;
+    for (;;) {
+        uint64_t q;
+        size_t k;
+        uint64_t span;
+        {
+            std::lock_guard<std::mutex> lk(I->mu);
+            if (P.tel_slots == 0) return RTC_E_STATE;
+            const uint64_t d = 1ull << P.tel_dshift;
+            span = d * (uint64_t)P.tel_slots;
+            // a record is overwritten once the frame span later has started
+            if (P.seq > P.tel_next + span) {
+                const uint64_t first = ((P.seq - span + d - 1) >> P.tel_dshift) << P.tel_dshift;
+                lost += (uint32_t)((first - P.tel_next) >> P.tel_dshift);
+                P.tel_next = first;
+            }
+            q = P.tel_next;
+            k = (size_t)((q >> P.tel_dshift) & (uint64_t)(P.tel_slots - 1));
+        }
+        // every part of the record copied for frame q
+        uint64_t *flags = P.tel_flags + k * kTelMaxTasks;
+        const int nt = tel_tasks(I);
+        for (int j = 0; j < nt;) {
+            if (load_acquire(flags + j) == q + 1) {
+                ++j;
+                continue;
+            }
+            if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
+            if (e->pe.running && stream_done(e->pe.stream) &&
+                *reinterpret_cast<volatile uint32_t *>(e->pe.status) != PERSIST_OK)
+                return fail(e, RTC_E_DEVICE);
+            std::this_thread::yield();
+        }
+        const float *rec = P.tel_host + k * (size_t)P.tel_rec;
+        if (slopes) std::memcpy(slopes, rec, (size_t)I->n_slopes * 4);
+        if (counts) std::memcpy(counts, rec + I->n_slopes, (size_t)I->n_units * 4);
+        if (cmds) std::memcpy(cmds, rec + I->n_slopes + I->n_units, (size_t)I->n_act * 4);
+        std::lock_guard<std::mutex> lk(I->mu);
+        if (P.seq > q + span) continue;     // overwritten while copied: skip ahead
+        if (info) {
+            info->frame = P.tel_frame[k];
+            info->dropped = P.tel_dropped[k];
+            info->lost = lost;
+        }
+        P.tel_next = q + (1ull << P.tel_dshift);
+        return RTC_OK;
+    }
 }
 
 // Matrix slot switch word: frames from sequence number q_switch on use `slot`,
@@ -532,6 +654,8 @@ rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int ch
             // loop skips its integrator update) so the loop can move on
             const uint64_t qd = P.q_cur;
             P.slot_dropped[qd % P.slot_dropped.size()] = 1;
+            if (P.tel_slots > 0 && (qd & ((1ull << P.tel_dshift) - 1)) == 0)
+                P.tel_dropped[(qd >> P.tel_dshift) & (uint64_t)(P.tel_slots - 1)] = 1;
             I->drops++;
             store_release(P.drop_host + qd % P.slot_dropped.size(), qd + 1);
             for (size_t s = 0; s < I->wfs.size(); ++s)
@@ -542,6 +666,11 @@ rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int ch
         settle_matrices(I, frame);
         P.q_cur = q;
         P.seq = q + 1;
+        if (P.tel_slots > 0 && (q & ((1ull << P.tel_dshift) - 1)) == 0) {
+            const size_t k = (size_t)((q >> P.tel_dshift) & (uint64_t)(P.tel_slots - 1));
+            P.tel_frame[k] = frame;
+            P.tel_dropped[k] = 0;
+        }
         const size_t slot = q % P.slot_frame.size();
         P.slot_frame[slot] = frame;
         P.slot_dropped[slot] = 0;

@@ -31,7 +31,7 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
            "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read",
            "rtc_acquire_chunk", "rtc_commit_chunk", "rtc_stage_matrices",
-           "rtc_swap_matrices")
+           "rtc_swap_matrices", "rtc_telemetry_enable", "rtc_telemetry_next")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -69,6 +69,10 @@ class FrameInfoC(C.Structure):
                 ("dev_ticks_cmd", C.c_uint64), ("drops", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class TelemetryInfoC(C.Structure):
+    _fields_ = [("frame", C.c_uint64), ("dropped", C.c_uint32), ("lost", C.c_uint32)]
+
+
 class InstanceInfoC(C.Structure):
     _fields_ = [("n_wfs", C.c_int32), ("n_units", C.c_int32), ("n_slopes", C.c_int32),
                 ("n_act", C.c_int32), ("n_kblocks", C.c_int32), ("mask_words", C.c_int32),
@@ -96,6 +100,8 @@ def lib() -> C.CDLL:
         L.rtc_chunk_rows.argtypes = [vp, i32, i32, i32, C.POINTER(i32), C.POINTER(i32)]
         L.rtc_load_matrices.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_stage_matrices.argtypes = [vp, i32, vp, vp, vp]
+        L.rtc_telemetry_enable.argtypes = [vp, i32, i32, i32]
+        L.rtc_telemetry_next.argtypes = [vp, i32, vp, vp, vp, i64, C.POINTER(TelemetryInfoC)]
         L.rtc_swap_matrices.argtypes = [vp, i32, C.POINTER(u64)]
         L.rtc_load_calibration.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.rtc_set_params.argtypes = [vp, i32, C.c_float, C.c_float, C.POINTER(u64)]
@@ -251,6 +257,21 @@ class Engine:
         f = C.c_uint64()
         _ok(lib().rtc_swap_matrices(self._h, inst, C.byref(f)), "rtc_swap_matrices")
         return f.value
+
+    def telemetry_enable(self, inst: int, decimation: int, n_slots: int):
+        _ok(lib().rtc_telemetry_enable(self._h, inst, decimation, n_slots),
+            "rtc_telemetry_enable")
+
+    def telemetry_next(self, inst: int = 0, timeout_s: float = 5.0):
+        """Next telemetry record: (slopes, counts, cmds, info dict)."""
+        info = self.infos[inst]
+        s = np.empty(info["n_slopes"], np.float32)
+        c = np.empty(info["n_units"], np.int32)
+        a = np.empty(info["n_act"], np.float32)
+        ti = TelemetryInfoC()
+        _ok(lib().rtc_telemetry_next(self._h, inst, _ptr(s), _ptr(c), _ptr(a),
+                                     int(timeout_s * 1e9), C.byref(ti)), "rtc_telemetry_next")
+        return s, c, a, {"frame": ti.frame, "dropped": ti.dropped, "lost": ti.lost}
 
     def load_calibration(self, inst: int, wfs: int, dark=None, flat=None, bg=None, thr=None,
                          ref=None):

@@ -49,6 +49,28 @@ def test_mcao_serving_vs_oracle(rtc, mcao, dtype):
     assert all(i["dev_ticks_cmd"] >= i["dev_ticks_start"] > 0 for i in infos)
 
 
+@pytest.fixture(scope="module")
+def mcao80():
+    log("building MCAO 6 LGS 80x80 + 3 NGS 2x2 inputs (6318 x 55416, the paper's LGS size)")
+    return Case("mcao_80", n_frames=4)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "fp8"])
+def test_mcao80_serving_vs_oracle(rtc, mcao80, dtype):
+    case = mcao80
+    log(f"case mcao_80 {dtype}: serving loop, 4 frames, POLC")
+    with rtc.Engine([(case.inst, dtype)], mode="persistent") as eng:
+        case.load(eng)
+        got, _ = run_stream(eng, 0, case)
+    ref = case.run_oracle(dtype)
+    deq = case.run_oracle(dtype, dequantized=True)
+    rel = rel_l2(got, ref["commands"])
+    rel_d = rel_l2(got, deq["commands"])
+    log(f"  max rel L2 {rel.max():.3e} (dequantised {rel_d.max():.3e})")
+    assert rel.max() <= TOL[dtype]
+    assert rel_d.max() <= DEQ_TOL
+
+
 def test_ltao_and_scao_in_one_launch_with_switch(rtc):
     """LTAO (POLC) beside the SCAO instance of uneven size in one persistent
     launch, the LTAO gain and leak switched through the API between frames."""

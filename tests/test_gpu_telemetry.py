@@ -1,0 +1,110 @@
+"""GPU tests of the telemetry stream (rtc_telemetry_enable / rtc_telemetry_next).
+
+The serving loop's telemetry records must hold, bit for bit, the slopes,
+thresholded-pixel counts and commands the batch path gives for the same
+frames; the counts must equal the oracle's.  Decimation, ring overrun and
+dropped frames follow the documented rules.
+"""
+import numpy as np
+import pytest
+
+from rtc_cases import TOL, Case, log, rel_l2, run_batch, run_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rtc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1903_01852_amd import rtc as mod
+    mod.lib()
+    return mod
+
+
+@pytest.mark.parametrize("name,n", [("scao_sh_small", 40), ("scao_pyr_92", 6)])
+def test_telemetry_equals_batch_outputs(rtc, name, n):
+    case = Case(name, n_frames=n)
+    log(f"case {name} serving with telemetry, every frame, {n} frames")
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        eng.telemetry_enable(0, 1, 64)
+        served, _ = run_stream(eng, 0, case)
+        recs = [eng.telemetry_next(0, timeout_s=5.0) for _ in range(n)]
+        eng.set_state(0, None, None, 0)
+        cmds, slopes, counts = run_batch(eng, 0, case)
+    assert [r[3]["frame"] for r in recs] == list(range(n))
+    assert all(r[3]["lost"] == 0 and r[3]["dropped"] == 0 for r in recs)
+    assert np.array_equal(np.stack([r[0] for r in recs]).astype(np.float64), slopes)
+    assert np.array_equal(np.stack([r[1] for r in recs]), counts)
+    assert np.array_equal(np.stack([r[2] for r in recs]).astype(np.float64), served)
+    assert np.array_equal(served, cmds)
+    ref = case.run_oracle("f32")
+    assert np.array_equal(counts, ref["counts"])
+    assert rel_l2(served, ref["commands"]).max() <= TOL["f32"]
+
+
+def test_telemetry_decimation_and_overrun(rtc):
+    """Every 4th frame into 2 slots: a reader that falls behind skips to the
+    oldest record still held and counts what it lost."""
+    n = 40
+    case = Case("scao_sh_small", n_frames=n)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        eng.telemetry_enable(0, 4, 2)
+        served, _ = run_stream(eng, 0, case, n=10)
+        s8, c8, a8, i8 = eng.telemetry_next(0)        # records of frames 0, 4, 8: 0 is gone
+        assert i8["frame"] == 4 and i8["lost"] == 1
+        assert np.array_equal(a8.astype(np.float64), served[4])
+        assert eng.telemetry_next(0)[3]["frame"] == 8
+        served2, _ = run_stream(eng, 0, case, n=n - 10, first_frame=10)
+        s, c, a, info = eng.telemetry_next(0)
+        # frames 12 .. 36 recorded; 12 .. 28 overwritten by 36 (2 slots x 4 frames)
+        assert info["frame"] == 32 and info["lost"] == 5
+        assert np.array_equal(a.astype(np.float64), served2[32 - 10])
+        assert eng.telemetry_next(0)[3]["frame"] == 36
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.telemetry_next(0, timeout_s=0.05)    # frame 40 never arrives
+        assert ei.value.status == -4
+        eng.set_state(0, None, None, 0)
+        _, slopes, counts = run_batch(eng, 0, case)
+    assert np.array_equal(s.astype(np.float64), slopes[32])
+    assert np.array_equal(c, counts[32])
+    assert np.array_equal(s8.astype(np.float64), slopes[4])
+
+
+def test_telemetry_dropped_frame_and_rules(rtc):
+    case = Case("scao_sh_small", n_frames=8)
+    with rtc.Engine([(case.inst, "f32")], mode="stream") as eng:
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.telemetry_enable(0, 1, 8)             # persistent mode only
+        assert ei.value.status == -5
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        for bad in ((3, 8), (1, 6), (0, 8), (1, -1)):
+            with pytest.raises(rtc.RtcError) as ei:
+                eng.telemetry_enable(0, *bad)
+            assert ei.value.status == -1
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.telemetry_next(0, timeout_s=0.01)     # not enabled
+        assert ei.value.status == -5
+        eng.telemetry_enable(0, 1, 8)
+        n_ch = case.inst.wfs[0].n_chunks
+        for f in range(5):
+            img = case.frames[0][f]
+            last = 1 if f == 2 else n_ch              # frame 2 delivers only its first chunk
+            for c in range(last):
+                r0, r1 = eng.chunk_rows(0, 0, c)
+                eng.submit_chunk(0, 0, f, c, img[r0:r1])
+            if f != 2:
+                eng.wait_commands(0, f)
+        recs = [eng.telemetry_next(0) for _ in range(5)]
+        assert [r[3]["frame"] for r in recs] == [0, 1, 2, 3, 4]
+        assert [r[3]["dropped"] for r in recs] == [0, 0, 1, 0, 0]
+        # a dropped frame keeps the previous commands
+        assert np.array_equal(recs[2][2], recs[1][2])
+        eng.telemetry_enable(0, 1, 0)                 # off
+        with pytest.raises(rtc.RtcError) as ei:
+            eng.telemetry_next(0, timeout_s=0.01)
+        assert ei.value.status == -5
