@@ -418,6 +418,44 @@ def latency_suite(torch, rtc, dtypes, n_frames, log):
     return res
 
 
+def wfs_sweep(torch, rtc, n_frames, log):
+    """Serving latency against sensor size at a constant frame size (the paper's
+    scaling study): Shack-Hartmann 74..110 subapertures across on 800x800 frames
+    (10, 10, 8, 8, 7 px per subaperture) and pyramid 80..120 pupil pixels across
+    on 240x240 frames, each with a 5318-actuator FP32 control matrix."""
+    import numpy as np
+    import synth
+    res = {}
+    points = [("sh", n, synth.ShWfs(nsub=n, px=min(10, 800 // n), obs=0.28, frame_h=800,
+                                    frame_w=800, origin=((800 - n * min(10, 800 // n)) // 2,) * 2))
+              for n in (74, 80, 90, 100, 110)]
+    for p in (80, 90, 100, 110, 120):
+        o0, o1 = (120 - p) // 2, 120 + (120 - p) // 2
+        points.append(("pyr", p, synth.PyrWfs(pupil_px=p, quad_origins=((o0, o0), (o1, o0),
+                                                                        (o0, o1), (o1, o1)))))
+    for i, (kind, n, wfs) in enumerate(points):
+        inst = synth.Instance(f"sweep_{kind}{n}", (wfs,), 5318, ("f32",))
+        wl = synth.Workload(200 + i, inst.name, (inst,), n_frames=n_frames, bank=16)
+        synth.workloads.WORKLOADS[wl.name] = wl
+        try:
+            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
+            R = synth.control_matrix(wl, 0)
+        finally:
+            del synth.workloads.WORKLOADS[wl.name]
+        eng = rtc.Engine([(inst, "f32")], ring_depth=4, mode="persistent")
+        eng.load_matrices(0, R)
+        eng.load_calibration(0, 0, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
+        r = serving_latency(eng, [(0, [fr])], n_frames)[0]
+        eng.close()
+        key = f"{kind}_{n}x{n}"
+        res[key] = {"n_slopes": inst.n_slopes, "n_act": inst.n_act,
+                    "px_per_subap": getattr(wfs, "px", None),
+                    **{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}}
+        log(f"bench: sweep {key}: {inst.n_slopes} slopes, p50 {r['p50']:.1f} p99 {r['p99']:.1f} "
+            f"jitter {r['rms_jitter']:.2f} us (device p50 {r['device']['p50']:.1f})")
+    return res
+
+
 # matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
 LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"),
              ("mcao_80", "bf16"), ("mcao_80", "fp8"))
@@ -523,6 +561,9 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-latency-suite", action="store_true",
                     help="skip the MCAO / LTAO+SCAO serving cases")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the serving-latency sweep over sensor sizes")
+    ap.add_argument("--sweep-frames", type=int, default=500)
     ap.add_argument("--no-mvm-large", action="store_true",
                     help="skip the standalone MVM on the MCAO / LTAO matrices")
     ap.add_argument("--mvm-large-only", action="store_true",
@@ -641,6 +682,10 @@ def main():
     if not args.quick and not args.no_latency and not args.no_latency_suite:
         suite = latency_suite(torch, rtc, dtypes, args.latency_frames, log)
 
+    sweep = None
+    if not args.quick and not args.no_latency and not args.no_sweep:
+        sweep = wfs_sweep(torch, rtc, args.sweep_frames, log)
+
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
@@ -679,6 +724,7 @@ def main():
         "paths": {p: {k: rnd(v) for k, v in d.items()} for p, d in paths.items() if d},
         "mvm": {k: rnd(v) for k, v in mvm.items()},
         "mvm_beyond_infinity_cache": large,
+        "latency_sweep_us": ({**sweep, "what": SERVING_NOTE} if sweep else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
