@@ -15,9 +15,10 @@ Also reported on the same JSON line:
   roofline     the dominant kernel of the chosen path (k_mvm_next: frame f's MVM
                with frame f + 1's slopes in one grid; or k_frame_loop):
                algorithmic bytes per launch / its average duration, from HIP
-               events recorded on its own stream around every launch of the
-               timed region; ``traffic`` from the committed rocprofv3 counter
-               summary when it was taken on the current kernel source;
+               events recorded on its own stream over the timed region (one
+               pair per run of 16 consecutive k_mvm_next launches, or per
+               frame-loop launch); ``traffic`` from the committed rocprofv3
+               counter summary when it was taken on the current kernel source;
   paths        frames/s and kernel GB/s of both batch forms for every storage
                type (FP32, BF16, FP8);
   latency_us   serving latency of the persistent loop per storage type (last
@@ -26,8 +27,17 @@ Also reported on the same JSON line:
                readout; p50 / p99 / RMS jitter; includes PCIe; ``zero_copy``
                the same with the chunks written in place into the lent ring
                slot (latency from the commit);
+               ``telemetry_every_frame``: the same with slopes, counts and
+               commands of every frame streamed to a host reader thread;
+               ``matrix_swap``: a second control matrix staged by another thread
+               while frames run and swapped in at a frame boundary, latency per
+               phase;
+  latency_suite_us  the same for the MCAO, LTAO + SCAO and 80x80 MCAO serving
+               cases (one persistent launch each);
+  latency_sweep_us  serving latency against sensor size at constant frame size;
   mvm          the standalone MVM kernel per storage type, warm (back to back)
                and after a 1 GiB read-only flush of the caches;
+  mvm_beyond_infinity_cache  the same on the matrices larger than the cache;
   cpu_baseline the CPU oracle on a bounded sample of the same frames.
 """
 from __future__ import annotations
@@ -46,7 +56,7 @@ if ROOT not in sys.path:
 METRIC = ("frame latency p50/p99 µs + RMS jitter; CM MVM HBM GB/s vs peak, "
           "FP32 vs BF16")
 HBM_PEAK_GBS = 8000.0
-MVM_SAMPLE_EVERY = 16      # per-launch path: time one MVM launch in 16
+MVM_RUN = 16               # per-launch path: k_mvm_next launches per event pair
 ELEM = {"f32": 4, "bf16": 2, "fp8": 1}
 
 WORKLOAD_TEXT = {
@@ -157,8 +167,9 @@ def run_steps(eng, dframes, bank, n, stream):
 def throughput(torch, eng, dframes, bank, steps, warmup, path):
     """Wall time of `steps` frames and the average duration of the path's
     dominant kernel: per launch of `bank` frames of the frame loop (HIP events
-    around each process_frames call on its stream), or per MVM launch of the
-    per-launch path (HIP events the library records around each MVM)."""
+    around each process_frames call on its stream), or per k_mvm_next launch of
+    the per-launch path (HIP events the library records around runs of
+    MVM_RUN consecutive launches)."""
     st = torch.cuda.current_stream()
     run_steps(eng, dframes, bank, warmup, st)
     torch.cuda.synchronize()
@@ -168,7 +179,7 @@ def throughput(torch, eng, dframes, bank, steps, warmup, path):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(n_launch)]
     else:
-        eng.mvm_timing(0, steps, MVM_SAMPLE_EVERY)
+        eng.mvm_timing(0, steps, MVM_RUN)
     t0 = time.perf_counter()
     done = 0
     for i in range(n_launch):

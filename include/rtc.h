@@ -278,15 +278,17 @@ rtc_status rtc_read_matrix(rtc_engine *e, int32_t inst, void *codes, float *scal
  * stream).  Changes no command state. */
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream);
 
-/* MVM kernel timer (RTC_MODE_STREAM diagnostics).  With capacity > 0, every
- * `every`-th later rtc_process_frames frame that has a successor in its batch
- * records a pair of HIP events on its stream around its reconstruction MVM
- * launch (which also forms the successor's slopes), up to capacity pairs (each
- * pair adds two queue packets, so sampling keeps the timed run close to an
- * untimed one); capacity 0 turns the timer off.  rtc_mvm_timing_read
- * synchronises on the last recorded pair, returns the number of timed
- * launches and the sum of their durations (ms) and clears the record.
- * RTC_E_STATE in persistent mode. */
+/* MVM kernel timer (RTC_MODE_STREAM diagnostics).  With capacity > 0, later
+ * rtc_process_frames frames that have a successor in their batch (their
+ * reconstruction MVM launch also forms the successor's slopes) are timed in
+ * runs of `every` consecutive launches: one pair of HIP events on the batch's
+ * stream brackets each run (a run also ends at the batch's last such frame),
+ * up to capacity pairs, so the two queue packets a pair adds are spread over
+ * the run.  A run includes what its frames enqueue between the launches (the
+ * POLC product, output copies).  capacity 0 turns the timer off.
+ * rtc_mvm_timing_read synchronises on the last recorded pair, returns the
+ * number of timed launches and the sum of the runs' durations (ms) and clears
+ * the record.  RTC_E_STATE in persistent mode. */
 rtc_status rtc_mvm_timing(rtc_engine *e, int32_t inst, int32_t capacity, int32_t every);
 rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *total_ms);
 

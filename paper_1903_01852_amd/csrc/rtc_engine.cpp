@@ -1069,14 +1069,21 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             N.s_out = I->d_sout;
             N.counts = I->d_counts;
             N.masks = I->d_masks;
-            // the sampled timer brackets these launches only (all alike)
-            const bool timed = 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size() &&
-                               I->mvm_ev_count++ % (uint64_t)I->mvm_ev_every == 0;
-            if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
+            // the timer brackets runs of these launches (all alike): one event
+            // pair per run of mvm_ev_every, or up to the batch's last of them
+            if (!I->mvm_open && 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size()) {
+                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
+                I->mvm_open = true;
+                I->mvm_run = 0;
+            }
             launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
                             I->d_pieces, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E, N,
                             I->params);
-            if (timed) HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used++ + 1], st));
+            if (I->mvm_open && (++I->mvm_run == I->mvm_ev_every || f + 2 >= n_frames)) {
+                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used + 1], st));
+                I->mvm_ev_len[I->mvm_ev_used++] = I->mvm_run;
+                I->mvm_open = false;
+            }
         } else {
             launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
                        I->d_pieces, 0, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E);
@@ -1120,9 +1127,10 @@ rtc_status rtc_mvm_timing(rtc_engine *e, int32_t inst, int32_t capacity, int32_t
     HIP_TRY(hipDeviceSynchronize());     // no recorded event may still be pending
     for (hipEvent_t ev : I->mvm_ev) HIP_TRY(hipEventDestroy(ev));
     I->mvm_ev.clear();
+    I->mvm_ev_len.assign((size_t)capacity, 0);
     I->mvm_ev_used = 0;
     I->mvm_ev_every = every;
-    I->mvm_ev_count = 0;
+    I->mvm_open = false;
     for (int32_t k = 0; k < 2 * capacity; ++k) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev));
@@ -1138,13 +1146,15 @@ rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *
     HIP_TRY(hipSetDevice(e->device));
     std::lock_guard<std::mutex> lk(I->mu);
     double tot = 0.0;
+    int32_t launches = 0;
     if (I->mvm_ev_used > 0) HIP_TRY(hipEventSynchronize(I->mvm_ev[2 * I->mvm_ev_used - 1]));
     for (size_t k = 0; k < I->mvm_ev_used; ++k) {
         float ms = 0.0f;
         HIP_TRY(hipEventElapsedTime(&ms, I->mvm_ev[2 * k], I->mvm_ev[2 * k + 1]));
         tot += ms;
+        launches += I->mvm_ev_len[k];
     }
-    if (n) *n = (int32_t)I->mvm_ev_used;
+    if (n) *n = launches;
     if (total_ms) *total_ms = tot;
     I->mvm_ev_used = 0;
     return RTC_OK;

@@ -112,9 +112,11 @@ struct PersistInstState {
 struct Instance {
     rtc_instance_desc d{};
     std::vector<hipEvent_t> mvm_ev;    // MVM timer: event pairs (rtc_mvm_timing)
+    std::vector<int32_t> mvm_ev_len;   // launches each recorded pair brackets
     size_t mvm_ev_used = 0;            // pairs recorded
-    int mvm_ev_every = 1;              // time every n-th frame
-    uint64_t mvm_ev_count = 0;         // frames since the timer was set
+    int mvm_ev_every = 1;              // launches per pair
+    int mvm_run = 0;                   // launches in the open pair
+    bool mvm_open = false;             // a pair's first event is recorded
     std::vector<WfsState> wfs;
     int n_units = 0, n_slopes = 0, n_act = 0, n_sh = 0, n_pyr = 0;
     int mask_words = 0;
