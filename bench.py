@@ -235,6 +235,7 @@ def mvm_timing(torch, eng, n_iter=200, cold=False):
 def _pct(v):
     import numpy as np
     v = np.asarray(v, dtype=np.float64)
+    v = v[~np.isnan(v)]
     return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)),
             "mean": float(v.mean()), "rms_jitter": float(v.std()), "max": float(v.max())}
 
@@ -319,7 +320,10 @@ def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s
             _, info = eng.wait_commands(idx, f, timeout_s=5.0)
             if f >= warmup:
                 host[idx].append((info["t_ready_ns"] - info["t_last_chunk_ns"]) / 1e3)
-                dev[idx].append((info["dev_ticks_cmd"] - info["dev_ticks_start"]) * 0.01)
+                # a frame published before its last chunk arrived (its last rows
+                # hold no pixel it needs) counts as 0
+                dev[idx].append(max(0, info["dev_ticks_cmd"] - info["dev_ticks_start"]) * 0.01
+                                if info["dev_ticks_start"] else float("nan"))
         if f >= warmup:
             fno.append(f)
         t_next = t_frame + period_s

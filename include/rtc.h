@@ -105,7 +105,10 @@ typedef struct {
     uint64_t frame;               /* frame number the commands belong to */
     int64_t t_last_chunk_ns;      /* host CLOCK_MONOTONIC at the last chunk's submission */
     int64_t t_ready_ns;           /* host CLOCK_MONOTONIC when the commands were seen */
-    uint64_t dev_ticks_start;     /* device 100 MHz clock: last chunk seen */
+    uint64_t dev_ticks_start;     /* device 100 MHz clock: last chunk seen (persistent
+                                     mode; 0 if not seen: a frame whose last chunks
+                                     hold no pixel it needs can be published first,
+                                     dev_ticks_cmd < dev_ticks_start then) */
     uint64_t dev_ticks_cmd;       /* device 100 MHz clock: commands published */
     uint32_t drops;               /* frames dropped on this instance so far */
     uint32_t reserved;

@@ -91,6 +91,7 @@ struct PersistInstState {
     uint64_t q_cur = 0;            // sequence number of the frame in progress
     std::vector<uint64_t> slot_frame;   // frame id of the frame in each slot
     std::vector<int64_t> slot_t_last;   // host clock at its last chunk
+    std::vector<uint64_t> slot_tlc0;    // the slot's last-chunk stamp before the frame (stale)
     std::vector<uint8_t> slot_dropped;
     uint64_t param_word = 0;       // (q_switch << 1) | staged slot, as last written
     uint64_t mword = 0;            // (q_mswitch << 1) | slot, as last written

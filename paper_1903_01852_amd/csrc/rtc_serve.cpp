@@ -22,6 +22,7 @@ namespace {
 constexpr uint64_t kIdleTicks = 10ull * 100000000ull;    // 10 s of the 100 MHz device clock
 constexpr uint64_t kDepTicks = 2ull * 100000000ull;      // 2 s for any internal dependency
 constexpr int64_t kStopTimeoutNs = 5000000000LL;
+constexpr int64_t kStampWaitNs = 2000000LL;     // last-chunk stamp after an early publication
 
 uint64_t db_word(uint64_t q, uint64_t chunks) { return (q << kDbShift) | chunks; }
 
@@ -330,6 +331,7 @@ rtc_status persist_alloc(rtc_engine *e) {
         TRY(host_pinned(e, &P.tel, e->ring_depth));
         P.slot_frame.assign(e->ring_depth, ~0ull);
         P.slot_t_last.assign(e->ring_depth, 0);
+        P.slot_tlc0.assign(e->ring_depth, 0);
         P.slot_dropped.assign(e->ring_depth, 0);
         // work of each column block; task 0 of each list goes to the worker
         // after the previous list's last task so that the load spreads evenly
@@ -675,6 +677,7 @@ rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int ch
         P.slot_frame[slot] = frame;
         P.slot_dropped[slot] = 0;
         P.slot_t_last[slot] = 0;
+        P.slot_tlc0[slot] = reinterpret_cast<volatile FrameTel *>(P.tel + slot)->ticks_last_chunk;
         I->cur_frame = frame;
         I->cur_started = false;
         for (auto &W : I->wfs) W.next_chunk = 0;
@@ -795,7 +798,17 @@ rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
         info->t_last_chunk_ns = P.slot_t_last[slot];
         info->t_ready_ns = t_ready;
         volatile FrameTel *tel = P.tel + slot;
-        info->dev_ticks_start = tel->ticks_last_chunk;
+        // a frame whose last chunks carry no pixel it needs is published before
+        // the loop sees those chunks arrive: wait briefly for that stamp (0 if
+        // it does not come)
+        uint64_t start = tel->ticks_last_chunk;
+        if (P.slot_t_last[slot] != 0) {
+            while (start == P.slot_tlc0[slot] && now_ns() - t_ready < kStampWaitNs) {
+                std::this_thread::yield();
+                start = tel->ticks_last_chunk;
+            }
+        }
+        info->dev_ticks_start = start == P.slot_tlc0[slot] ? 0 : start;
         info->dev_ticks_cmd = tel->ticks_publish;
         info->drops = I->drops;
     }
