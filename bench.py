@@ -38,6 +38,8 @@ Also reported on the same JSON line:
   mvm          the standalone MVM kernel per storage type, warm (back to back)
                and after a 1 GiB read-only flush of the caches;
   mvm_beyond_infinity_cache  the same on the matrices larger than the cache;
+  pyramid_normalisation  per-launch frames/s of the 92-pixel pyramid with local
+               and with global normalisation;
   cpu_baseline the CPU oracle on a bounded sample of the same frames.
 """
 from __future__ import annotations
@@ -471,6 +473,41 @@ def wfs_sweep(torch, rtc, n_frames, log):
     return res
 
 
+def pyramid_norms(torch, rtc, steps, log):
+    """Per-launch batch frames/s of the 92-pixel pyramid (5318 x 12288 FP32
+    matrix) with local and with global normalisation (the latter adds the
+    pupil-sum kernel before each frame's slopes)."""
+    import dataclasses
+    import synth
+    res = {}
+    base = synth.get_workload("scao_pyr_92")
+    for norm in ("local", "global"):
+        wfs = dataclasses.replace(base.instances[0].wfs[0], norm=norm)
+        inst = dataclasses.replace(base.instances[0], wfs=(wfs,))
+        wl = dataclasses.replace(base, name=f"scao_pyr_92_{norm}", instances=(inst,))
+        synth.workloads.WORKLOADS[wl.name] = wl
+        try:
+            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
+            R = synth.control_matrix(wl, 0)
+        finally:
+            del synth.workloads.WORKLOADS[wl.name]
+        eng = rtc.Engine([(inst, "f32")], mode="stream")
+        eng.load_matrices(0, R)
+        eng.load_calibration(0, 0, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
+        d = [torch.from_numpy(fr).cuda()]
+        st = torch.cuda.current_stream()
+        run_steps(eng, d, 16, 64, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(eng, d, 16, steps, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        eng.close()
+        res[norm] = {"frames_per_s": round(steps / dt, 1), "n_slopes": inst.n_slopes}
+        log(f"bench: pyramid 92 px {norm} normalisation: {steps / dt:.0f} frames/s")
+    return res
+
+
 # matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
 LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"),
              ("mcao_80", "bf16"), ("mcao_80", "fp8"))
@@ -700,6 +737,7 @@ def main():
     sweep = None
     if not args.quick and not args.no_latency and not args.no_sweep:
         sweep = wfs_sweep(torch, rtc, args.sweep_frames, log)
+    pyr_norm = None if args.quick else pyramid_norms(torch, rtc, 2000, log)
 
     cpu = None
     if not args.quick and not args.no_cpu_baseline:
@@ -740,6 +778,7 @@ def main():
         "mvm": {k: rnd(v) for k, v in mvm.items()},
         "mvm_beyond_infinity_cache": large,
         "latency_sweep_us": ({**sweep, "what": SERVING_NOTE} if sweep else None),
+        "pyramid_normalisation": pyr_norm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

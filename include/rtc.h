@@ -59,6 +59,12 @@ enum { RTC_CM_F32 = 0, RTC_CM_BF16 = 1, RTC_CM_FP8 = 2 };
 /* Threshold after calibration, c = ((raw - dark) * flat) - bg in binary32:
  * SUBTRACT: w = c > T ? c - T : 0;  ZERO: w = c > T ? c : 0;  NONE: w = c. */
 enum { RTC_THR_SUBTRACT = 0, RTC_THR_ZERO = 1, RTC_THR_NONE = 2 };
+/* Pyramid normalisation: LOCAL divides each pupil pixel's differences by its
+ * own four-image sum (section 2.2: four pixels per slope, so slopes follow the
+ * rows as they arrive); GLOBAL by one sum over every valid pupil pixel of the
+ * frame, so the sensor's slopes wait for its whole frame.  GLOBAL is available
+ * in RTC_MODE_STREAM only (rtc_create gives RTC_E_INVAL otherwise). */
+enum { RTC_PYR_NORM_LOCAL = 0, RTC_PYR_NORM_GLOBAL = 1 };
 /* STREAM: each chunk submission enqueues its own kernels on the engine stream.
  * PERSISTENT: one resident kernel polls the pinned pixel ring and runs the
  * whole frame loop on the device. */
@@ -82,6 +88,7 @@ typedef struct {
     int32_t pupil_px;
     int32_t quad_row[4], quad_col[4];
     const uint8_t *pupil_valid;   /* host, pupil_px*pupil_px flags */
+    int32_t pyr_norm;             /* RTC_PYR_NORM_* */
 } rtc_wfs_desc;
 
 typedef struct {

@@ -133,7 +133,9 @@ def pyr_slopes(raw: np.ndarray, wfs, cal):
     Section 2.2: a pyramid slope is formed from the relative x and y
     differences of corresponding pixels of the four pupil images, four pixels
     per slope.  Sx = (I1 + I2 - I3 - I4) / S and Sy = (I1 + I3 - I2 - I4) / S
-    with the local sum S = I1 + I2 + I3 + I4; S <= 0 gives (0, 0).
+    with the local sum S = I1 + I2 + I3 + I4 (wfs.norm "local"), or with one
+    sum S over every valid pupil pixel of the four images ("global"); S <= 0
+    gives (0, 0).
     Returns (slopes, counts of masked quadrant pixels per pupil pixel, masks
     (n, 4)).
     """
@@ -148,6 +150,8 @@ def pyr_slopes(raw: np.ndarray, wfs, cal):
         masks.append(m)
     i1, i2, i3, i4 = quads
     s = i1 + i2 + i3 + i4
+    if getattr(wfs, "norm", "local") == "global":
+        s = np.full_like(s, s.sum())
     n = s.shape[0]
     out = np.zeros((n, 2))
     ok = s > 0

@@ -222,18 +222,19 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
 
 // Pyramid unit: one lane.  Calibration arrays are [quadrant][unit] so that
 // lanes read consecutive addresses.
-template <int SP, int LP = LOAD_PLAIN>
-__device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, float T,
-                                         const uint16_t *__restrict__ fr, const WfsParam &P,
-                                         const float *__restrict__ dark4,
-                                         const float *__restrict__ flat4,
-                                         const float *__restrict__ bg4,
-                                         const float *__restrict__ ref, const SlopeOut &o) {
+// Calibrated, thresholded intensities of pupil pixel k in the four images
+// (bit q of the return value: the pixel of image q is in the mask).
+template <int LP = LOAD_PLAIN>
+__device__ __forceinline__ uint64_t pyr_intensities(const PyrUnit &d, int k, int n_pyr, float T,
+                                                    const uint16_t *__restrict__ fr,
+                                                    const WfsParam &P,
+                                                    const float *__restrict__ dark4,
+                                                    const float *__restrict__ flat4,
+                                                    const float *__restrict__ bg4, float (&I)[4]) {
     uint32_t raw[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         raw[q] = load_px<LP>(fr + (size_t)(P.qrow[q] + d.i) * P.W + (P.qcol[q] + d.j));
-    float I[4];
     uint64_t bits = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -243,7 +244,23 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
         I[q] = threshold_px(cv, T, P.thr_mode, m);
         bits |= (uint64_t)m << q;
     }
-    const float S = (I[0] + I[1]) + (I[2] + I[3]);
+    return bits;
+}
+
+// gsum: per sensor, the frame's intensity sum over the pupil (sensors with
+// global normalisation; unused otherwise).
+template <int SP, int LP = LOAD_PLAIN>
+__device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, float T,
+                                         const uint16_t *__restrict__ fr, const WfsParam &P,
+                                         const float *__restrict__ dark4,
+                                         const float *__restrict__ flat4,
+                                         const float *__restrict__ bg4,
+                                         const float *__restrict__ ref, const SlopeOut &o,
+                                         const float *__restrict__ gsum) {
+    float I[4];
+    const uint64_t bits = pyr_intensities<LP>(d, k, n_pyr, T, fr, P, dark4, flat4, bg4, I);
+    const float S =
+        P.norm == RTC_PYR_NORM_GLOBAL ? gbl(gsum)[d.wfs] : (I[0] + I[1]) + (I[2] + I[3]);
     float sx = 0.0f, sy = 0.0f;
     if (S > 0.0f) {
         sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - gbl(ref)[2 * d.unit];

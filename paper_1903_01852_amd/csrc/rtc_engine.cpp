@@ -66,6 +66,8 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
         if (w.origin_col + (int64_t)w.nsub * w.px > w.frame_w) return RTC_E_INVAL;
     } else if (w.kind == RTC_WFS_PYR) {
         if (w.pupil_px <= 0 || !w.pupil_valid) return RTC_E_INVAL;
+        if (w.pyr_norm != RTC_PYR_NORM_LOCAL && w.pyr_norm != RTC_PYR_NORM_GLOBAL)
+            return RTC_E_INVAL;
         for (int q = 0; q < 4; ++q) {
             if (w.quad_row[q] < 0 || w.quad_col[q] < 0) return RTC_E_INVAL;
             if (w.quad_row[q] + w.pupil_px > w.frame_h) return RTC_E_INVAL;
@@ -149,6 +151,10 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
             }
             int qmax = 0;
             for (int q = 0; q < 4; ++q) qmax = std::max(qmax, d.quad_row[q]);
+            // globally normalised slopes all complete with the frame's last row
+            const bool global = d.pyr_norm == RTC_PYR_NORM_GLOBAL;
+            P.norm = d.pyr_norm;
+            if (global) I->pyr_global.w[I->pyr_global.n++] = w;
             S.kind0 = (int)I->py.size();
             for (int i = 0; i < d.pupil_px; ++i)
                 for (int j = 0; j < d.pupil_px; ++j) {
@@ -161,8 +167,10 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                     u.mask = mask;
                     mask += 1;
                     I->py.push_back(u);
-                    S.unit_ready.push_back(qmax + i);
+                    S.unit_ready.push_back(global ? d.frame_h - 1 : qmax + i);
                 }
+            P.pu0 = S.kind0;
+            P.pn = (int)I->py.size() - S.kind0;
         }
         S.u1 = unit;
         if (S.u1 == S.u0) return RTC_E_INVAL;    // a sensor without units
@@ -324,6 +332,7 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_py_bg, 4 * I->py.size()));
     TRY(dev_alloc(e, &I->d_py_thr, I->py.size()));
     TRY(dev_alloc(e, &I->d_ref, I->n_slopes));
+    TRY(dev_alloc(e, &I->d_pyr_sum, RTC_MAX_WFS));
     TRY(dev_alloc(e, &I->d_spad, I->spad_len));
     TRY(dev_alloc(e, &I->d_spad2, I->spad_len));
     TRY(dev_alloc(e, &I->d_sout, I->n_slopes));
@@ -430,9 +439,16 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
                            I->d_counts, I->d_masks);
     } else {
         const int a = S.kind0 + (u_begin - S.u0), b = S.kind0 + (u_end - S.u0);
+        if (S.d.pyr_norm == RTC_PYR_NORM_GLOBAL) {
+            WfsList one{};
+            one.w[0] = w;
+            one.n = 1;
+            launch_pyr_sum(st, I->d_py, I->n_pyr, fs, I->params, I->d_py_dark, I->d_py_flat,
+                           I->d_py_bg, I->d_py_thr, one, I->d_pyr_sum);
+        }
         launch_pyr_slopes(st, I->d_py, a, b, I->n_pyr, fs, I->params, I->d_py_dark,
                           I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, I->d_spad,
-                          I->d_sout, I->d_counts, I->d_masks);
+                          I->d_sout, I->d_counts, I->d_masks, I->d_pyr_sum);
     }
 }
 
@@ -651,8 +667,13 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
         if (d.n_wfs < 1 || d.n_wfs > RTC_MAX_WFS || !d.wfs || d.n_act < 1) return RTC_E_INVAL;
         if (d.cm_dtype < RTC_CM_F32 || d.cm_dtype > RTC_CM_FP8) return RTC_E_INVAL;
         if (!std::isfinite(d.gain) || !std::isfinite(d.leak)) return RTC_E_INVAL;
-        for (int w = 0; w < d.n_wfs; ++w)
+        for (int w = 0; w < d.n_wfs; ++w) {
             if (validate_wfs(d.wfs[w]) != RTC_OK) return RTC_E_INVAL;
+            // the frame loop forms pyramid slopes block by block as rows arrive
+            if (d.wfs[w].kind == RTC_WFS_PYR && d.wfs[w].pyr_norm == RTC_PYR_NORM_GLOBAL &&
+                desc->mode != RTC_MODE_STREAM)
+                return RTC_E_INVAL;
+        }
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev)
@@ -1034,10 +1055,13 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             launch_sh_centroid(st, I->d_sh, 0, I->n_sh, fs, I->params, I->d_sh_dark,
                                I->d_sh_flat, I->d_sh_bg, I->d_sh_thr, I->d_ref, spad[0],
                                I->d_sout, I->d_counts, I->d_masks);
-        if (I->n_pyr > 0)
+        if (I->n_pyr > 0) {
+            launch_pyr_sum(st, I->d_py, I->n_pyr, fs, I->params, I->d_py_dark, I->d_py_flat,
+                           I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
             launch_pyr_slopes(st, I->d_py, 0, I->n_pyr, I->n_pyr, fs, I->params, I->d_py_dark,
                               I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, spad[0],
-                              I->d_sout, I->d_counts, I->d_masks);
+                              I->d_sout, I->d_counts, I->d_masks, I->d_pyr_sum);
+        }
         TRY(copy_out(0));
     }
     for (int f = 0; f < n_frames; ++f) {
@@ -1064,6 +1088,10 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
             N.py_flat = I->d_py_flat;
             N.py_bg = I->d_py_bg;
             N.py_thr = I->d_py_thr;
+            N.py_gsum = I->d_pyr_sum;
+            // frame f + 1's pupil sums before the grid that forms its slopes
+            launch_pyr_sum(st, I->d_py, I->n_pyr, N.frames, I->params, I->d_py_dark,
+                           I->d_py_flat, I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
             N.ref = I->d_ref;
             N.s_pad = spad[(f + 1) & 1];
             N.s_out = I->d_sout;

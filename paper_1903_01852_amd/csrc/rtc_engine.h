@@ -135,6 +135,7 @@ struct Instance {
     int64_t cm_bytes = 0, m_bytes = 0;
     bool stream_nt = false;        // non-temporal matrix loads (the engine's matrices exceed the cache)
     WfsParamSet params{};
+    rtc::WfsList pyr_global{};     // pyramid sensors with global normalisation
     // device
     ShUnit *d_sh = nullptr;
     PyrUnit *d_py = nullptr;
@@ -145,6 +146,7 @@ struct Instance {
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
     float *d_ref = nullptr;
+    float *d_pyr_sum = nullptr;    // per sensor: the frame's pupil sum (global normalisation)
     float *d_spad = nullptr, *d_sout = nullptr;
     float *d_spad2 = nullptr;      // per-launch batch: slopes of the next frame
     int32_t *d_counts = nullptr;

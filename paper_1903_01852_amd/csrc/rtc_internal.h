@@ -24,8 +24,9 @@ struct WfsParam {
     int32_t thr_mode;      // RTC_THR_*
     int32_t mask_words;    // SH: ceil(p*p/64)
     float half;            // SH: (p - 1) / 2
-    int32_t pad0;
+    int32_t norm;          // pyramid: RTC_PYR_NORM_*
     int32_t qrow[4], qcol[4];
+    int32_t pu0, pn;       // pyramid: the sensor's units [pu0, pu0 + pn) of the unit list
 };
 
 struct WfsParamSet {
@@ -34,6 +35,12 @@ struct WfsParamSet {
 
 struct FrameSet {
     const uint16_t *f[RTC_MAX_WFS];
+};
+
+// A list of sensors (indices into the instance's sensors).
+struct WfsList {
+    int32_t w[RTC_MAX_WFS];
+    int32_t n;
 };
 
 // One Shack-Hartmann subaperture (32 bytes).
@@ -291,7 +298,12 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        const FrameSet &frames, const WfsParamSet &params,
                        const float *dark4, const float *flat4, const float *bg4,
                        const float *thr, const float *ref, float *s_pad, float *s_out,
-                       int32_t *counts, uint64_t *masks);
+                       int32_t *counts, uint64_t *masks, const float *gsum);
+// Per sensor of `wfs` (pyramids with global normalisation), the frame's
+// intensity sum over the pupil into gsum[sensor].
+void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const FrameSet &frames,
+                    const WfsParamSet &params, const float *dark4, const float *flat4,
+                    const float *bg4, const float *thr, const WfsList &wfs, float *gsum);
 // stream_nt: stream the matrix with non-temporal loads (matrices larger than
 // the Infinity Cache); otherwise ordinary loads keep a smaller matrix resident.
 constexpr int64_t kCacheResidentBytes = 192ll << 20;
@@ -311,6 +323,7 @@ struct NextSlopes {
     float *s_pad, *s_out;
     int32_t *counts;
     uint64_t *masks;
+    const float *py_gsum;          // pyramid sensors with global normalisation: frame sums
 };
 // launch_mvm (reading x_pad) plus, in the same grid, the slopes of the next
 // frame into next.s_pad (a different buffer than x_pad).

@@ -44,12 +44,43 @@ __global__ __launch_bounds__(256) void k_pyr_slopes(
     const PyrUnit *__restrict__ units, int u0, int u1, int n_pyr, FrameSet frames,
     WfsParamSet params, const float *__restrict__ dark4, const float *__restrict__ flat4,
     const float *__restrict__ bg4, const float *__restrict__ thr,
-    const float *__restrict__ ref, SlopeOut o) {
+    const float *__restrict__ ref, SlopeOut o, const float *__restrict__ gsum) {
     const int k = u0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= u1) return;
     const PyrUnit d = units[k];
     pyr_unit<STORE_PLAIN>(d, k, n_pyr, thr[k], frames.f[d.wfs], params.w[d.wfs], dark4, flat4,
-                          bg4, ref, o);
+                          bg4, ref, o, gsum);
+}
+
+// Global normalisation: the frame's intensity sum over the pupil of pyramid
+// sensor wfs[blockIdx.x] (every valid pixel, its four images).  Thread t adds
+// the sensor's units t, t + 256, ... in order, then a fixed halving tree in LDS
+// adds the 256 partial sums: the same value on every run and path.
+__global__ __launch_bounds__(256) void k_pyr_sum(const PyrUnit *__restrict__ units, int n_pyr,
+                                                 FrameSet frames, WfsParamSet params,
+                                                 const float *__restrict__ dark4,
+                                                 const float *__restrict__ flat4,
+                                                 const float *__restrict__ bg4,
+                                                 const float *__restrict__ thr, WfsList wfs,
+                                                 float *__restrict__ gsum) {
+    __shared__ float part[256];
+    const int w = wfs.w[blockIdx.x];
+    const WfsParam &P = params.w[w];
+    float acc = 0.0f;
+    for (int j = (int)threadIdx.x; j < P.pn; j += 256) {
+        const int k = P.pu0 + j;
+        const PyrUnit d = units[k];
+        float I[4];
+        (void)pyr_intensities(d, k, n_pyr, thr[k], frames.f[w], P, dark4, flat4, bg4, I);
+        acc += (I[0] + I[1]) + (I[2] + I[3]);
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gsum[w] = part[0];
 }
 
 // Epilogue run by the last wavefront to finish a 64-row tile (every column
@@ -176,7 +207,7 @@ __global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm
         if (k >= N.n_pyr) return;
         const PyrUnit d = N.py[k];
         pyr_unit<STORE_PLAIN>(d, k, N.n_pyr, N.py_thr[k], N.frames.f[d.wfs], params.w[d.wfs],
-                              N.py_dark, N.py_flat, N.py_bg, N.ref, o);
+                              N.py_dark, N.py_flat, N.py_bg, N.ref, o, N.py_gsum);
     }
 }
 
@@ -242,12 +273,20 @@ void launch_pyr_slopes(hipStream_t st, const PyrUnit *units, int u0, int u1, int
                        const FrameSet &frames, const WfsParamSet &params, const float *dark4,
                        const float *flat4, const float *bg4, const float *thr,
                        const float *ref, float *s_pad, float *s_out, int32_t *counts,
-                       uint64_t *masks) {
+                       uint64_t *masks, const float *gsum) {
     const int n = u1 - u0;
     if (n <= 0) return;
     const SlopeOut o{s_pad, s_out, counts, masks};
     hipLaunchKernelGGL(k_pyr_slopes, dim3((n + 255) / 256), dim3(256), 0, st, units, u0, u1,
-                       n_pyr, frames, params, dark4, flat4, bg4, thr, ref, o);
+                       n_pyr, frames, params, dark4, flat4, bg4, thr, ref, o, gsum);
+}
+
+void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const FrameSet &frames,
+                    const WfsParamSet &params, const float *dark4, const float *flat4,
+                    const float *bg4, const float *thr, const WfsList &wfs, float *gsum) {
+    if (wfs.n <= 0) return;
+    hipLaunchKernelGGL(k_pyr_sum, dim3(wfs.n), dim3(256), 0, st, units, n_pyr, frames, params,
+                       dark4, flat4, bg4, thr, wfs, gsum);
 }
 
 // Vectors per batch: 16 for FP32; 8 for BF16 and FP8, whose batch of slope

@@ -603,12 +603,15 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
             const int k = W.cu0 + jc * kWave + lane;
             if (k < W.cu1) {
                 const PyrUnit d = ldg(I.py + k);
+                // global normalisation is per-launch only (rejected at create)
                 if (I.serving)
                     pyr_unit<STORE_AGENT, LOAD_AGENT>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
-                                                       I.py_dark, I.py_flat, I.py_bg, I.ref, so);
+                                                       I.py_dark, I.py_flat, I.py_bg, I.ref, so,
+                                                       nullptr);
                 else
                     pyr_unit<STORE_AGENT, LOAD_PLAIN>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
-                                                      I.py_dark, I.py_flat, I.py_bg, I.ref, so);
+                                                      I.py_dark, I.py_flat, I.py_bg, I.ref, so,
+                                                      nullptr);
             }
         }
     }

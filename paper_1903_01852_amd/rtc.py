@@ -23,6 +23,7 @@ CM_DTYPE = {"f32": 0, "bf16": 1, "fp8": 2}
 CM_ELEM = {"f32": 4, "bf16": 2, "fp8": 1}
 THR_MODE = {"subtract": 0, "zero": 1, "none": 2}
 MODE = {"stream": 0, "persistent": 1}
+PYR_NORM = {"local": 0, "global": 1}
 MAX_WFS = 16
 
 EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chunk_rows",
@@ -48,7 +49,8 @@ class WfsDescC(C.Structure):
                 ("nsub", C.c_int32), ("px", C.c_int32), ("origin_row", C.c_int32),
                 ("origin_col", C.c_int32), ("subap_valid", C.POINTER(C.c_uint8)),
                 ("pupil_px", C.c_int32), ("quad_row", C.c_int32 * 4),
-                ("quad_col", C.c_int32 * 4), ("pupil_valid", C.POINTER(C.c_uint8))]
+                ("quad_col", C.c_int32 * 4), ("pupil_valid", C.POINTER(C.c_uint8)),
+                ("pyr_norm", C.c_int32)]
 
 
 class InstanceDescC(C.Structure):
@@ -168,6 +170,7 @@ def wfs_to_c(w, keep: list) -> WfsDescC:
         for q, (r, c) in enumerate(w.quad_origins):
             d.quad_row[q], d.quad_col[q] = int(r), int(c)
         d.pupil_valid = vptr
+        d.pyr_norm = PYR_NORM[getattr(w, "norm", "local")]
     return d
 
 

@@ -73,6 +73,7 @@ class PyrWfs:
     threshold: float = 0.0
     thr_mode: str = "none"
     photons_per_px: float = 100.0   # expected photo-electrons per quadrant pixel
+    norm: str = "local"             # "local": per-pixel sum; "global": sum over the pupil
     kind: str = field(default="pyr", init=False)
 
     @cached_property

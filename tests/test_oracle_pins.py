@@ -206,6 +206,45 @@ def test_pyramid_linear_surrogate_exact():
     assert np.all(counts == 4)
 
 
+def test_pyramid_global_normalisation():
+    """One sum over the pupil: in the linear surrogate every pixel's four images
+    add to F (the gradient terms cancel), so S = N F and (Sx, Sy) = (g_x, g_y) / N
+    exactly for N valid pixels; uniform images still give 0; a pupil of one
+    valid pixel gives the local slopes."""
+    import dataclasses
+    wfs = dataclasses.replace(synth.PyrWfs(), norm="global")
+    rng = np.random.default_rng(6)
+    n = wfs.pupil_px
+    gx = rng.integers(-32, 33, (n, n)) / 64.0
+    gy = rng.integers(-32, 33, (n, n)) / 64.0
+    img = np.zeros((wfs.frame_h, wfs.frame_w))
+    for (r0, c0), (sx, sy) in zip(wfs.quad_origins, ((1, 1), (1, -1), (-1, 1), (-1, -1))):
+        img[r0:r0 + n, c0:c0 + n] = 64.0 * (1 + sx * gx + sy * gy)
+    s = oracle.pyr_slopes(img, wfs, _pyr_cal(wfs))[0].reshape(-1, 2)
+    N = int(wfs.valid.sum())
+    assert np.abs(s[:, 0] - gx[wfs.valid] / N).max() <= 1e-15
+    assert np.abs(s[:, 1] - gy[wfs.valid] / N).max() <= 1e-15
+    assert np.all(oracle.pyr_slopes(np.full_like(img, 80.0), wfs, _pyr_cal(wfs))[0] == 0)
+    local = synth.PyrWfs()
+    one = np.zeros_like(wfs.valid)
+    one[n // 2, 3] = True
+    wl_ = dataclasses.replace(local, pupil_px=n)
+    g1 = type("W", (), {})()
+    for k in ("pupil_px", "quad_origins", "thr_mode", "frame_h", "frame_w"):
+        setattr(g1, k, getattr(wl_, k))
+    g1.valid, g1.n_units, g1.norm = one, 1, "global"
+    l1 = type("W", (), {})()
+    for k in ("pupil_px", "quad_origins", "thr_mode", "frame_h", "frame_w"):
+        setattr(l1, k, getattr(wl_, k))
+    l1.valid, l1.n_units, l1.norm = one, 1, "local"
+    cal = _pyr_cal(wl_)
+    cal1 = synth.Calibration(dark=cal.dark, flat=cal.flat, bg=cal.bg, thr=cal.thr,
+                             ref=np.zeros(2, np.float32), gain_map=cal.gain_map,
+                             dark_true=cal.dark_true)
+    noisy = rng.uniform(10, 200, img.shape)
+    assert np.array_equal(oracle.pyr_slopes(noisy, g1, cal1)[0], oracle.pyr_slopes(noisy, l1, cal1)[0])
+
+
 def test_pyramid_quadrant_signs():
     """Light in one pupil image only: (Sx, Sy) = (+,+) I1, (+,-) I2, (-,+) I3, (-,-) I4."""
     wfs = synth.PyrWfs()
