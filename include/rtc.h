@@ -62,8 +62,8 @@ enum { RTC_THR_SUBTRACT = 0, RTC_THR_ZERO = 1, RTC_THR_NONE = 2 };
 /* Pyramid normalisation: LOCAL divides each pupil pixel's differences by its
  * own four-image sum (section 2.2: four pixels per slope, so slopes follow the
  * rows as they arrive); GLOBAL by one sum over every valid pupil pixel of the
- * frame, so the sensor's slopes wait for its whole frame.  GLOBAL is available
- * in RTC_MODE_STREAM only (rtc_create gives RTC_E_INVAL otherwise). */
+ * frame (formed in one fixed order, so every path gives the same value), so
+ * the sensor's slopes wait for its whole frame and form one column block. */
 enum { RTC_PYR_NORM_LOCAL = 0, RTC_PYR_NORM_GLOBAL = 1 };
 /* STREAM: each chunk submission enqueues its own kernels on the engine stream.
  * PERSISTENT: one resident kernel polls the pinned pixel ring and runs the

@@ -247,8 +247,43 @@ __device__ __forceinline__ uint64_t pyr_intensities(const PyrUnit &d, int k, int
     return bits;
 }
 
-// gsum: per sensor, the frame's intensity sum over the pupil (sensors with
-// global normalisation; unused otherwise).
+// The frame's intensity sum over the pupil of pyramid sensor P by one
+// wavefront, in exactly the order of k_pyr_sum's 256 threads: lane l holds the
+// running sums of threads l, l + 64, l + 128, l + 192 (units t, t + 256, ... in
+// order), then the same halving tree, its first two levels in registers and
+// the rest across lanes.  Every lane returns the sum.
+template <int LP = LOAD_PLAIN>
+__device__ __forceinline__ float pyr_pupil_sum_wave(const PyrUnit *__restrict__ units, int n_pyr,
+                                                    const float *__restrict__ thr,
+                                                    const uint16_t *__restrict__ fr,
+                                                    const WfsParam &P,
+                                                    const float *__restrict__ dark4,
+                                                    const float *__restrict__ flat4,
+                                                    const float *__restrict__ bg4, int lane) {
+    float a[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j0 = 0; j0 < P.pn; j0 += 256) {
+#pragma unroll 1
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + c * kWave + lane;
+            if (j < P.pn) {
+                const int k = P.pu0 + j;
+                const PyrUnit d = ldg(units + k);
+                float I[4];
+                (void)pyr_intensities<LP>(d, k, n_pyr, gbl(thr)[k], fr, P, dark4, flat4, bg4, I);
+                a[c] += (I[0] + I[1]) + (I[2] + I[3]);
+            }
+        }
+    }
+    a[0] += a[2];
+    a[1] += a[3];
+    a[0] += a[1];
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1) a[0] += __shfl_down(a[0], h, kWave);
+    return __shfl(a[0], 0, kWave);
+}
+
+// gS: the frame's intensity sum over the pupil (sensors with global
+// normalisation; unused otherwise).
 template <int SP, int LP = LOAD_PLAIN>
 __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, float T,
                                          const uint16_t *__restrict__ fr, const WfsParam &P,
@@ -256,11 +291,10 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
                                          const float *__restrict__ flat4,
                                          const float *__restrict__ bg4,
                                          const float *__restrict__ ref, const SlopeOut &o,
-                                         const float *__restrict__ gsum) {
+                                         float gS) {
     float I[4];
     const uint64_t bits = pyr_intensities<LP>(d, k, n_pyr, T, fr, P, dark4, flat4, bg4, I);
-    const float S =
-        P.norm == RTC_PYR_NORM_GLOBAL ? gbl(gsum)[d.wfs] : (I[0] + I[1]) + (I[2] + I[3]);
+    const float S = P.norm == RTC_PYR_NORM_GLOBAL ? gS : (I[0] + I[1]) + (I[2] + I[3]);
     float sx = 0.0f, sy = 0.0f;
     if (S > 0.0f) {
         sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - gbl(ref)[2 * d.unit];

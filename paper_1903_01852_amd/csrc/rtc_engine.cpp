@@ -667,13 +667,8 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
         if (d.n_wfs < 1 || d.n_wfs > RTC_MAX_WFS || !d.wfs || d.n_act < 1) return RTC_E_INVAL;
         if (d.cm_dtype < RTC_CM_F32 || d.cm_dtype > RTC_CM_FP8) return RTC_E_INVAL;
         if (!std::isfinite(d.gain) || !std::isfinite(d.leak)) return RTC_E_INVAL;
-        for (int w = 0; w < d.n_wfs; ++w) {
+        for (int w = 0; w < d.n_wfs; ++w)
             if (validate_wfs(d.wfs[w]) != RTC_OK) return RTC_E_INVAL;
-            // the frame loop forms pyramid slopes block by block as rows arrive
-            if (d.wfs[w].kind == RTC_WFS_PYR && d.wfs[w].pyr_norm == RTC_PYR_NORM_GLOBAL &&
-                desc->mode != RTC_MODE_STREAM)
-                return RTC_E_INVAL;
-        }
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || desc->device < 0 || desc->device >= ndev)

@@ -48,8 +48,9 @@ __global__ __launch_bounds__(256) void k_pyr_slopes(
     const int k = u0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= u1) return;
     const PyrUnit d = units[k];
-    pyr_unit<STORE_PLAIN>(d, k, n_pyr, thr[k], frames.f[d.wfs], params.w[d.wfs], dark4, flat4,
-                          bg4, ref, o, gsum);
+    const WfsParam &P = params.w[d.wfs];
+    pyr_unit<STORE_PLAIN>(d, k, n_pyr, thr[k], frames.f[d.wfs], P, dark4, flat4, bg4, ref, o,
+                          P.norm == RTC_PYR_NORM_GLOBAL ? gsum[d.wfs] : 0.0f);
 }
 
 // Global normalisation: the frame's intensity sum over the pupil of pyramid
@@ -206,8 +207,10 @@ __global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm
         const int k = (b - sh_blocks) * 256 + (int)threadIdx.x;
         if (k >= N.n_pyr) return;
         const PyrUnit d = N.py[k];
-        pyr_unit<STORE_PLAIN>(d, k, N.n_pyr, N.py_thr[k], N.frames.f[d.wfs], params.w[d.wfs],
-                              N.py_dark, N.py_flat, N.py_bg, N.ref, o, N.py_gsum);
+        const WfsParam &P = params.w[d.wfs];
+        pyr_unit<STORE_PLAIN>(d, k, N.n_pyr, N.py_thr[k], N.frames.f[d.wfs], P, N.py_dark,
+                              N.py_flat, N.py_bg, N.ref, o,
+                              P.norm == RTC_PYR_NORM_GLOBAL ? N.py_gsum[d.wfs] : 0.0f);
     }
 }
 

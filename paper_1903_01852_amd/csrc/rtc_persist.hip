@@ -587,6 +587,18 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
     const uint16_t *fr = frame_src(I, W.wfs, q);
     WfsParam P = ldc(I.wp + W.wfs);
     P.W = I.src_pitch[W.wfs];            // row pitch of the frame source
+    // global normalisation: the sensor's one block waits for its whole frame,
+    // and each wavefront forms the pupil sum itself (no cross-wavefront
+    // dependency), in the per-launch path's order
+    float gS = 0.0f;
+    if (W.kind == RTC_WFS_PYR && P.norm == RTC_PYR_NORM_GLOBAL) {
+        if (I.serving)
+            gS = pyr_pupil_sum_wave<LOAD_AGENT>(I.py, I.n_pyr, I.py_thr, fr, P, I.py_dark,
+                                                I.py_flat, I.py_bg, lane);
+        else
+            gS = pyr_pupil_sum_wave<LOAD_PLAIN>(I.py, I.n_pyr, I.py_thr, fr, P, I.py_dark,
+                                                I.py_flat, I.py_bg, lane);
+    }
     for (; j < end; j += nw) {
         const int jc = j - W.cen_base;
         if (stripe_lane(global_idx ? j : jc, lane)) ++cnt;
@@ -603,15 +615,14 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
             const int k = W.cu0 + jc * kWave + lane;
             if (k < W.cu1) {
                 const PyrUnit d = ldg(I.py + k);
-                // global normalisation is per-launch only (rejected at create)
                 if (I.serving)
                     pyr_unit<STORE_AGENT, LOAD_AGENT>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
                                                        I.py_dark, I.py_flat, I.py_bg, I.ref, so,
-                                                       nullptr);
+                                                       gS);
                 else
                     pyr_unit<STORE_AGENT, LOAD_PLAIN>(d, k, I.n_pyr, gbl(I.py_thr)[k], fr, P,
                                                       I.py_dark, I.py_flat, I.py_bg, I.ref, so,
-                                                      nullptr);
+                                                      gS);
             }
         }
     }

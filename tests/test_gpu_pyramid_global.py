@@ -2,11 +2,9 @@
 
 The per-launch path forms each frame's pupil sum in a fixed order, then the
 slopes; the commands must match the oracle to the FP32 bar, the thresholded
-pixel counts bit for bit, and the serving form must give the batch commands
-bit for bit.  The frame loop does not take such sensors.
+pixel counts bit for bit, and the serving forms and the frame loop must give
+the per-launch batch commands bit for bit.
 """
-import dataclasses
-
 import numpy as np
 import pytest
 
@@ -74,12 +72,20 @@ def test_pyramid_global_serving_equals_batch(rtc):
         assert rel_l2(served, ref["commands"]).max() <= TOL["f32"]
 
 
-def test_pyramid_global_needs_per_launch_mode(rtc):
-    case = _global_case(2, n_act=300, index=97)
-    with pytest.raises(rtc.RtcError) as ei:
-        rtc.Engine([(case.inst, "f32")], mode="persistent")
-    assert ei.value.status == -1
-    local = dataclasses.replace(case.inst.wfs[0], norm="local")
-    inst = dataclasses.replace(case.inst, wfs=(local,))
-    with rtc.Engine([(inst, "f32")], mode="persistent") as eng:
-        assert eng.infos[0]["n_slopes"] == case.inst.n_slopes
+def test_pyramid_global_frame_loop_equals_launch_path(rtc):
+    """The frame loop (each wavefront forms the pupil sum itself, in the sum
+    kernel's order) gives the per-launch commands, slopes and counts bit for
+    bit, in batch and in serving."""
+    case = _global_case(8, pupil_px=92, n_act=700, index=97)
+    with rtc.Engine([(case.inst, "f32")], mode="stream") as eng:
+        case.load(eng)
+        c1, s1, n1 = run_batch(eng, 0, case)
+    with rtc.Engine([(case.inst, "f32")], mode="persistent") as eng:
+        case.load(eng)
+        c2, s2, n2 = run_batch(eng, 0, case)
+        eng.set_state(0, None, None, 0)
+        served, _ = run_stream(eng, 0, case)
+    assert np.array_equal(n1, n2)
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(c1, served)
