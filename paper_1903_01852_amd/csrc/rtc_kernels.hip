@@ -68,6 +68,9 @@ __global__ __launch_bounds__(256) void k_pyr_sum(const PyrUnit *__restrict__ uni
     const int w = wfs.w[blockIdx.x];
     const WfsParam &P = params.w[w];
     float acc = 0.0f;
+    // unrolled so that several units' loads are in flight; the additions stay
+    // in unit order
+#pragma unroll 4
     for (int j = (int)threadIdx.x; j < P.pn; j += 256) {
         const int k = P.pu0 + j;
         const PyrUnit d = units[k];
