@@ -474,7 +474,13 @@ void persist_reset(Instance *I) {
     }
     persist_mswap(I, ~0ull >> 2, 1 - I->m_active);   // every frame on the active slot
     P.mq_last = 0;
+    // frames count from 0 again: no part flag may still name one of them
     P.tel_next = 0;
+    if (P.tel_slots > 0) {
+        std::memset(P.tel_flags, 0, (size_t)P.tel_slots * kTelMaxTasks * 8);
+        std::fill(P.tel_frame.begin(), P.tel_frame.end(), ~0ull);
+        std::fill(P.tel_dropped.begin(), P.tel_dropped.end(), 0);
+    }
 }
 
 void persist_telemetry_free(Instance *I) {
@@ -554,20 +560,25 @@ rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int
             q = P.tel_next;
             k = (size_t)((q >> P.tel_dshift) & (uint64_t)(P.tel_slots - 1));
         }
-        // every part of the record copied for frame q
+        // every part of the record copied for frame q (a part already holding
+        // a later frame's copy: the record was overwritten, skip ahead)
         uint64_t *flags = P.tel_flags + k * kTelMaxTasks;
         const int nt = tel_tasks(I);
-        for (int j = 0; j < nt;) {
-            if (load_acquire(flags + j) == q + 1) {
+        bool overwritten = false;
+        for (int j = 0; j < nt && !overwritten;) {
+            const uint64_t fv = load_acquire(flags + j);
+            if (fv == q + 1) {
                 ++j;
                 continue;
             }
+            overwritten = fv > q + 1;
             if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
             if (e->pe.running && stream_done(e->pe.stream) &&
                 *reinterpret_cast<volatile uint32_t *>(e->pe.status) != PERSIST_OK)
                 return fail(e, RTC_E_DEVICE);
             std::this_thread::yield();
         }
+        if (overwritten) continue;
         const float *rec = P.tel_host + k * (size_t)P.tel_rec;
         if (slopes) std::memcpy(slopes, rec, (size_t)I->n_slopes * 4);
         if (counts) std::memcpy(counts, rec + I->n_slopes, (size_t)I->n_units * 4);

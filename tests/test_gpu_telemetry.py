@@ -67,8 +67,16 @@ def test_telemetry_decimation_and_overrun(rtc):
         with pytest.raises(rtc.RtcError) as ei:
             eng.telemetry_next(0, timeout_s=0.05)    # frame 40 never arrives
         assert ei.value.status == -4
+        # a state reset counts frames from 0 again (here from frame number 5)
+        eng.set_state(0, None, None, 5)
+        run_stream(eng, 0, case, n=6, first_frame=5)
+        s5, c5, _, i5 = eng.telemetry_next(0)
+        assert i5["frame"] == 5 and i5["lost"] == 0
+        assert eng.telemetry_next(0)[3]["frame"] == 9
         eng.set_state(0, None, None, 0)
         _, slopes, counts = run_batch(eng, 0, case)
+        assert np.array_equal(s5.astype(np.float64), slopes[5])
+        assert np.array_equal(c5, counts[5])
     assert np.array_equal(s.astype(np.float64), slopes[32])
     assert np.array_equal(c, counts[32])
     assert np.array_equal(s8.astype(np.float64), slopes[4])
