@@ -368,11 +368,39 @@ __device__ __forceinline__ void dot16(const vec16_t q, XS xs, int v, float &a0, 
 // last, partial batch guards each load instead.  NT: non-temporal loads, for
 // matrices larger than the Infinity Cache (a matrix that fits stays resident
 // from frame to frame with ordinary loads).
-template <int DT, int U, class XS, bool NT = false>
+//
+// REV streams the vectors from the last to the first (the partial batch
+// first), accumulating in that order.  Frames alternate the direction: the
+// vectors a wavefront read last in one frame are still in L2 when the next
+// frame starts there.
+template <int DT, int U, class XS, bool NT = false, bool REV = false>
 __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, int nr, XS xs,
                                                 int nv) {
     const RTC_GLOBAL vec16_t *__restrict__ p = (const RTC_GLOBAL vec16_t *)pg;
     float a0 = 0.0f, a1 = 0.0f;
+    if constexpr (REV) {
+        int v = nv - nv % U;
+        if (v < nv) {
+            vec16_t q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (v + u < nv)
+                    q[u] = NT ? __builtin_nontemporal_load(p + (v + u) * nr) : p[(v + u) * nr];
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u)
+                if (v + u < nv) dot16<DT>(q[u], xs, v + u, a0, a1);
+        }
+        while (v > 0) {
+            v -= U;
+            vec16_t q[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                q[u] = NT ? __builtin_nontemporal_load(p + (v + u) * nr) : p[(v + u) * nr];
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u) dot16<DT>(q[u], xs, v + u, a0, a1);
+        }
+        return a0 + a1;
+    }
     int v = 0;
     for (; v + U <= nv; v += U) {
         vec16_t q[U];
@@ -391,6 +419,38 @@ __device__ __forceinline__ float stream_segment(const uint4 *__restrict__ pg, in
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (v + u < nv) dot16<DT>(q[u], xs, v + u, a0, a1);
+    }
+    return a0 + a1;
+}
+
+// stream_segment with the direction chosen at run time (one copy of the loop):
+// pass vector j is vector j (forward) or nv - 1 - j (backward), so the
+// accumulation order equals stream_segment's or its REV form's.
+template <int DT, int U, class XS>
+__device__ __forceinline__ float stream_segment_dir(const uint4 *__restrict__ pg, int nr, XS xs,
+                                                    int nv, bool rev) {
+    const RTC_GLOBAL vec16_t *__restrict__ p = (const RTC_GLOBAL vec16_t *)pg;
+    const int s = rev ? -1 : 1;
+    const int c0 = rev ? nv - 1 : 0;
+    float a0 = 0.0f, a1 = 0.0f;
+    int j = 0;
+    for (; j + U <= nv; j += U) {
+        const int c = c0 + s * j;
+        vec16_t q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) q[u] = p[(c + s * u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dot16<DT>(q[u], xs, c + s * u, a0, a1);
+    }
+    if (j < nv) {
+        const int c = c0 + s * j;
+        vec16_t q[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j + u < nv) q[u] = p[(c + s * u) * nr];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j + u < nv) dot16<DT>(q[u], xs, c + s * u, a0, a1);
     }
     return a0 + a1;
 }

@@ -453,10 +453,11 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
 }
 
 // Epilogue of the reconstruction MVM: integrate frame f's commands (matrix
-// slot ms: its FP8 row scales).
-MvmEpilogue integrate_epi(Instance *I, int ms, float c1, float g, float *out) {
+// slot ms: its FP8 row scales).  Odd frames stream each segment backwards.
+MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t f, float c1, float g, float *out) {
     MvmEpilogue E{};
     E.mode = EPI_INTEGRATE;
+    E.rev = (int32_t)(f & 1);
     E.n_parts = (int)I->seg.size();
     E.n_kb = (int)I->kb.size();
     E.kb_segs = I->d_kb_segs;
@@ -1067,7 +1068,8 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         const int ms = mat_slot(I, I->next_frame);
         settle_matrices(I, I->next_frame);
         const MvmEpilogue E =
-            integrate_epi(I, ms, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr);
+            integrate_epi(I, ms, I->next_frame, c1, g,
+                          cmds ? cmds + (size_t)f * I->n_act : nullptr);
         if (f + 1 < n_frames) {
             NextSlopes N{};
             N.sh = I->d_sh;
@@ -1342,7 +1344,8 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
         launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_kb,
                    I->d_seg, I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
-                   I->d_ypart, integrate_epi(I, I->frame_mslot, I->frame_c1, I->frame_g, nullptr));
+                   I->d_ypart, integrate_epi(I, I->frame_mslot, frame, I->frame_c1,
+                                 I->frame_g, nullptr));
     }
     S.next_chunk++;
     bool all = true;

@@ -107,6 +107,7 @@ struct MvmEpilogue {
     int32_t mode;          // EPI_*
     int32_t n_parts;       // segment partials per row (all launches of the frame)
     int32_t n_kb;          // column blocks; kb_segs[b] = {first segment, segments}
+    int32_t rev;           // 1: each segment streamed last vector first (odd frames)
     const int2 *kb_segs;
     uint32_t *count;       // per-tile arrival counters, zero between frames
     const float *p;        // INTEGRATE: POLC term (nullable)

@@ -127,8 +127,10 @@ __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__rest
     const int t = wv - pi * n_tiles;
     const Piece P = pieces[p0 + pi];
     const int nr = min(kTileRows, n_rows - t * kTileRows);
+    // odd frames run the piece backwards, segments and vectors alike
+    const int rev = __builtin_amdgcn_readfirstlane(E.rev);
     for (int sgi = 0; sgi < P.nseg; ++sgi) {
-        const int sg = P.seg0 + sgi;
+        const int sg = P.seg0 + (rev ? P.nseg - 1 - sgi : sgi);
         const Segment S = segs[sg];
         const KBlock K = kbs[S.kb];
         if (lane < nr) {
@@ -137,7 +139,8 @@ __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__rest
                 (int64_t)S.v0 * nr + lane;
             const float4 *__restrict__ xs =
                 reinterpret_cast<const float4 *>(x + K.spad + (int64_t)S.v0 * kE);
-            const float part = stream_segment<DT, U, const float4 *, NT>(p, nr, xs, S.nv);
+            const float part = rev ? stream_segment<DT, U, const float4 *, NT, true>(p, nr, xs, S.nv)
+                                   : stream_segment<DT, U, const float4 *, NT>(p, nr, xs, S.nv);
             // agent-scope atomic store: written through to the memory side,
             // where every XCD's agent-scope loads see it
             __hip_atomic_store(y_part + (size_t)sg * n_rows + t * kTileRows + lane, part,

@@ -228,34 +228,32 @@ __device__ __forceinline__ int vec_elems(int dtype) {
 template <int DT> struct LoopBatch { static constexpr int U = 8; };
 template <> struct LoopBatch<RTC_CM_FP8> { static constexpr int U = 4; };
 
-template <int DT, bool NT>
-__device__ __forceinline__ float stream_part(const uint8_t *cm, const KBlock &K, const Segment &S,
-                                             int t, int nr, int lane, const RTC_LDS float *lds) {
+// Partial of one segment on tile t for this lane's row (0 past the tile's rows);
+// rev streams it backwards.  Ordinary loads whatever the matrix size: the
+// non-temporal variants double the loop's streaming code and push the kernel
+// into spills.
+template <int DT>
+__device__ __forceinline__ float mvm_partial(const uint8_t *cm, const KBlock &K, const Segment &S,
+                                             int t, int nr, int lane, const RTC_LDS float *lds,
+                                             bool rev) {
+    if (lane >= nr) return 0.0f;
     const uint4 *p = reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
                      (int64_t)S.v0 * nr + lane;
-    return stream_segment<DT, LoopBatch<DT>::U, const RTC_LDS lds4_t *, NT>(
-        p, nr, (const RTC_LDS lds4_t *)lds, S.nv);
+    return stream_segment_dir<DT, LoopBatch<DT>::U, const RTC_LDS lds4_t *>(
+        p, nr, (const RTC_LDS lds4_t *)lds, S.nv, rev);
 }
 
-// Partial of one segment on tile t for this lane's row (0 past the tile's rows).
-template <int DT>
-__device__ __forceinline__ float mvm_partial(InstRef I, const uint8_t *cm, const KBlock &K,
-                                             const Segment &S, int t, int nr, int lane,
-                                             const RTC_LDS float *lds) {
-    // ordinary loads whatever the matrix size: the non-temporal variants
-    // double the loop's streaming code and push the kernel into spills
-    if (lane >= nr) return 0.0f;
-    return stream_part<DT, false>(cm, K, S, t, nr, lane, lds);
-}
-
-__device__ __forceinline__ float seg_partial(InstRef I, int ms, const KBlock &K,
+// Reconstruction partial of frame q: odd frames stream the segment backwards,
+// as the per-launch kernels do.
+__device__ __forceinline__ float seg_partial(InstRef I, int ms, uint64_t q, const KBlock &K,
                                              const Segment &S, int t, int nr, int lane,
                                              const RTC_LDS float *lds) {
     const uint8_t *cm = I.cm[ms];   // read from the descriptor at use: no registers held
+    const bool rev = (q & 1) != 0;
     switch (I.dtype) {
-    case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(I, cm, K, S, t, nr, lane, lds);
-    case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(I, cm, K, S, t, nr, lane, lds);
-    default: return mvm_partial<RTC_CM_FP8>(I, cm, K, S, t, nr, lane, lds);
+    case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(cm, K, S, t, nr, lane, lds, rev);
+    case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(cm, K, S, t, nr, lane, lds, rev);
+    default: return mvm_partial<RTC_CM_FP8>(cm, K, S, t, nr, lane, lds, rev);
     }
 }
 
@@ -533,7 +531,7 @@ __device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
             !wait_geq(slot(I.p_done, t), q - kDepth + 1, A, A.dep_watchdog))
             return false;
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = mvm_partial<RTC_CM_F32>(I, I.M[ms], K, S, t, nr, lane, lds);
+        const float v = mvm_partial<RTC_CM_F32>(I.M[ms], K, S, t, nr, lane, lds, false);
         if (lane < nr) st_agent(part + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         lds_done();
         drain();
@@ -655,7 +653,7 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
             staged = sg;
         }
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = seg_partial(I, ms, K, Sg, t, nr, lane, lds);
+        const float v = seg_partial(I, ms, q, K, Sg, t, nr, lane, lds);
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
         const int jkb = I.serving ? kb : 0;
