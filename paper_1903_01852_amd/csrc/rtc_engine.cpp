@@ -452,12 +452,13 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
     }
 }
 
-// Epilogue of the reconstruction MVM: integrate frame f's commands (matrix
-// slot ms: its FP8 row scales).  Odd frames stream each segment backwards.
-MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t f, float c1, float g, float *out) {
+// Epilogue of the reconstruction MVM: integrate the commands of the frame at
+// index seq of the sequence (matrix slot ms: its FP8 row scales).  Odd indices
+// stream each segment backwards.
+MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t seq, float c1, float g, float *out) {
     MvmEpilogue E{};
     E.mode = EPI_INTEGRATE;
-    E.rev = (int32_t)(f & 1);
+    E.rev = (int32_t)(seq & 1);
     E.n_parts = (int)I->seg.size();
     E.n_kb = (int)I->kb.size();
     E.kb_segs = I->d_kb_segs;
@@ -813,6 +814,7 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     HIP_TRY(hipMemset(I->d_spad, 0, (size_t)I->spad_len * 4));
     HIP_TRY(hipMemset(I->d_spad2, 0, (size_t)I->spad_len * 4));
     I->next_frame = 0;
+    I->seq = 0;
     I->cur_frame = ~0ull;
     I->cur_started = false;
     if (e->mode == RTC_MODE_PERSISTENT) persist_reset(I);
@@ -994,6 +996,7 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     if (p && I->d.polc) HIP_TRY(hipMemcpy(I->d_p, p, I->n_act * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
     I->next_frame = next_frame;
+    I->seq = 0;
     I->cur_frame = ~0ull;
     I->cur_started = false;
     for (auto &sl : I->slots) {
@@ -1068,8 +1071,7 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         const int ms = mat_slot(I, I->next_frame);
         settle_matrices(I, I->next_frame);
         const MvmEpilogue E =
-            integrate_epi(I, ms, I->next_frame, c1, g,
-                          cmds ? cmds + (size_t)f * I->n_act : nullptr);
+            integrate_epi(I, ms, I->seq++, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr);
         if (f + 1 < n_frames) {
             NextSlopes N{};
             N.sh = I->d_sh;
@@ -1319,6 +1321,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         for (auto &W : I->wfs) W.next_chunk = 0;
         coeffs(I, frame, &I->frame_c1, &I->frame_g);
         I->frame_mslot = mat_slot(I, frame);
+        I->frame_seq = I->seq++;
         sl.frame = frame;
         sl.complete = false;
         sl.dropped = false;
@@ -1344,7 +1347,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
         launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_kb,
                    I->d_seg, I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
-                   I->d_ypart, integrate_epi(I, I->frame_mslot, frame, I->frame_c1,
+                   I->d_ypart, integrate_epi(I, I->frame_mslot, I->frame_seq, I->frame_c1,
                                  I->frame_g, nullptr));
     }
     S.next_chunk++;

@@ -178,6 +178,11 @@ struct Instance {
     bool pending = false;
     uint64_t f_switch = 0;
     uint64_t next_frame = 0;       // next frame the batch path processes
+    // Frames started since the last matrix load or state reset (the frame loop
+    // counts the same in its q): the parity of a frame's index in this
+    // sequence picks its streaming direction.
+    uint64_t seq = 0;
+    uint64_t frame_seq = 0;        // index of the frame in progress (per-launch serving)
     uint32_t drops = 0;
     // serving
     uint64_t cur_frame = ~0ull;

@@ -52,6 +52,43 @@ def test_small_sh_f32_batch(rtc):
     assert rel.max() <= TOL["f32"]
 
 
+def _serve_numbered(eng, case, numbers):
+    """Serving: bank frame f submitted as frame number numbers[f]."""
+    out = []
+    for f, no in enumerate(numbers):
+        for w, bank in enumerate(case.frames):
+            for c in range(case.inst.wfs[w].n_chunks):
+                r0, r1 = eng.chunk_rows(0, w, c)
+                eng.submit_chunk(0, w, no, c, bank[f][r0:r1])
+        cmds, _ = eng.wait_commands(0, no, timeout_s=10.0)
+        out.append(cmds.astype(np.float64))
+    return np.stack(out)
+
+
+def test_direction_follows_frame_sequence(rtc):
+    """Odd frames stream every segment backwards, frames counted from the last
+    state reset whatever their numbers.  The same three frames (ELT SCAO SH
+    74x74, FP32) from next frame number 0 and 1, and served as frames 1, 2, 5:
+    per-launch and frame-loop paths, batch and serving, agree bit for bit and
+    meet the oracle's bar."""
+    case = Case("scao_sh_74", n_frames=3)
+    ref = case.run_oracle("f32")
+    outs = []
+    for mode in ("stream", "persistent"):
+        with rtc.Engine([(case.inst, "f32")], mode=mode) as eng:
+            case.load(eng)
+            for start in (0, 1):
+                log(f"case scao_sh_74 f32 {mode}: batch of 3 from frame number {start}")
+                eng.set_state(0, None, None, start)
+                outs.append(run_batch(eng, 0, case)[0])
+            log(f"case scao_sh_74 f32 {mode}: served as frames 1, 2, 5")
+            eng.set_state(0, None, None, 1)
+            outs.append(_serve_numbered(eng, case, (1, 2, 5)))
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
+    assert rel_l2(outs[0], ref["commands"]).max() <= TOL["f32"]
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "fp8"])
 def test_scao74_batch(rtc, dtype):
     """ELT SCAO SH (74x74, 5318 x 7944) at full size."""
