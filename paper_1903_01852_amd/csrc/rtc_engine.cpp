@@ -109,6 +109,18 @@ void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces,
     }
 }
 
+// Segments with their block's fields folded in (E slope values per vector).
+std::vector<SegRun> seg_runs(const std::vector<KBlock> &kbs, const std::vector<Segment> &seg,
+                             int E) {
+    std::vector<SegRun> run;
+    run.reserve(seg.size());
+    for (const Segment &S : seg) {
+        const KBlock &K = kbs[S.kb];
+        run.push_back(SegRun{K.base, K.kv, K.spad + S.v0 * E, S.v0, S.nv, 0, 0});
+    }
+    return run;
+}
+
 // Geometry -> units, chunk readiness, column blocks, padded slope layout.
 rtc_status build_instance(rtc_engine *e, Instance *I) {
     const int E = elems_per_vec(I->d.cm_dtype);
@@ -320,6 +332,8 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_single, I->single.size()));
     TRY(dev_alloc(e, &I->d_pieces, I->pieces.size()));
     TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
+    TRY(dev_alloc(e, &I->d_run, I->seg.size()));
+    TRY(dev_alloc(e, &I->d_runm, std::max<size_t>(I->segm.size(), 1)));
     TRY(dev_alloc(e, &I->d_pieces_m, std::max<size_t>(I->pieces_m.size(), 1)));
     size_t sh_px = 0;
     for (auto &u : I->sh) sh_px += (size_t)I->params.w[u.wfs].p * I->params.w[u.wfs].p;
@@ -370,6 +384,10 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     HIP_TRY(up(I->d_pieces, I->pieces.data(), I->pieces.size() * sizeof(Piece)));
     HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));
     HIP_TRY(up(I->d_pieces_m, I->pieces_m.data(), I->pieces_m.size() * sizeof(Piece)));
+    const std::vector<SegRun> run = seg_runs(I->kb, I->seg, elems_per_vec(I->d.cm_dtype));
+    const std::vector<SegRun> runm = seg_runs(I->kbm, I->segm, elems_per_vec(RTC_CM_F32));
+    HIP_TRY(up(I->d_run, run.data(), run.size() * sizeof(SegRun)));
+    HIP_TRY(up(I->d_runm, runm.data(), runm.size() * sizeof(SegRun)));
     // default calibration: dark 0, flat 1, bg 0, threshold 0, reference 0
     std::vector<float> ones(std::max(sh_px, 4 * I->py.size()), 1.0f);
     HIP_TRY(hipMemcpy(I->d_sh_flat, ones.data(), sh_px * 4, hipMemcpyHostToDevice));
@@ -484,7 +502,7 @@ void enqueue_polc(Instance *I, hipStream_t st, int ms) {
     E.kb_segs = I->d_kbm_segs;
     E.count = I->d_count_m;
     E.y = I->d_p;
-    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_kbm, I->d_segm, I->d_pieces_m, 0,
+    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_runm, I->d_pieces_m, 0,
                (int)I->pieces_m.size(), I->n_act, I->d_a, I->d_ppart, E);
 }
 
@@ -1103,7 +1121,7 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
                 I->mvm_open = true;
                 I->mvm_run = 0;
             }
-            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
+            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
                             I->d_pieces, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E, N,
                             I->params);
             if (I->mvm_open && (++I->mvm_run == I->mvm_ev_every || f + 2 >= n_frames)) {
@@ -1112,7 +1130,7 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
                 I->mvm_open = false;
             }
         } else {
-            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_kb, I->d_seg,
+            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
                        I->d_pieces, 0, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E);
         }
         enqueue_polc(I, st, ms);
@@ -1139,7 +1157,7 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     E.y = I->d_yscratch;
     std::lock_guard<std::mutex> lk(I->mu);
     for (int i = 0; i < n_iter; ++i)
-        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->m_active], I->d_kb, I->d_seg,
+        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->m_active], I->d_run,
                    I->d_pieces, 0, (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
     return last_error(e);
 }
@@ -1345,8 +1363,8 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             fs.f[w] = I->wfs[w].d_ring + (size_t)slot * I->wfs[w].d.frame_h * I->wfs[w].d.frame_w;
         const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
-        launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_kb,
-                   I->d_seg, I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
+        launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_run,
+                   I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
                    I->d_ypart, integrate_epi(I, I->frame_mslot, I->frame_seq, I->frame_c1,
                                  I->frame_g, nullptr));
     }

@@ -141,6 +141,7 @@ struct Instance {
     PyrUnit *d_py = nullptr;
     KBlock *d_kb = nullptr, *d_kbm = nullptr;
     Segment *d_seg = nullptr, *d_segm = nullptr;
+    rtc::SegRun *d_run = nullptr, *d_runm = nullptr;   // the segments, block fields folded in
     int2 *d_kb_segs = nullptr, *d_kbm_segs = nullptr;   // per block {first segment, count}
     Piece *d_pieces = nullptr, *d_pieces_m = nullptr, *d_single = nullptr;
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;

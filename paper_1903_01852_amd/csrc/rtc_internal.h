@@ -100,6 +100,15 @@ struct Segment {
 struct Piece {
     int32_t seg0, nseg;
 };
+// A segment with its column block's fields folded in, for the per-launch MVM:
+// one record read per segment instead of a segment then its block.
+struct SegRun {
+    int64_t base;          // the block's byte offset of tile 0
+    int32_t kv;            // the block's 16-byte vectors per row
+    int32_t xoff;          // offset of the segment's first slope in the padded vector
+    int32_t v0, nv;        // the segment's vectors within the block
+    int32_t r0, r1;
+};
 
 // Work done by the last wavefront to finish a row tile of an MVM.
 enum { EPI_NONE = 0, EPI_INTEGRATE = 1, EPI_REDUCE = 2 };
@@ -308,9 +317,9 @@ void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const Frame
 // stream_nt: stream the matrix with non-temporal loads (matrices larger than
 // the Infinity Cache); otherwise ordinary loads keep a smaller matrix resident.
 constexpr int64_t kCacheResidentBytes = 192ll << 20;
-void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
-                const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
-                const float *x_pad, float *y_part, const MvmEpilogue &epi);
+void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const SegRun *runs,
+                const Piece *pieces, int p0, int n_pieces, int n_rows, const float *x_pad,
+                float *y_part, const MvmEpilogue &epi);
 // Slopes of the next frame, formed by extra workgroups of the current frame's
 // MVM launch (every SH unit, then every pyramid unit of the instance).
 struct NextSlopes {
@@ -328,8 +337,8 @@ struct NextSlopes {
 };
 // launch_mvm (reading x_pad) plus, in the same grid, the slopes of the next
 // frame into next.s_pad (a different buffer than x_pad).
-void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
-                     const Segment *segs, const Piece *pieces, int n_pieces, int n_rows,
+void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm,
+                     const SegRun *runs, const Piece *pieces, int n_pieces, int n_rows,
                      const float *x_pad, float *y_part, const MvmEpilogue &epi,
                      const NextSlopes &next, const WfsParamSet &params);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,

@@ -116,12 +116,10 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
 // One wavefront of the split-K MVM: piece wv / n_tiles of tile wv % n_tiles.
 template <int DT, int U, bool NT>
 __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__restrict__ cm,
-                                         const KBlock *__restrict__ kbs,
-                                         const Segment *__restrict__ segs,
+                                         const SegRun *__restrict__ runs,
                                          const Piece *__restrict__ pieces, int p0, int n_pieces,
                                          int n_tiles, int n_rows, const float *__restrict__ x,
                                          float *__restrict__ y_part, const MvmEpilogue &E) {
-    constexpr int kE = Elem<DT>::E;
     if (wv >= n_pieces * n_tiles) return;
     const int pi = wv / n_tiles;
     const int t = wv - pi * n_tiles;
@@ -131,14 +129,12 @@ __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__rest
     const int rev = __builtin_amdgcn_readfirstlane(E.rev);
     for (int sgi = 0; sgi < P.nseg; ++sgi) {
         const int sg = P.seg0 + (rev ? P.nseg - 1 - sgi : sgi);
-        const Segment S = segs[sg];
-        const KBlock K = kbs[S.kb];
+        const SegRun S = runs[sg];
         if (lane < nr) {
             const uint4 *__restrict__ p =
-                reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
+                reinterpret_cast<const uint4 *>(cm + S.base + (int64_t)t * kTileRows * S.kv * 16) +
                 (int64_t)S.v0 * nr + lane;
-            const float4 *__restrict__ xs =
-                reinterpret_cast<const float4 *>(x + K.spad + (int64_t)S.v0 * kE);
+            const float4 *__restrict__ xs = reinterpret_cast<const float4 *>(x + S.xoff);
             const float part = rev ? stream_segment<DT, U, const float4 *, NT, true>(p, nr, xs, S.nv)
                                    : stream_segment<DT, U, const float4 *, NT>(p, nr, xs, S.nv);
             // agent-scope atomic store: written through to the memory side,
@@ -168,24 +164,21 @@ __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__rest
 
 template <int DT, int U, bool NT>
 __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
-                                             const KBlock *__restrict__ kbs,
-                                             const Segment *__restrict__ segs,
+                                             const SegRun *__restrict__ runs,
                                              const Piece *__restrict__ pieces, int p0,
                                              int n_pieces, int n_tiles, int n_rows,
                                              const float *__restrict__ x,
                                              float *__restrict__ y_part, MvmEpilogue E) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    mvm_wave<DT, U, NT>(wv, lane, cm, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x, y_part,
-                        E);
+    mvm_wave<DT, U, NT>(wv, lane, cm, runs, pieces, p0, n_pieces, n_tiles, n_rows, x, y_part, E);
 }
 
 // The MVM's workgroups come first, so they are dispatched first and stream
 // from the start; the slope workgroups fill the remaining wavefront slots.
 template <int DT, int U, bool NT>
 __global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm,
-                                                  const KBlock *__restrict__ kbs,
-                                                  const Segment *__restrict__ segs,
+                                                  const SegRun *__restrict__ runs,
                                                   const Piece *__restrict__ pieces, int n_pieces,
                                                   int n_tiles, int n_rows,
                                                   const float *__restrict__ x,
@@ -196,8 +189,8 @@ __global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x);
     if (blk < mvm_blocks) {
-        mvm_wave<DT, U, NT>(blk * 4 + wave, lane, cm, kbs, segs, pieces, 0, n_pieces, n_tiles,
-                            n_rows, x, y_part, E);
+        mvm_wave<DT, U, NT>(blk * 4 + wave, lane, cm, runs, pieces, 0, n_pieces, n_tiles, n_rows,
+                            x, y_part, E);
         return;
     }
     const SlopeOut o{N.s_pad, N.s_out, N.counts, N.masks};
@@ -302,79 +295,79 @@ void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const Frame
 // values (8 or 16 per vector, read through the scalar unit) would not fit the
 // scalar registers at 16 (measured: FP8 on a 302 MB matrix 87 -> 78 us cold).
 template <bool NT>
-void launch_mvm_t(hipStream_t st, int dtype, const uint8_t *c, const KBlock *kbs,
-                  const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_tiles,
-                  int n_rows, const float *x_pad, float *y_part, const MvmEpilogue &epi) {
+void launch_mvm_t(hipStream_t st, int dtype, const uint8_t *c, const SegRun *runs,
+                  const Piece *pieces, int p0, int n_pieces, int n_tiles, int n_rows,
+                  const float *x_pad, float *y_part, const MvmEpilogue &epi) {
     const dim3 grid((n_pieces * n_tiles + 3) / 4), block(256);
     switch (dtype) {
     case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, kbs, segs, pieces,
-                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, runs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, kbs, segs, pieces,
-                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, runs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     default:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, kbs, segs, pieces,
-                           p0, n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, runs, pieces, p0,
+                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
         break;
     }
 }
 
-void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
-                const Segment *segs, const Piece *pieces, int p0, int n_pieces, int n_rows,
-                const float *x_pad, float *y_part, const MvmEpilogue &epi) {
+void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const SegRun *runs,
+                const Piece *pieces, int p0, int n_pieces, int n_rows, const float *x_pad,
+                float *y_part, const MvmEpilogue &epi) {
     if (n_pieces <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
     const uint8_t *c = static_cast<const uint8_t *>(cm);
     if (stream_nt)
-        launch_mvm_t<true>(st, dtype, c, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
-                           y_part, epi);
+        launch_mvm_t<true>(st, dtype, c, runs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad, y_part,
+                           epi);
     else
-        launch_mvm_t<false>(st, dtype, c, kbs, segs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
+        launch_mvm_t<false>(st, dtype, c, runs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
                             y_part, epi);
 }
 
 template <bool NT>
-void launch_mvm_next_t(hipStream_t st, int dtype, const uint8_t *c, const KBlock *kbs,
-                       const Segment *segs, const Piece *pieces, int n_pieces, int n_tiles,
+void launch_mvm_next_t(hipStream_t st, int dtype, const uint8_t *c, const SegRun *runs,
+                       const Piece *pieces, int n_pieces, int n_tiles,
                        int n_rows, const float *x_pad, float *y_part, const MvmEpilogue &epi,
                        const NextSlopes &next, const WfsParamSet &params) {
     const int mvm_blocks = (n_pieces * n_tiles + 3) / 4;
     const dim3 grid(mvm_blocks + (next.n_sh + 3) / 4 + (next.n_pyr + 255) / 256), block(256);
     switch (dtype) {
     case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, kbs, segs,
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, runs,
                            pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
                            next, params);
         break;
     case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, kbs, segs,
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, runs,
                            pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
                            next, params);
         break;
     default:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, kbs, segs,
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, runs,
                            pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
                            next, params);
         break;
     }
 }
 
-void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm, const KBlock *kbs,
-                     const Segment *segs, const Piece *pieces, int n_pieces, int n_rows,
+void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm,
+                     const SegRun *runs, const Piece *pieces, int n_pieces, int n_rows,
                      const float *x_pad, float *y_part, const MvmEpilogue &epi,
                      const NextSlopes &next, const WfsParamSet &params) {
     if (n_pieces <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
     const uint8_t *c = static_cast<const uint8_t *>(cm);
     if (stream_nt)
-        launch_mvm_next_t<true>(st, dtype, c, kbs, segs, pieces, n_pieces, n_tiles, n_rows, x_pad,
+        launch_mvm_next_t<true>(st, dtype, c, runs, pieces, n_pieces, n_tiles, n_rows, x_pad,
                                 y_part, epi, next, params);
     else
-        launch_mvm_next_t<false>(st, dtype, c, kbs, segs, pieces, n_pieces, n_tiles, n_rows,
-                                 x_pad, y_part, epi, next, params);
+        launch_mvm_next_t<false>(st, dtype, c, runs, pieces, n_pieces, n_tiles, n_rows, x_pad,
+                                 y_part, epi, next, params);
 }
 
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
