@@ -27,6 +27,13 @@
  *    error is sticky: once RTC_E_DEVICE is returned, every later call on the
  *    engine returns it, except rtc_destroy.
  *  - Arrays are row-major and densely packed.
+ *  - Results are deterministic: the same frames from the same state give the
+ *    same commands bit for bit on every path (batch or serving, per-launch or
+ *    persistent engine).  The FP32 accumulation order of the matrix product
+ *    alternates with the parity of a frame's index among the frames started
+ *    since the last rtc_load_matrices or rtc_set_state (not its frame number),
+ *    so one frame processed at an even and at an odd index differs by FP32
+ *    rounding only.
  */
 #ifndef RTC_H
 #define RTC_H
