@@ -81,8 +81,10 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
 
 // Cut the concatenated vector range of the blocks into pieces of about
 // `target` vectors, but at least `min_pieces` of them; a piece's
-// intersections with blocks are its segments.
-void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces,
+// intersections with blocks are its segments, each cut into nearly equal
+// parts of at most max_seg vectors (the frame loop stages a segment's slopes
+// in LDS).
+void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces, int max_seg,
                     std::vector<Segment> &seg, std::vector<Piece> &pieces) {
     int64_t V = 0;
     std::vector<int64_t> start(kbs.size() + 1, 0);
@@ -101,11 +103,30 @@ void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces,
         while (lo < hi) {
             while (start[b + 1] <= lo) ++b;
             const int64_t end = std::min(hi, start[b + 1]);
-            seg.push_back(Segment{(int32_t)b, (int32_t)(lo - start[b]), (int32_t)(end - lo), 0});
+            const int64_t n = (end - lo + max_seg - 1) / max_seg;
+            for (int64_t i = 0; i < n; ++i) {
+                const int64_t a = lo + (end - lo) * i / n, z = lo + (end - lo) * (i + 1) / n;
+                seg.push_back(Segment{(int32_t)b, (int32_t)(a - start[b]), (int32_t)(z - a), 0});
+            }
             lo = end;
         }
         pc.nseg = (int32_t)seg.size() - pc.seg0;
         pieces.push_back(pc);
+    }
+}
+
+// Shape of the per-launch reconstruction MVM by storage type: pieces of about
+// `target` vectors per wavefront, at least `min_waves` wavefronts (SCAO 74x74,
+// same-box sweep: a launch streams fastest with fewer, longer wavefronts than
+// the POLC product's 128 / 1536, FP32 29.4 us against 32.1 us).
+struct PieceShape {
+    int target, min_waves;
+};
+PieceShape piece_shape(int dtype) {
+    switch (dtype) {
+    case RTC_CM_F32: return {256, 768};
+    case RTC_CM_BF16: return {128, 768};
+    default: return {128, 1152};
     }
 }
 
@@ -274,8 +295,9 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                       (int64_t)last_nr * L.kv * 16;
     }
     I->spad_len = spad;
-    const int min_pieces = (kMinMvmWaves + n_tiles - 1) / n_tiles;
-    build_segments(I->kb, kPieceVectors, min_pieces, I->seg, I->pieces);
+    const PieceShape ps = piece_shape(I->d.cm_dtype);
+    build_segments(I->kb, ps.target, (ps.min_waves + n_tiles - 1) / n_tiles, kMaxSegVectors,
+                   I->seg, I->pieces);
     I->kb_seg0.assign(I->kb.size(), 0);
     I->kb_nseg.assign(I->kb.size(), 0);
     for (size_t i = 0; i < I->seg.size(); ++i) {
@@ -304,7 +326,8 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->m_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
                      (int64_t)last_nr * L.kv * 16;
         I->a_len = nb * kPolcBlock;
-        build_segments(I->kbm, kPieceVectors, (kMinMvmWaves + n_tiles - 1) / n_tiles, I->segm,
+        build_segments(I->kbm, kPieceVectors, (kMinMvmWaves + n_tiles - 1) / n_tiles,
+                       kMaxSegVectors, I->segm,
                        I->pieces_m);
         std::vector<int> s0(I->kbm.size(), 0), ns(I->kbm.size(), 0);
         for (size_t i = 0; i < I->segm.size(); ++i) {
