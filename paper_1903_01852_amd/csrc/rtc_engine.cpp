@@ -126,7 +126,7 @@ PieceShape piece_shape(int dtype) {
     switch (dtype) {
     case RTC_CM_F32: return {256, 768};
     case RTC_CM_BF16: return {128, 768};
-    default: return {128, 1152};
+    default: return {128, 1344};
     }
 }
 
