@@ -256,8 +256,20 @@ def mvm(R: np.ndarray, s: np.ndarray) -> np.ndarray:
 
 
 def polc_matrix(R: np.ndarray, D: np.ndarray) -> np.ndarray:
-    """Implicit pseudo-open-loop operator M = R D, float64, computed once."""
-    return np.asarray(R, np.float64) @ np.asarray(D, np.float64)
+    """Implicit pseudo-open-loop operator M = R D, float64, computed once.
+
+    Section 3.4: the pseudo-open-loop slopes add the slopes D a that the
+    applied commands a produce (D: n_slopes x n_act, commands -> slopes) to
+    the measured ones, and reconstructing them with R (n_act x n_slopes) adds
+    R (D a) = M a to the reconstruction; M (n_act x n_act) is that composition,
+    M[i, j] = sum_k R[i, k] D[k, j].
+    """
+    R = np.asarray(R, np.float64)
+    D = np.asarray(D, np.float64)
+    if R.ndim != 2 or D.ndim != 2 or R.shape[1] != D.shape[0] or R.shape[0] != D.shape[1]:
+        raise ValueError(f"POLC needs R (n_act x n_s) and D (n_s x n_act), got {R.shape}, "
+                         f"{D.shape}")
+    return R @ D
 
 
 def integrate(a_prev: np.ndarray, y: np.ndarray, gain: float, leak: float,
@@ -301,6 +313,8 @@ def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
     Returns a dict with commands (n_frames, n_act), slopes, counts and,
     optionally, masks.
     """
+    if inst.polc and M is None:
+        raise ValueError("the instance has implicit POLC on: give its matrix M (n_act x n_act)")
     if dequantized:
         codes, scale = quantize(R, cm_dtype)
         Rm = dequantize(codes, scale, cm_dtype)
@@ -322,7 +336,7 @@ def run(inst, frames, cals, R, n_frames: int, cm_dtype: str = "f32",
         y = Rm @ s
         g, lam = params_at(inst, f)
         p = None
-        if inst.polc and M is not None:
+        if inst.polc:
             p = np.asarray(p0, np.float64) if (f == f0 and p0 is not None) else M @ a
         a = integrate(a, y, g, lam, p)
         cmds[f - f0] = a

@@ -477,3 +477,53 @@ def test_polc_term_given_for_first_frame():
     for m in (1, 2, 30):
         expect = (1 - lam) ** (m - 1) * g * d
         assert np.abs((c - a)[m - 1] - expect).max() <= 1e-12 * np.abs(d).max()
+
+
+def test_polc_matrix_brute_force_elements():
+    """M = R D element by element from Python loops over small integer
+    matrices (exact in float64): M[i, j] = sum_k R[i, k] D[k, j], with R
+    n_act x n_s and D n_s x n_act.  The result is far from symmetric, so a
+    transposed product, swapped operands or a dropped term fails."""
+    rng = np.random.default_rng(31)
+    n_act, n_s = 5, 7
+    R = rng.integers(-9, 10, size=(n_act, n_s)).astype(np.float32)
+    D = rng.integers(-9, 10, size=(n_s, n_act)).astype(np.float64)
+    M = oracle.polc_matrix(R, D)
+    assert M.shape == (n_act, n_act)
+    for i in range(n_act):
+        for j in range(n_act):
+            expect = 0
+            for k in range(n_s):
+                expect += int(R[i, k]) * int(D[k, j])
+            assert M[i, j] == expect
+    assert not np.array_equal(M, M.T)
+
+
+def test_polc_matrix_is_reconstruction_of_pseudo_open_loop_slopes():
+    """Section 3.4: the POLC term is the reconstruction of the slopes that the
+    applied commands produce: M a = R (D a) for any command vector a (two
+    matrix-vector products, associativity), and a D that maps commands onto
+    slopes the reconstructor inverts (R D = I on the commands) gives M = I."""
+    rng = np.random.default_rng(32)
+    n_act, n_s = 9, 20
+    R = rng.standard_normal((n_act, n_s)).astype(np.float32)
+    D = rng.standard_normal((n_s, n_act))
+    M = oracle.polc_matrix(R, D)
+    for _ in range(3):
+        a = rng.standard_normal(n_act)
+        lhs = M @ a
+        rhs = oracle.mvm(R, oracle.mvm(D, a))
+        assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+    # D = right inverse of R: the pseudo-open-loop slopes of commands a
+    # reconstruct to a itself
+    Rd = R.astype(np.float64)
+    D_inv = Rd.T @ np.linalg.inv(Rd @ Rd.T)
+    assert np.abs(oracle.polc_matrix(R, D_inv) - np.eye(n_act)).max() <= 1e-12
+    with pytest.raises(ValueError):
+        oracle.polc_matrix(R, D.T)
+
+
+def test_run_refuses_polc_without_its_matrix():
+    inst, frames, cal, R = _tiny_instance(polc=True)
+    with pytest.raises(ValueError):
+        oracle.run(inst, [frames], [cal], R, 2)
