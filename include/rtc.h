@@ -140,9 +140,18 @@ typedef struct {
     int64_t polc_bytes;           /* bytes of the stored POLC matrix (0 if off) */
 } rtc_instance_info;
 
-/* Engine lifetime. rtc_create copies the descriptors; subap/pupil maps are
- * read during the call only.  Allocates every device and pinned host buffer
- * the frame loop uses; nothing is allocated afterwards while frames run. */
+/* Engine lifetime.  rtc_create sets up one or more controller instances on
+ * one GPU, each with its own sensors, command vector and control matrix: the
+ * paper's SCAO, MCAO (6 LGS + 3 NGS, 3 DMs) and LTAO (6 LGS + 1 NGS, 1 DM)
+ * systems (section 3, table comparing SCAO, MCAO and LTAO), where the partial
+ * commands of every sensor of an instance are summed into one command vector
+ * (section 3, the master node).  Copies the descriptors; subap/pupil maps
+ * are read during the call only.  Allocates every device and pinned host
+ * buffer the frame loop uses; nothing is allocated afterwards while frames
+ * run.  RTC_E_INVAL on a malformed descriptor (sizes, a sensor outside its
+ * frame, a sensor without valid units), RTC_E_DEVICE when the device is
+ * missing, RTC_E_NOMEM when an allocation fails; *out is NULL on error.
+ * rtc_destroy stops the loop and frees everything (NULL: RTC_E_INVAL). */
 rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out);
 rtc_status rtc_destroy(rtc_engine *e);
 const char *rtc_strerror(rtc_status s);
@@ -152,11 +161,16 @@ rtc_status rtc_chunk_rows(rtc_engine *e, int32_t inst, int32_t wfs, int32_t chun
                           int32_t *row_begin, int32_t *row_end);
 
 /* Control matrix R (host, n_act x n_slopes, FP32, slopes ordered sensor by
- * sensor, units in raster order, (x, y) interleaved).  The library encodes R
+ * sensor, units in raster order, (x, y) interleaved): reconstruction is one
+ * dense matrix-vector product per frame (section 2.3, the 5318 x 9232 MVM;
+ * section 3.4 for the POLC matrix M, applied to the summed command).  The library encodes R
  * in the instance's storage type and re-tiles it on the device.  With POLC
  * on, give either D (host, n_slopes x n_act, FP64), and M = R.D is formed
  * once in FP64 on the device from the FP32 R, or M itself (host, n_act x
- * n_act, FP32).  M is stored in FP32.  Resets the command state. */
+ * n_act, FP32).  M is stored in FP32.  Resets the command state.  Blocks
+ * until the matrices are resident (stops a running serving loop first).
+ * RTC_E_INVAL without R, or with POLC on and neither D nor M; non-finite
+ * values in R give RTC_E_INVAL for FP8 storage (its row scales). */
 rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R,
                              const double *D, const float *M);
 
@@ -188,7 +202,10 @@ rtc_status rtc_stage_matrices(rtc_engine *e, int32_t inst, const float *R,
                               const double *D, const float *M);
 rtc_status rtc_swap_matrices(rtc_engine *e, int32_t inst, uint64_t *f_eff_out);
 
-/* Detector calibration of one sensor (host FP32 arrays, each nullable):
+/* Detector calibration of one sensor, the first per-sensor stage of the
+ * pipeline (section 2.3 names pixel calibration among the stages timed; the
+ * order dark -> flat -> background -> threshold is this library's reading).
+ * Host FP32 arrays, each nullable:
  * dark, flat, bg: frame_h x frame_w (defaults 0, 1, 0); thr: one value per
  * subaperture (SH) or one value (pyramid) (default 0); ref: reference slopes,
  * 2 per unit (default 0). */
@@ -202,14 +219,24 @@ rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs,
 rtc_status rtc_set_params(rtc_engine *e, int32_t inst, float gain, float leak,
                           uint64_t *f_eff_out);
 
-/* Command state: a (n_act) and the POLC term p for the next frame (n_act),
- * host FP32.  rtc_set_state with NULL pointers zeroes them. */
+/* Command state of the integrator: a (n_act), the commands of the last
+ * frame, and the POLC term p = M a for the next frame (n_act; section 3.4:
+ * formed for the next frame once the command is ready), host FP32, and the
+ * number of the next frame.  rtc_set_state with NULL pointers zeroes them and
+ * restarts the frame sequence (the accumulation direction restarts at even).
+ * Both stop a running serving loop between frames (RTC_E_STATE while a frame
+ * is half delivered) and synchronise the device. */
 rtc_status rtc_get_state(rtc_engine *e, int32_t inst, float *a, float *p, uint64_t *next_frame);
 rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const float *p,
                          uint64_t next_frame);
 
-/* Serving path.  Submit chunk `chunk` of frame `frame` of sensor `wfs`
- * (host rows: the chunk's rows, frame_w uint16 each).  Chunks of one frame
+/* Serving path.  Pixels arrive from each camera as a stream of row chunks
+ * tagged with a frame number (section 2.1, the UDP camera stream; section 3:
+ * the frame number stamped by the camera matches commands to frames), and
+ * slopes are formed as soon as the rows they need have arrived (section 2.2,
+ * pipelining of SH and pyramid sensors).  Submit chunk `chunk` of frame
+ * `frame` of sensor `wfs` (host rows: the chunk's rows, frame_w uint16 each;
+ * copied during the call).  Chunks of one frame
  * and sensor must come in increasing order (else RTC_E_INVAL).  A frame
  * number below the frame in progress gives RTC_E_FRAME_DROPPED; starting a
  * newer frame before the current one completed drops the current one.  The
@@ -234,7 +261,12 @@ rtc_status rtc_acquire_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t 
 rtc_status rtc_commit_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint64_t frame,
                             int32_t chunk);
 /* Wait up to timeout_ns for the commands of `frame` and copy them to cmds
- * (host, n_act FP32).  info (nullable) receives the frame's timestamps. */
+ * (host, n_act FP32).  info (nullable) receives the frame's timestamps: the
+ * paper's latency runs from the arrival of the last pixel to the DM command
+ * being ready (section 3, lab test setup; section 3.1).  RTC_E_TIMEOUT when
+ * the commands are not out in time, RTC_E_FRAME_DROPPED when the frame was
+ * superseded, never started, or its mailbox slot was reused by a later frame
+ * while it was copied (a slow reader on a separate thread). */
 rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float *cmds,
                              int64_t timeout_ns, rtc_frame_info *info);
 

@@ -547,10 +547,9 @@ rtc_status last_error(rtc_engine *e) {
 }
 
 // Encode R (n_act x n_s, FP32, row-major) into the tiled storage layout.
-void encode_matrix(const Instance *I, const float *R, int dt, const float *inv_scale_unused,
-                   const std::vector<float> &scale, std::vector<uint8_t> &out,
-                   const std::vector<KBlock> &blocks, int n_cols, int64_t bytes) {
-    (void)inv_scale_unused;
+void encode_matrix(const Instance *I, const float *R, int dt, const std::vector<float> &scale,
+                   std::vector<uint8_t> &out, const std::vector<KBlock> &blocks, int n_cols,
+                   int64_t bytes) {
     out.assign((size_t)bytes, 0);
     const int es = elem_size(dt), E = 16 / es;
     const int n_rows = I->n_act;
@@ -647,7 +646,7 @@ rtc_status put_matrices(rtc_engine *e, Instance *I, int slot, const float *R, co
         }
     }
     std::vector<uint8_t> enc;
-    encode_matrix(I, R, dt, nullptr, scale, enc, I->kb, ns, I->cm_bytes);
+    encode_matrix(I, R, dt, scale, enc, I->kb, ns, I->cm_bytes);
     TRY(upload(e, I->d_cm_s[slot], enc.data(), enc.size()));
     TRY(upload(e, I->d_scale_s[slot], scale.data(), (size_t)na * 4));
     enc.clear();
@@ -657,12 +656,19 @@ rtc_status put_matrices(rtc_engine *e, Instance *I, int slot, const float *R, co
         if (M) {
             std::memcpy(Mf.data(), M, Mf.size() * 4);
         } else {
-            // M = R.D in FP64 on the device, rounded once to FP32
-            float *dR = nullptr;
-            double *dD = nullptr, *dM = nullptr;
-            HIP_TRY(hipMalloc(&dR, (size_t)na * ns * 4));
-            HIP_TRY(hipMalloc(&dD, (size_t)ns * na * 8));
-            HIP_TRY(hipMalloc(&dM, (size_t)na * na * 8));
+            // M = R.D in FP64 on the device, rounded once to FP32; the
+            // temporaries are freed on every return path
+            struct DevTmp {
+                void *p = nullptr;
+                ~DevTmp() {
+                    if (p) (void)hipFree(p);
+                }
+            } tR, tD, tM;
+            HIP_TRY(hipMalloc(&tR.p, (size_t)na * ns * 4));
+            HIP_TRY(hipMalloc(&tD.p, (size_t)ns * na * 8));
+            HIP_TRY(hipMalloc(&tM.p, (size_t)na * na * 8));
+            float *dR = static_cast<float *>(tR.p);
+            double *dD = static_cast<double *>(tD.p), *dM = static_cast<double *>(tM.p);
             HIP_TRY(hipMemcpy(dR, R, (size_t)na * ns * 4, hipMemcpyHostToDevice));
             HIP_TRY(hipMemcpy(dD, D, (size_t)ns * na * 8, hipMemcpyHostToDevice));
             launch_dgemm_rd(e->stream, dR, dD, dM, na, ns);
@@ -670,13 +676,10 @@ rtc_status put_matrices(rtc_engine *e, Instance *I, int slot, const float *R, co
             HIP_TRY(hipStreamSynchronize(e->stream));
             std::vector<double> Md((size_t)na * na);
             HIP_TRY(hipMemcpy(Md.data(), dM, Md.size() * 8, hipMemcpyDeviceToHost));
-            (void)hipFree(dR);
-            (void)hipFree(dD);
-            (void)hipFree(dM);
             for (size_t i = 0; i < Md.size(); ++i) Mf[i] = (float)Md[i];
         }
         std::vector<float> one(na, 1.0f);
-        encode_matrix(I, Mf.data(), RTC_CM_F32, nullptr, one, enc, I->kbm, na, I->m_bytes);
+        encode_matrix(I, Mf.data(), RTC_CM_F32, one, enc, I->kbm, na, I->m_bytes);
         TRY(upload(e, I->d_M_s[slot], enc.data(), enc.size()));
     }
     return RTC_OK;

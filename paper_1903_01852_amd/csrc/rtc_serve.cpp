@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "rtc_engine.h"
+#include "rtc_seq.h"
 
 using namespace rtc;
 
@@ -802,7 +803,17 @@ rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
         if (P.slot_dropped[slot]) return RTC_E_FRAME_DROPPED;
     }
     std::memcpy(cmds, I->h_mail + slot * (size_t)I->n_act, (size_t)I->n_act * 4);
-    if (load_acquire(P.cmd_seq) >= q + 1 + depth) return RTC_E_FRAME_DROPPED;   // overwritten
+    // The loop rewrites this mailbox slot for frame q + depth, which a
+    // producer thread may start once frame q is published.  As in a seqlock,
+    // the copy is whole only if that frame had not been started when the copy
+    // ended (the loop writes a frame's commands after its chunks arrive, which
+    // is after the host started it).
+    std::atomic_thread_fence(std::memory_order_acquire);
+    {
+        std::lock_guard<std::mutex> lk(I->mu);
+        if (!mailbox_copy_whole(P.seq, q, depth) || P.slot_frame[slot] != frame)
+            return RTC_E_FRAME_DROPPED;
+    }
     if (info) {
         std::memset(info, 0, sizeof(*info));
         info->frame = frame;

@@ -75,3 +75,71 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[cname]) == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_mailbox_copy_check_rejects_torn_copies(tmp_path):
+    """The waiter's check after copying a mailbox slot (a seqlock on the
+    host's count of started frames): a writer thread that starts frame n,
+    rewrites slot n % depth value by value and then publishes it races a
+    reader that copies the slot of an already-published frame; every copy the
+    check accepts must be whole (all values from that frame), and copies are
+    accepted often."""
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    src = tmp_path / "seq.cpp"
+    src.write_text(r'''
+#include <atomic>
+#include <cstdio>
+#include <mutex>
+#include <thread>
+#include <vector>
+#include "rtc_seq.h"
+int main() {
+    const uint64_t depth = 3, n_act = 512, n_frames = 60000;
+    std::vector<std::atomic<uint64_t>> mail(depth * n_act);
+    for (auto &m : mail) m.store(~0ull);
+    std::mutex mu;
+    uint64_t seq = 0;                       // frames started (under mu)
+    std::atomic<uint64_t> pub{0};           // frames published
+    std::thread writer([&] {
+        for (uint64_t n = 0; n < n_frames; ++n) {
+            while (n - pub.load(std::memory_order_acquire) >= depth) {}
+            { std::lock_guard<std::mutex> lk(mu); seq = n + 1; }
+            for (uint64_t i = 0; i < n_act; ++i)
+                mail[(n % depth) * n_act + i].store(n, std::memory_order_relaxed);
+            pub.store(n + 1, std::memory_order_release);
+        }
+    });
+    uint64_t accepted = 0, rejected = 0, torn = 0;
+    std::vector<uint64_t> copy(n_act);
+    for (;;) {
+        const uint64_t p = pub.load(std::memory_order_acquire);
+        if (p >= n_frames) break;
+        if (p == 0) continue;
+        const uint64_t q = p - 1;
+        for (uint64_t i = 0; i < n_act; ++i)
+            copy[i] = mail[(q % depth) * n_act + i].load(std::memory_order_relaxed);
+        std::atomic_thread_fence(std::memory_order_acquire);
+        uint64_t s;
+        { std::lock_guard<std::mutex> lk(mu); s = seq; }
+        if (!rtc::mailbox_copy_whole(s, q, depth)) { ++rejected; continue; }
+        ++accepted;
+        for (uint64_t i = 0; i < n_act; ++i) torn += copy[i] != q;
+    }
+    writer.join();
+    std::printf("%llu %llu %llu\n", (unsigned long long)accepted, (unsigned long long)rejected,
+                (unsigned long long)torn);
+    return 0;
+}
+''')
+    exe = tmp_path / "seq"
+    csrc = os.path.join(ROOT, "paper_1903_01852_amd", "csrc")
+    subprocess.run([cxx, "-O2", "-std=c++17", f"-I{csrc}", str(src), "-o", str(exe), "-lpthread"],
+                   check=True)
+    accepted, rejected, torn = map(int, subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True, timeout=120).stdout.split())
+    assert torn == 0
+    assert accepted > 100
