@@ -510,4 +510,67 @@ __device__ __forceinline__ float sum_in_blocks(const float *vals, int n, int n_k
     return y;
 }
 
+// Block ends of a segment list as a bitmask: bit j of word j / 32 is set when
+// segment j is the last of its column block.  A wavefront holds the mask in
+// registers, lane l holding words l, l + 64, ... (kEndWordsPerLane of them:
+// up to kMaxSegments segments, checked when an instance is built), so that a
+// reduction tests block ends without a dependent memory access per block.
+struct SegEnds {
+    uint32_t w[kEndWordsPerLane];
+};
+__device__ __forceinline__ SegEnds load_seg_ends(const uint32_t *ends, int n, int lane) {
+    SegEnds m;
+    const int nw = (n + 31) >> 5;
+#pragma unroll
+    for (int k = 0; k < kEndWordsPerLane; ++k) {
+        const int i = k * kWave + lane;
+        m.w[k] = i < nw ? gbl(ends)[i] : 0u;
+    }
+    return m;
+}
+// Mask word wi (uniform): segments 32 wi .. 32 wi + 31.
+__device__ __forceinline__ uint32_t seg_end_word(const SegEnds &m, int wi) {
+    const int k = wi >> 6;
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kEndWordsPerLane; ++i)
+        if (i == k) v = (uint32_t)__builtin_amdgcn_readlane((int)m.w[i], wi & 63);
+    return v;
+}
+
+// Sum of one row over a tile's column blocks, in block order, each block's
+// segment partials in order: y = ((B_0 + B_1) + B_2) + ..., B_k = ((0 + p_a)
+// + p_b) + ... for part[j * n_rows + r], j in [0, n), block ends from the mask.
+// BATCH (a multiple of 32) loads in flight.
+template <int BATCH>
+__device__ __forceinline__ float sum_partials(const float *part, int n, int n_rows, int r,
+                                              const SegEnds &ends) {
+    static_assert(BATCH % 32 == 0, "batches cover whole mask words");
+    float y = 0.0f, blk = 0.0f;
+    bool first = true;
+    for (int s0 = 0; s0 < n; s0 += BATCH) {
+        float v[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u)
+            v[u] = s0 + u < n ? load_agent(part + (size_t)(s0 + u) * n_rows + r) : 0.0f;
+#pragma unroll
+        for (int h = 0; h < BATCH / 32; ++h) {
+            const uint32_t w = seg_end_word(ends, (s0 >> 5) + h);
+#pragma unroll
+            for (int u = 0; u < 32; ++u) {
+                const int j = s0 + 32 * h + u;
+                if (j < n) {
+                    blk += v[32 * h + u];
+                    if ((w >> u) & 1u) {
+                        y = first ? blk : y + blk;
+                        first = false;
+                        blk = 0.0f;
+                    }
+                }
+            }
+        }
+    }
+    return y;
+}
+
 }  // namespace rtc

@@ -79,55 +79,32 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
     return RTC_OK;
 }
 
-// Cut the concatenated vector range of the blocks into pieces of about
-// `target` vectors, but at least `min_pieces` of them; a piece's
-// intersections with blocks are its segments, each cut into nearly equal
-// parts of at most max_seg vectors (the frame loop stages a segment's slopes
-// in LDS).
-void build_segments(const std::vector<KBlock> &kbs, int target, int min_pieces, int max_seg,
-                    std::vector<Segment> &seg, std::vector<Piece> &pieces) {
-    int64_t V = 0;
-    std::vector<int64_t> start(kbs.size() + 1, 0);
+// Segments of a matrix: each column block cut into nearly equal parts of at
+// most max_seg vectors, in block order.  A segment is one wavefront's work on
+// one 64-row tile (per-launch MVM and frame loop alike) and owns one partial.
+void build_segments(const std::vector<KBlock> &kbs, int max_seg, std::vector<Segment> &seg) {
     for (size_t b = 0; b < kbs.size(); ++b) {
-        start[b] = V;
-        V += kbs[b].kv;
-    }
-    start[kbs.size()] = V;
-    const int64_t P = std::min<int64_t>(V, std::max<int64_t>(min_pieces, (V + target - 1) / target));
-    size_t b = 0;
-    for (int64_t p = 0; p < P; ++p) {
-        int64_t lo = p * V / P;
-        const int64_t hi = (p + 1) * V / P;
-        if (lo == hi) continue;
-        Piece pc{(int32_t)seg.size(), 0};
-        while (lo < hi) {
-            while (start[b + 1] <= lo) ++b;
-            const int64_t end = std::min(hi, start[b + 1]);
-            const int64_t n = (end - lo + max_seg - 1) / max_seg;
-            for (int64_t i = 0; i < n; ++i) {
-                const int64_t a = lo + (end - lo) * i / n, z = lo + (end - lo) * (i + 1) / n;
-                seg.push_back(Segment{(int32_t)b, (int32_t)(a - start[b]), (int32_t)(z - a), 0});
-            }
-            lo = end;
+        const int kv = kbs[b].kv;
+        const int n = (kv + max_seg - 1) / max_seg;
+        for (int i = 0; i < n; ++i) {
+            const int a = (int)((int64_t)kv * i / n), z = (int)((int64_t)kv * (i + 1) / n);
+            seg.push_back(Segment{(int32_t)b, a, z - a, 0});
         }
-        pc.nseg = (int32_t)seg.size() - pc.seg0;
-        pieces.push_back(pc);
     }
 }
 
-// Shape of the per-launch reconstruction MVM by storage type: pieces of about
-// `target` vectors per wavefront, at least `min_waves` wavefronts (SCAO 74x74,
-// same-box sweep: a launch streams fastest with fewer, longer wavefronts than
-// the POLC product's 128 / 1536, FP32 29.4 us against 32.1 us).
-struct PieceShape {
-    int target, min_waves;
-};
-PieceShape piece_shape(int dtype) {
-    switch (dtype) {
-    case RTC_CM_F32: return {256, 768};
-    case RTC_CM_BF16: return {128, 768};
-    default: return {128, 1344};
-    }
+// Bit j set when segment j is the last of its column block.
+std::vector<uint32_t> segment_ends(const std::vector<Segment> &seg) {
+    std::vector<uint32_t> m((seg.size() + 31) / 32 + 1, 0u);
+    for (size_t j = 0; j < seg.size(); ++j)
+        if (j + 1 == seg.size() || seg[j + 1].kb != seg[j].kb) m[j / 32] |= 1u << (j % 32);
+    return m;
+}
+
+// Longest segment of the reconstruction MVM by storage type (vectors).
+int segment_vectors(int dtype) {
+    (void)dtype;
+    return kMaxSegVectors;
 }
 
 // Segments with their block's fields folded in (E slope values per vector).
@@ -295,18 +272,17 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                       (int64_t)last_nr * L.kv * 16;
     }
     I->spad_len = spad;
-    const PieceShape ps = piece_shape(I->d.cm_dtype);
-    build_segments(I->kb, ps.target, (ps.min_waves + n_tiles - 1) / n_tiles, kMaxSegVectors,
-                   I->seg, I->pieces);
+    build_segments(I->kb, std::min(segment_vectors(I->d.cm_dtype), kMaxSegVectors), I->seg);
     I->kb_seg0.assign(I->kb.size(), 0);
     I->kb_nseg.assign(I->kb.size(), 0);
     for (size_t i = 0; i < I->seg.size(); ++i) {
         const int b = I->seg[i].kb;
         if (I->kb_nseg[b] == 0) I->kb_seg0[b] = (int)i;
         I->kb_nseg[b]++;
-        I->single.push_back(Piece{(int32_t)i, 1});
     }
     for (size_t b = 0; b < I->kb.size(); ++b) I->kb_segs.push_back(int2{I->kb_seg0[b], I->kb_nseg[b]});
+    if (I->seg.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
+    I->seg_ends = segment_ends(I->seg);
     // POLC column blocks of kPolcBlock commands, F32
     if (I->d.polc) {
         const int nb = (I->n_act + kPolcBlock - 1) / kPolcBlock;
@@ -326,9 +302,7 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->m_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
                      (int64_t)last_nr * L.kv * 16;
         I->a_len = nb * kPolcBlock;
-        build_segments(I->kbm, kPieceVectors, (kMinMvmWaves + n_tiles - 1) / n_tiles,
-                       kMaxSegVectors, I->segm,
-                       I->pieces_m);
+        build_segments(I->kbm, kMaxSegVectors, I->segm);
         std::vector<int> s0(I->kbm.size(), 0), ns(I->kbm.size(), 0);
         for (size_t i = 0; i < I->segm.size(); ++i) {
             const int b = I->segm[i].kb;
@@ -336,6 +310,8 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
             ns[b]++;
         }
         for (size_t b = 0; b < I->kbm.size(); ++b) I->kbm_segs.push_back(int2{s0[b], ns[b]});
+        if (I->segm.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
+        I->segm_ends = segment_ends(I->segm);
     } else {
         I->a_len = I->n_act;
     }
@@ -352,12 +328,11 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_seg, I->seg.size()));
     TRY(dev_alloc(e, &I->d_kb_segs, I->kb_segs.size()));
     TRY(dev_alloc(e, &I->d_kbm_segs, std::max<size_t>(I->kbm_segs.size(), 1)));
-    TRY(dev_alloc(e, &I->d_single, I->single.size()));
-    TRY(dev_alloc(e, &I->d_pieces, I->pieces.size()));
+    TRY(dev_alloc(e, &I->d_seg_ends, I->seg_ends.size()));
+    TRY(dev_alloc(e, &I->d_segm_ends, std::max<size_t>(I->segm_ends.size(), 1)));
     TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
     TRY(dev_alloc(e, &I->d_run, I->seg.size()));
     TRY(dev_alloc(e, &I->d_runm, std::max<size_t>(I->segm.size(), 1)));
-    TRY(dev_alloc(e, &I->d_pieces_m, std::max<size_t>(I->pieces_m.size(), 1)));
     size_t sh_px = 0;
     for (auto &u : I->sh) sh_px += (size_t)I->params.w[u.wfs].p * I->params.w[u.wfs].p;
     TRY(dev_alloc(e, &I->d_sh_dark, sh_px));
@@ -388,9 +363,9 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_p, I->n_act));
     TRY(dev_alloc(e, &I->d_yscratch, I->n_act));
     I->n_tiles = (I->n_act + kTileRows - 1) / kTileRows;
-    TRY(dev_alloc(e, &I->d_count, I->n_tiles));
-    TRY(dev_alloc(e, &I->d_count_m, I->n_tiles));
-    TRY(dev_alloc(e, &I->d_count_t, I->n_tiles));
+    TRY(dev_alloc(e, &I->d_count, (size_t)I->n_tiles * kCountStride));
+    TRY(dev_alloc(e, &I->d_count_m, (size_t)I->n_tiles * kCountStride));
+    TRY(dev_alloc(e, &I->d_count_t, (size_t)I->n_tiles * kCountStride));
     HIP_TRY(hipMemcpy(I->d_sh, I->sh.data(), I->sh.size() * sizeof(ShUnit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(I->d_py, I->py.data(), I->py.size() * sizeof(PyrUnit), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(I->d_kb, I->kb.data(), nkb * sizeof(KBlock), hipMemcpyHostToDevice));
@@ -403,10 +378,9 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     HIP_TRY(up(I->d_seg, I->seg.data(), I->seg.size() * sizeof(Segment)));
     HIP_TRY(up(I->d_kb_segs, I->kb_segs.data(), I->kb_segs.size() * sizeof(int2)));
     HIP_TRY(up(I->d_kbm_segs, I->kbm_segs.data(), I->kbm_segs.size() * sizeof(int2)));
-    HIP_TRY(up(I->d_single, I->single.data(), I->single.size() * sizeof(Piece)));
-    HIP_TRY(up(I->d_pieces, I->pieces.data(), I->pieces.size() * sizeof(Piece)));
+    HIP_TRY(up(I->d_seg_ends, I->seg_ends.data(), I->seg_ends.size() * 4));
+    HIP_TRY(up(I->d_segm_ends, I->segm_ends.data(), I->segm_ends.size() * 4));
     HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));
-    HIP_TRY(up(I->d_pieces_m, I->pieces_m.data(), I->pieces_m.size() * sizeof(Piece)));
     const std::vector<SegRun> run = seg_runs(I->kb, I->seg, elems_per_vec(I->d.cm_dtype));
     const std::vector<SegRun> runm = seg_runs(I->kbm, I->segm, elems_per_vec(RTC_CM_F32));
     HIP_TRY(up(I->d_run, run.data(), run.size() * sizeof(SegRun)));
@@ -501,8 +475,7 @@ MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t seq, float c1, float g, 
     E.mode = EPI_INTEGRATE;
     E.rev = (int32_t)(seq & 1);
     E.n_parts = (int)I->seg.size();
-    E.n_kb = (int)I->kb.size();
-    E.kb_segs = I->d_kb_segs;
+    E.seg_ends = I->d_seg_ends;
     E.count = I->d_count;
     E.p = I->d.polc ? I->d_p : nullptr;
     E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale_s[ms] : nullptr;
@@ -521,12 +494,11 @@ void enqueue_polc(Instance *I, hipStream_t st, int ms) {
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
     E.n_parts = (int)I->segm.size();
-    E.n_kb = (int)I->kbm.size();
-    E.kb_segs = I->d_kbm_segs;
+    E.seg_ends = I->d_segm_ends;
     E.count = I->d_count_m;
     E.y = I->d_p;
-    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_runm, I->d_pieces_m, 0,
-               (int)I->pieces_m.size(), I->n_act, I->d_a, I->d_ppart, E);
+    launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_runm, 0, (int)I->segm.size(),
+               I->n_act, I->d_a, I->d_ppart, E);
 }
 
 rtc_status check(rtc_engine *e, int32_t inst, Instance **out) {
@@ -853,7 +825,7 @@ rtc_status rtc_load_matrices(rtc_engine *e, int32_t inst, const float *R, const 
     TRY(put_matrices(e, I, I->m_active, R, D, M));
     const int na = I->n_act;
     HIP_TRY(hipMemset(I->d_p, 0, (size_t)na * 4));
-    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
+    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * kCountStride * 4));
     HIP_TRY(hipMemset(I->d_a, 0, (size_t)I->a_len * 4));
     HIP_TRY(hipMemset(I->d_spad, 0, (size_t)I->spad_len * 4));
     HIP_TRY(hipMemset(I->d_spad2, 0, (size_t)I->spad_len * 4));
@@ -1038,7 +1010,7 @@ rtc_status rtc_set_state(rtc_engine *e, int32_t inst, const float *a, const floa
     if (a) HIP_TRY(hipMemcpy(I->d_a, a, I->n_act * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemset(I->d_p, 0, (size_t)I->n_act * 4));
     if (p && I->d.polc) HIP_TRY(hipMemcpy(I->d_p, p, I->n_act * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * 4));
+    HIP_TRY(hipMemset(I->d_count, 0, (size_t)I->n_tiles * kCountStride * 4));
     I->next_frame = next_frame;
     I->seq = 0;
     I->cur_frame = ~0ull;
@@ -1148,16 +1120,15 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
                 I->mvm_run = 0;
             }
             launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
-                            I->d_pieces, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E, N,
-                            I->params);
+                            (int)I->seg.size(), I->n_act, x, I->d_ypart, E, N, I->params);
             if (I->mvm_open && (++I->mvm_run == I->mvm_ev_every || f + 2 >= n_frames)) {
                 HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used + 1], st));
                 I->mvm_ev_len[I->mvm_ev_used++] = I->mvm_run;
                 I->mvm_open = false;
             }
         } else {
-            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
-                       I->d_pieces, 0, (int)I->pieces.size(), I->n_act, x, I->d_ypart, E);
+            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run, 0,
+                       (int)I->seg.size(), I->n_act, x, I->d_ypart, E);
         }
         enqueue_polc(I, st, ms);
         if (f + 1 < n_frames) TRY(copy_out(f + 1));
@@ -1177,14 +1148,13 @@ rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
     E.n_parts = (int)I->seg.size();
-    E.n_kb = (int)I->kb.size();
-    E.kb_segs = I->d_kb_segs;
+    E.seg_ends = I->d_seg_ends;
     E.count = I->d_count_t;
     E.y = I->d_yscratch;
     std::lock_guard<std::mutex> lk(I->mu);
     for (int i = 0; i < n_iter; ++i)
-        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->m_active], I->d_run,
-                   I->d_pieces, 0, (int)I->pieces.size(), I->n_act, I->d_spad, I->d_ypart, E);
+        launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->m_active], I->d_run, 0,
+                   (int)I->seg.size(), I->n_act, I->d_spad, I->d_ypart, E);
     return last_error(e);
 }
 
@@ -1347,7 +1317,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
             old.dropped = true;
             I->drops++;
             // its column blocks left partial arrival counts behind
-            HIP_TRY(hipMemsetAsync(I->d_count, 0, (size_t)I->n_tiles * 4, e->stream));
+            HIP_TRY(hipMemsetAsync(I->d_count, 0, (size_t)I->n_tiles * kCountStride * 4, e->stream));
         }
         FrameSlot &sl = I->slots[frame % I->slots.size()];
         if (sl.frame != ~0ull) {
@@ -1390,9 +1360,9 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         const int ub = K.k0 / 2, ue = (K.k0 + K.k) / 2;
         enqueue_centroid(I, e->stream, fs, wfs, ub, ue);
         launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_run,
-                   I->d_single, I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad,
-                   I->d_ypart, integrate_epi(I, I->frame_mslot, I->frame_seq, I->frame_c1,
-                                 I->frame_g, nullptr));
+                   I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad, I->d_ypart,
+                   integrate_epi(I, I->frame_mslot, I->frame_seq, I->frame_c1, I->frame_g,
+                                 nullptr));
     }
     S.next_chunk++;
     bool all = true;

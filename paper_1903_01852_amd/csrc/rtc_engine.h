@@ -19,7 +19,6 @@ using rtc::KBlock;
 using rtc::KbWork;
 using rtc::ParamBlock;
 using rtc::PersistInst;
-using rtc::Piece;
 using rtc::PyrUnit;
 using rtc::Segment;
 using rtc::ShUnit;
@@ -127,10 +126,9 @@ struct Instance {
     std::vector<Step> steps;       // (sensor, chunk) pairs in readout order
     std::vector<KBlock> kbm;       // POLC column blocks
     std::vector<Segment> seg, segm;            // segments: reconstruction, POLC
-    std::vector<Piece> pieces, pieces_m;       // equal-length pieces (whole frame)
-    std::vector<Piece> single;                 // one piece per reconstruction segment
     std::vector<int> kb_seg0, kb_nseg;         // segments of each column block
     std::vector<int2> kb_segs, kbm_segs;       // the same as {first, count}, recon / POLC
+    std::vector<uint32_t> seg_ends, segm_ends; // bit j: segment j ends its block (recon / POLC)
     int spad_len = 0;
     int64_t cm_bytes = 0, m_bytes = 0;
     bool stream_nt = false;        // non-temporal matrix loads (the engine's matrices exceed the cache)
@@ -143,7 +141,7 @@ struct Instance {
     Segment *d_seg = nullptr, *d_segm = nullptr;
     rtc::SegRun *d_run = nullptr, *d_runm = nullptr;   // the segments, block fields folded in
     int2 *d_kb_segs = nullptr, *d_kbm_segs = nullptr;   // per block {first segment, count}
-    Piece *d_pieces = nullptr, *d_pieces_m = nullptr, *d_single = nullptr;
+    uint32_t *d_seg_ends = nullptr, *d_segm_ends = nullptr;
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
     float *d_ref = nullptr;

@@ -11,8 +11,9 @@ namespace rtc {
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kTileRows = 64;      // matrix rows per MVM tile: one row per lane
 constexpr int kPolcBlock = 512;    // command elements per POLC column block
-constexpr int kPieceVectors = 128; // target length of an MVM piece (16-byte vectors per row)
-constexpr int kMinMvmWaves = 1536; // at least this many wavefronts per full MVM (6 per CU)
+constexpr int kMaxSegVectors = 128; // longest MVM segment (16-byte vectors per row; its slopes sit in LDS)
+constexpr int kEndWordsPerLane = 4; // block-end mask words each lane holds in a reduction
+constexpr int kMaxSegments = kEndWordsPerLane * kWave * 32;   // segments of one matrix
 constexpr int kMaxShPx = 16;       // largest SH subaperture side (pixels)
 constexpr int kMaxShPasses = (kMaxShPx * kMaxShPx + kWave - 1) / kWave;
 
@@ -88,17 +89,13 @@ struct Step {
 constexpr int kIngestUnits = 512;                 // 16-byte units per ingest piece (8 KiB)
 
 // A segment is the part of one column block that one wavefront streams for a
-// tile: vectors [v0, v0 + nv) of block kb.  Each segment owns one partial
-// (its index in the global segment order).  The column range of every tile is
-// cut into pieces of nearly equal length so that wavefronts finish together;
-// a piece is a run of consecutive segments.  The serving path launches the
-// same segments chunk by chunk, so both paths add the same partials in the
-// same order.
+// tile: vectors [v0, v0 + nv) of block kb (each block is cut into nearly
+// equal segments of at most kMaxSegVectors).  Each segment owns one partial
+// (its index in the global segment order).  Every path (per-launch MVM, the
+// frame loop's batch and serving tasks) streams the same segments and adds
+// the same partials in the same order.
 struct Segment {
     int32_t kb, v0, nv, r;
-};
-struct Piece {
-    int32_t seg0, nseg;
 };
 // A segment with its column block's fields folded in, for the per-launch MVM:
 // one record read per segment instead of a segment then its block.
@@ -110,15 +107,21 @@ struct SegRun {
     int32_t r0, r1;
 };
 
+// Per-tile arrival counters of the per-launch MVM sit 256 bytes apart:
+// agent-scope atomics on one cache line serialise (~10^4 arrivals per MVM on
+// a handful of lines cost 25-45 us), on distinct lines they run in parallel.
+constexpr int kCountStride = 64;   // uint32 per counter
+
 // Work done by the last wavefront to finish a row tile of an MVM.
 enum { EPI_NONE = 0, EPI_INTEGRATE = 1, EPI_REDUCE = 2 };
 struct MvmEpilogue {
     int32_t mode;          // EPI_*
     int32_t n_parts;       // segment partials per row (all launches of the frame)
-    int32_t n_kb;          // column blocks; kb_segs[b] = {first segment, segments}
     int32_t rev;           // 1: each segment streamed last vector first (odd frames)
-    const int2 *kb_segs;
-    uint32_t *count;       // per-tile arrival counters, zero between frames
+    int32_t r0;
+    const uint32_t *seg_ends;  // bit j: segment j ends its column block
+    uint32_t *count;       // per-tile arrival counters (tile t at count[t * kCountStride]),
+                           // zero between frames
     const float *p;        // INTEGRATE: POLC term (nullable)
     const float *scale;    // INTEGRATE: FP8 row scales (nullable)
     float *a;              // INTEGRATE: command state, updated in place
@@ -283,7 +286,6 @@ constexpr int kTelUnits = 1024;
 constexpr int kTelMaxTasks = 128;
 constexpr uint64_t kDbChunkMask = (1ull << 20) - 1;
 constexpr int kDbShift = 20;
-constexpr int kMaxSegVectors = kPieceVectors;   // longest segment (slopes staged in LDS)
 // Frame-loop counters sit 256 bytes apart: agent-scope atomics on one cache
 // line serialise (~12 ns each), on distinct lines they proceed in parallel.
 constexpr int kCtrSlot = 32;                      // uint64 per counter slot
@@ -317,9 +319,12 @@ void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const Frame
 // stream_nt: stream the matrix with non-temporal loads (matrices larger than
 // the Infinity Cache); otherwise ordinary loads keep a smaller matrix resident.
 constexpr int64_t kCacheResidentBytes = 192ll << 20;
+// Segments [s0, s0 + n_segs) of a matrix times x_pad into their partials
+// (y_part[segment][row]); the epilogue runs when a tile's partials are
+// complete (E.n_parts segments over all launches of the frame).
 void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const SegRun *runs,
-                const Piece *pieces, int p0, int n_pieces, int n_rows, const float *x_pad,
-                float *y_part, const MvmEpilogue &epi);
+                int s0, int n_segs, int n_rows, const float *x_pad, float *y_part,
+                const MvmEpilogue &epi);
 // Slopes of the next frame, formed by extra workgroups of the current frame's
 // MVM launch (every SH unit, then every pyramid unit of the instance).
 struct NextSlopes {
@@ -338,9 +343,9 @@ struct NextSlopes {
 // launch_mvm (reading x_pad) plus, in the same grid, the slopes of the next
 // frame into next.s_pad (a different buffer than x_pad).
 void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm,
-                     const SegRun *runs, const Piece *pieces, int n_pieces, int n_rows,
-                     const float *x_pad, float *y_part, const MvmEpilogue &epi,
-                     const NextSlopes &next, const WfsParamSet &params);
+                     const SegRun *runs, int n_segs, int n_rows, const float *x_pad,
+                     float *y_part, const MvmEpilogue &epi, const NextSlopes &next,
+                     const WfsParamSet &params);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
                      int n_s);
 

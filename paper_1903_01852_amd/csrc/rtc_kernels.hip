@@ -95,54 +95,159 @@ __global__ __launch_bounds__(256) void k_pyr_sum(const PyrUnit *__restrict__ uni
 // order, exactly as the persistent frame loop accumulates it.
 __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float *__restrict__ part,
                                               int n_rows, int t, int lane, int nr) {
-    const int r = t * kTileRows + lane;
+    // every lane loads its words of the block-end mask (the test reads them
+    // across lanes); lanes past a short tile read row 0's partials
+    const SegEnds ends = load_seg_ends(E.seg_ends, E.n_parts, lane);
+    const int r = t * kTileRows + (lane < nr ? lane : 0);
+    // the integrator's operands load beside the partials
+    const bool integ = E.mode == EPI_INTEGRATE;
+    const float sc = integ && E.scale != nullptr ? E.scale[r] : 1.0f;
+    const float pp = integ && E.p != nullptr ? E.p[r] : 0.0f;
+    const float ap = integ ? E.a[r] : 0.0f;
+    float y = sum_partials<64>(part, E.n_parts, n_rows, r, ends);
     if (lane >= nr) return;
-    const int2 *kb_segs = E.kb_segs;
-    float y = sum_in_blocks<32>(part, E.n_parts, E.n_kb, n_rows, r, [&](int b) {
-        const int2 sb = kb_segs[b];
-        return sb.x + sb.y;
-    });
-    if (E.mode == EPI_REDUCE) {
+    if (!integ) {
         E.y[r] = y;
         return;
     }
-    if (E.scale != nullptr) y *= E.scale[r];
-    if (E.p != nullptr) y += E.p[r];
-    const float an = fmaf(E.c1, E.a[r], E.g * y);
+    if (E.scale != nullptr) y *= sc;
+    if (E.p != nullptr) y += pp;
+    const float an = fmaf(E.c1, ap, E.g * y);
     E.a[r] = an;
     if (E.out != nullptr) E.out[r] = an;
 }
 
-// One wavefront of the split-K MVM: piece wv / n_tiles of tile wv % n_tiles.
-template <int DT, int U, bool NT>
-__device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__restrict__ cm,
-                                         const SegRun *__restrict__ runs,
-                                         const Piece *__restrict__ pieces, int p0, int n_pieces,
-                                         int n_tiles, int n_rows, const float *__restrict__ x,
-                                         float *__restrict__ y_part, const MvmEpilogue &E) {
-    if (wv >= n_pieces * n_tiles) return;
-    const int pi = wv / n_tiles;
-    const int t = wv - pi * n_tiles;
-    const Piece P = pieces[p0 + pi];
-    const int nr = min(kTileRows, n_rows - t * kTileRows);
-    // odd frames run the piece backwards, segments and vectors alike
-    const int rev = __builtin_amdgcn_readfirstlane(E.rev);
-    for (int sgi = 0; sgi < P.nseg; ++sgi) {
-        const int sg = P.seg0 + (rev ? P.nseg - 1 - sgi : sgi);
-        const SegRun S = runs[sg];
-        if (lane < nr) {
-            const uint4 *__restrict__ p =
-                reinterpret_cast<const uint4 *>(cm + S.base + (int64_t)t * kTileRows * S.kv * 16) +
-                (int64_t)S.v0 * nr + lane;
-            const float4 *__restrict__ xs = reinterpret_cast<const float4 *>(x + S.xoff);
-            const float part = rev ? stream_segment<DT, U, const float4 *, NT, true>(p, nr, xs, S.nv)
-                                   : stream_segment<DT, U, const float4 *, NT>(p, nr, xs, S.nv);
-            // agent-scope atomic store: written through to the memory side,
-            // where every XCD's agent-scope loads see it
-            __hip_atomic_store(y_part + (size_t)sg * n_rows + t * kTileRows + lane, part,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+// The split-K MVM.  A workgroup streams one segment (part of one column
+// block) for four consecutive 64-row tiles, one tile per wavefront, one row
+// per lane; the segment's slope values are staged once in LDS and read by
+// every lane as broadcasts.
+//
+// Each wavefront streams its segment in batches of U 16-byte vectors,
+// double-buffered: the loads of batch i + 1 are in flight while batch i's
+// products run, so every lane keeps 2U loads outstanding.  Loads are buffer
+// loads over the segment's part of the tile: the offsets are scalar, and a
+// vector past the segment's end reads as zeros without a memory access (its
+// slopes in LDS are zero too), so every batch issues exactly U loads and the
+// compiler's memory-counter waits stay exact instead of draining the stream.
+// Odd frames (REV) visit the vectors last to first.  Products accumulate in
+// visiting order into two running sums (even and odd elements of each
+// vector), exactly as stream_segment does, so the partial equals the frame
+// loop's bit for bit.
+constexpr int kBufNT = 2;      // buffer-load cache policy: non-temporal
+
+// Batches are taken in pairs, so that no loop exit sits between a batch's
+// loads and their use (the compiler would otherwise sink the prefetch past
+// it).  An odd batch count ends with one batch past the end: its loads return
+// zeros without touching memory and its slopes in LDS are zeros, so it adds
+// exact zeros after every real product.
+template <int U, bool NT>
+struct SegStream {
+    __amdgpu_buffer_rsrc_t rs;
+    int nb, voff, vstride;
+    __device__ __forceinline__ int bmap(int b) const { return (b < 0 || b >= nb) ? nb : b; }
+    __device__ __forceinline__ void load(vec16_t (&q)[U], int b) const {
+        const int o = bmap(b) * U * vstride;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, o + u * vstride,
+                                                         NT ? kBufNT : 0);
     }
+};
+
+// A segment's slope values staged in LDS by the whole workgroup (zero past
+// its last vector, one zero batch beyond), with this wavefront's first matrix
+// batch issued before the copy's wait, so that the two round trips overlap;
+// then the double-buffered stream.  Returns this lane's partial.
+template <int DT, int U, bool NT, bool REV>
+__device__ __forceinline__ float seg_partial_buf(const SegStream<U, NT> &ss, const float *x,
+                                                 int nx, int n4, bool live, RTC_LDS float *lds) {
+    constexpr int EL = Elem<DT>::E;
+    constexpr int kStage = (((kMaxSegVectors + U - 1) / U + 1) * U * EL / 4 + 255) / 256;
+    constexpr int step = REV ? -1 : 1;
+    lds4_t sv[kStage];
+    const lds4_t *__restrict__ xs4 = reinterpret_cast<const lds4_t *>(x);
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+        const int i = j * 256 + (int)threadIdx.x;
+        sv[j] = xs4[4 * i < nx ? i : 0];
+    }
+    int b = REV ? ss.nb - 1 : 0;
+    vec16_t qa[U], qb[U];
+    ss.load(qa, b);
+#pragma unroll
+    for (int j = 0; j < kStage; ++j) {
+        const int i = j * 256 + (int)threadIdx.x;
+        if (i < n4) ((RTC_LDS lds4_t *)lds)[i] = 4 * i < nx ? sv[j] : lds4_t{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    // LDS writes complete, then the barrier (no fence: it would also wait for
+    // the matrix loads in flight)
+    __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    if (!live) return 0.0f;
+    const RTC_LDS lds4_t *xl = (const RTC_LDS lds4_t *)lds;
+    float a0 = 0.0f, a1 = 0.0f;
+    auto compute = [&](const vec16_t (&q)[U], int bb) {
+        const int v0 = ss.bmap(bb) * U;
+        if constexpr (!REV) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
+        } else {
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
+        }
+    };
+    // the scheduler barriers keep each batch's loads ahead of the previous
+    // batch's products (left to itself, the scheduler sinks them to save
+    // registers, which drains the stream at every batch)
+    for (int i = 0; i < (ss.nb + 1) / 2; ++i) {
+        ss.load(qb, b + step);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(qa, b);
+        __builtin_amdgcn_sched_barrier(0);
+        ss.load(qa, b + 2 * step);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(qb, b + step);
+        __builtin_amdgcn_sched_barrier(0);
+        b += 2 * step;
+    }
+    return a0 + a1;
+}
+
+template <int DT, int U, bool NT>
+__device__ __forceinline__ void mvm_group(int g, int wave, int lane, const uint8_t *__restrict__ cm,
+                                          const SegRun *__restrict__ runs, int s0, int n_tiles,
+                                          int n_rows, const float *__restrict__ x,
+                                          float *__restrict__ y_part, const MvmEpilogue &E,
+                                          RTC_LDS float *lds) {
+    constexpr int EL = Elem<DT>::E;
+    const int tgroups = (n_tiles + 3) / 4;
+    const int si = g / tgroups;
+    const int t = (g - si * tgroups) * 4 + wave;
+    const int sg = s0 + si;
+    const SegRun S = runs[sg];
+    const int nb = (S.nv + U - 1) / U;
+    const int n4 = (nb + 1) * U * EL / 4;      // padded slope float4s
+    const int nx = S.nv * EL;                  // real slope values
+    // the segment's part of tile t: nv vectors of nr rows, 16 bytes each (a
+    // wavefront past the last tile gets an empty range: its loads read zeros)
+    const bool live = t < n_tiles;
+    const int tt = live ? t : n_tiles - 1;
+    const int nr = min(kTileRows, n_rows - tt * kTileRows);
+    SegStream<U, NT> ss;
+    ss.rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(cm + S.base + ((int64_t)tt * kTileRows * S.kv + (int64_t)S.v0 * nr) * 16),
+        (short)0, live ? S.nv * nr * 16 : 0, 0x00020000);
+    ss.nb = nb;
+    ss.voff = lane * 16;                      // this lane's row within a vector
+    ss.vstride = nr * 16;                     // bytes between consecutive vectors
+    const bool rev = __builtin_amdgcn_readfirstlane(E.rev) != 0;
+    const float *xs = x + S.xoff;
+    const float part = rev ? seg_partial_buf<DT, U, NT, true>(ss, xs, nx, n4, live, lds)
+                           : seg_partial_buf<DT, U, NT, false>(ss, xs, nx, n4, live, lds);
+    if (!live) return;
+    if (lane < nr)
+        __hip_atomic_store(y_part + (size_t)sg * n_rows + t * kTileRows + lane, part,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (E.mode == EPI_NONE) return;
     // Count this tile's partials only once their stores have completed
     // (vmcnt drained); the wavefront bringing the count to E.n_parts runs the
@@ -154,24 +259,28 @@ __device__ __forceinline__ void mvm_wave(int wv, int lane, const uint8_t *__rest
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     uint32_t old = 0;
     if (lane == 0)
-        old = __hip_atomic_fetch_add(&E.count[t], (uint32_t)P.nseg, __ATOMIC_RELAXED,
+        old = __hip_atomic_fetch_add(&E.count[t * kCountStride], 1u, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT);
     old = __shfl(old, 0, kWave);
-    if (old + (uint32_t)P.nseg != (uint32_t)E.n_parts) return;
-    if (lane == 0) __hip_atomic_store(&E.count[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1u != (uint32_t)E.n_parts) return;
+    if (lane == 0)
+        __hip_atomic_store(&E.count[t * kCountStride], 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     tile_epilogue(E, y_part, n_rows, t, lane, nr);
 }
 
+// Segments [s0, s0 + n) of the matrix, grid = n x ceil(n_tiles / 4).
 template <int DT, int U, bool NT>
 __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
-                                             const SegRun *__restrict__ runs,
-                                             const Piece *__restrict__ pieces, int p0,
-                                             int n_pieces, int n_tiles, int n_rows,
+                                             const SegRun *__restrict__ runs, int s0,
+                                             int n_tiles, int n_rows,
                                              const float *__restrict__ x,
                                              float *__restrict__ y_part, MvmEpilogue E) {
+    extern __shared__ __attribute__((aligned(16))) float lds_dyn[];
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    mvm_wave<DT, U, NT>(wv, lane, cm, runs, pieces, p0, n_pieces, n_tiles, n_rows, x, y_part, E);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    mvm_group<DT, U, NT>(__builtin_amdgcn_readfirstlane(blockIdx.x), wave, lane, cm, runs, s0,
+                         n_tiles, n_rows, x, y_part, E, (RTC_LDS float *)lds_dyn);
 }
 
 // The MVM's workgroups come first, so they are dispatched first and stream
@@ -179,18 +288,18 @@ __global__ __launch_bounds__(256) void k_mvm(const uint8_t *__restrict__ cm,
 template <int DT, int U, bool NT>
 __global__ __launch_bounds__(256) void k_mvm_next(const uint8_t *__restrict__ cm,
                                                   const SegRun *__restrict__ runs,
-                                                  const Piece *__restrict__ pieces, int n_pieces,
                                                   int n_tiles, int n_rows,
                                                   const float *__restrict__ x,
                                                   float *__restrict__ y_part, MvmEpilogue E,
                                                   int mvm_blocks, NextSlopes N,
                                                   WfsParamSet params) {
+    extern __shared__ __attribute__((aligned(16))) float lds_dyn[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x);
     if (blk < mvm_blocks) {
-        mvm_wave<DT, U, NT>(blk * 4 + wave, lane, cm, runs, pieces, 0, n_pieces, n_tiles, n_rows,
-                            x, y_part, E);
+        mvm_group<DT, U, NT>(blk, wave, lane, cm, runs, 0, n_tiles, n_rows, x, y_part, E,
+                             (RTC_LDS float *)lds_dyn);
         return;
     }
     const SlopeOut o{N.s_pad, N.s_out, N.counts, N.masks};
@@ -291,83 +400,88 @@ void launch_pyr_sum(hipStream_t st, const PyrUnit *units, int n_pyr, const Frame
                        dark4, flat4, bg4, thr, wfs, gsum);
 }
 
-// Vectors per batch: 16 for FP32; 8 for BF16 and FP8, whose batch of slope
-// values (8 or 16 per vector, read through the scalar unit) would not fit the
-// scalar registers at 16 (measured: FP8 on a 302 MB matrix 87 -> 78 us cold).
+// Vectors per batch (double-buffered, so twice as many 16-byte loads per lane
+// in flight): 8 for every storage type.
+constexpr int kMvmBatch = 8;
+
+// LDS of an MVM workgroup: its segment's slope values, padded to whole batches
+// plus one batch of zeros.
+size_t mvm_lds_bytes(int dtype) {
+    const int E = dtype == RTC_CM_F32 ? 4 : dtype == RTC_CM_BF16 ? 8 : 16;
+    return (size_t)(((kMaxSegVectors + kMvmBatch - 1) / kMvmBatch + 1) * kMvmBatch) * E * 4;
+}
+
 template <bool NT>
-void launch_mvm_t(hipStream_t st, int dtype, const uint8_t *c, const SegRun *runs,
-                  const Piece *pieces, int p0, int n_pieces, int n_tiles, int n_rows,
-                  const float *x_pad, float *y_part, const MvmEpilogue &epi) {
-    const dim3 grid((n_pieces * n_tiles + 3) / 4), block(256);
+void launch_mvm_t(hipStream_t st, int dtype, const uint8_t *c, const SegRun *runs, int s0,
+                  int n_segs, int n_tiles, int n_rows, const float *x_pad, float *y_part,
+                  const MvmEpilogue &epi) {
+    const dim3 grid(n_segs * ((n_tiles + 3) / 4)), block(256);
+    const size_t lds = mvm_lds_bytes(dtype);
     switch (dtype) {
     case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, runs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_F32, kMvmBatch, NT>), grid, block, lds, st, c, runs, s0,
+                           n_tiles, n_rows, x_pad, y_part, epi);
         break;
     case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, runs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_BF16, kMvmBatch, NT>), grid, block, lds, st, c, runs, s0,
+                           n_tiles, n_rows, x_pad, y_part, epi);
         break;
     default:
-        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, runs, pieces, p0,
-                           n_pieces, n_tiles, n_rows, x_pad, y_part, epi);
+        hipLaunchKernelGGL((k_mvm<RTC_CM_FP8, kMvmBatch, NT>), grid, block, lds, st, c, runs, s0,
+                           n_tiles, n_rows, x_pad, y_part, epi);
         break;
     }
 }
 
 void launch_mvm(hipStream_t st, int dtype, bool stream_nt, const void *cm, const SegRun *runs,
-                const Piece *pieces, int p0, int n_pieces, int n_rows, const float *x_pad,
-                float *y_part, const MvmEpilogue &epi) {
-    if (n_pieces <= 0 || n_rows <= 0) return;
+                int s0, int n_segs, int n_rows, const float *x_pad, float *y_part,
+                const MvmEpilogue &epi) {
+    if (n_segs <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
     const uint8_t *c = static_cast<const uint8_t *>(cm);
     if (stream_nt)
-        launch_mvm_t<true>(st, dtype, c, runs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad, y_part,
-                           epi);
+        launch_mvm_t<true>(st, dtype, c, runs, s0, n_segs, n_tiles, n_rows, x_pad, y_part, epi);
     else
-        launch_mvm_t<false>(st, dtype, c, runs, pieces, p0, n_pieces, n_tiles, n_rows, x_pad,
-                            y_part, epi);
+        launch_mvm_t<false>(st, dtype, c, runs, s0, n_segs, n_tiles, n_rows, x_pad, y_part, epi);
 }
 
 template <bool NT>
 void launch_mvm_next_t(hipStream_t st, int dtype, const uint8_t *c, const SegRun *runs,
-                       const Piece *pieces, int n_pieces, int n_tiles,
-                       int n_rows, const float *x_pad, float *y_part, const MvmEpilogue &epi,
-                       const NextSlopes &next, const WfsParamSet &params) {
-    const int mvm_blocks = (n_pieces * n_tiles + 3) / 4;
+                       int n_segs, int n_tiles, int n_rows, const float *x_pad, float *y_part,
+                       const MvmEpilogue &epi, const NextSlopes &next,
+                       const WfsParamSet &params) {
+    const int mvm_blocks = n_segs * ((n_tiles + 3) / 4);
     const dim3 grid(mvm_blocks + (next.n_sh + 3) / 4 + (next.n_pyr + 255) / 256), block(256);
+    const size_t lds = mvm_lds_bytes(dtype);
     switch (dtype) {
     case RTC_CM_F32:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_F32, 16, NT>), grid, block, 0, st, c, runs,
-                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
-                           next, params);
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_F32, kMvmBatch, NT>), grid, block, lds, st, c,
+                           runs, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks, next, params);
         break;
     case RTC_CM_BF16:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_BF16, 8, NT>), grid, block, 0, st, c, runs,
-                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
-                           next, params);
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_BF16, kMvmBatch, NT>), grid, block, lds, st, c,
+                           runs, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks, next, params);
         break;
     default:
-        hipLaunchKernelGGL((k_mvm_next<RTC_CM_FP8, 8, NT>), grid, block, 0, st, c, runs,
-                           pieces, n_pieces, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks,
-                           next, params);
+        hipLaunchKernelGGL((k_mvm_next<RTC_CM_FP8, kMvmBatch, NT>), grid, block, lds, st, c,
+                           runs, n_tiles, n_rows, x_pad, y_part, epi, mvm_blocks, next, params);
         break;
     }
 }
 
 void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm,
-                     const SegRun *runs, const Piece *pieces, int n_pieces, int n_rows,
-                     const float *x_pad, float *y_part, const MvmEpilogue &epi,
-                     const NextSlopes &next, const WfsParamSet &params) {
-    if (n_pieces <= 0 || n_rows <= 0) return;
+                     const SegRun *runs, int n_segs, int n_rows, const float *x_pad,
+                     float *y_part, const MvmEpilogue &epi, const NextSlopes &next,
+                     const WfsParamSet &params) {
+    if (n_segs <= 0 || n_rows <= 0) return;
     const int n_tiles = (n_rows + kTileRows - 1) / kTileRows;
     const uint8_t *c = static_cast<const uint8_t *>(cm);
     if (stream_nt)
-        launch_mvm_next_t<true>(st, dtype, c, runs, pieces, n_pieces, n_tiles, n_rows, x_pad,
-                                y_part, epi, next, params);
+        launch_mvm_next_t<true>(st, dtype, c, runs, n_segs, n_tiles, n_rows, x_pad, y_part, epi,
+                                next, params);
     else
-        launch_mvm_next_t<false>(st, dtype, c, runs, pieces, n_pieces, n_tiles, n_rows, x_pad,
-                                 y_part, epi, next, params);
+        launch_mvm_next_t<false>(st, dtype, c, runs, n_segs, n_tiles, n_rows, x_pad, y_part,
+                                 epi, next, params);
 }
 
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
