@@ -1,46 +1,38 @@
 """Benchmark of the pixel -> command hot path on one MI355X.
 
-A step is one frame through every stage: calibration + slopes for every
-sensor, the split-K control-matrix MVM, the in-order accumulation +
-integrator (and the POLC product when the workload has it).  Frames are
-resident in HBM before the timed region.  ``value`` is frames per second of
-the batch path named by ``--path``:
-  stream      per-launch kernels on one stream: frame f's split-K MVM (whose
-              last wavefront per row tile runs the integrator) in one grid with
-              frame f + 1's calibration + slopes (into the other slope buffer);
-              the default, and the faster batch form;
-  persistent  the persistent frame loop, ``--bank`` frames per launch.
+Headline (BASELINE metric: frame latency p50/p99 us + RMS jitter, the MVM's
+HBM GB/s against peak, FP32 vs BF16): the LTAO serving configuration, the
+largest that runs on one GPU -- an LTAO instance (6 LGS Shack-Hartmann
+sensors of 68x68 subapertures at 10 px and one 8x8 NGS at 16 px, 5330
+actuators, 5330 x 40368 control matrix, implicit POLC, gain and leak switched
+mid-run through the API) running beside the 74x74 SCAO instance of uneven
+size in one persistent frame loop, FP32 control matrices.
 
-Also reported on the same JSON line:
-  roofline     the dominant kernel of the chosen path (k_mvm_next: frame f's MVM
-               with frame f + 1's slopes in one grid; or k_frame_loop):
-               algorithmic bytes per launch / its average duration, from HIP
-               events recorded on its own stream over the timed region (one
-               pair per run of 16 consecutive k_mvm_next launches, or per
-               frame-loop launch); ``traffic`` from the committed rocprofv3
-               counter summary when it was taken on the current kernel source;
-  paths        frames/s and kernel GB/s of both batch forms for every storage
-               type (FP32, BF16, FP8);
-  latency_us   serving latency of the persistent loop per storage type (last
-               chunk submitted from host memory -> commands seen on the host),
-               frames paced at 500 Hz with the chunks spread over a 1.5 ms
-               readout; p50 / p99 / RMS jitter; includes PCIe; ``zero_copy``
-               the same with the chunks written in place into the lent ring
-               slot (latency from the commit);
-               ``telemetry_every_frame``: the same with slopes, counts and
-               commands of every frame streamed to a host reader thread;
-               ``matrix_swap``: a second control matrix staged by another thread
-               while frames run and swapped in at a frame boundary, latency per
-               phase;
-  latency_suite_us  the same for the MCAO, LTAO + SCAO and 80x80 MCAO serving
-               cases (one persistent launch each);
-  latency_sweep_us  serving latency against sensor size at constant frame size;
-  mvm          the standalone MVM kernel per storage type, warm (back to back)
-               and after a 1 GiB read-only flush of the caches;
-  mvm_beyond_infinity_cache  the same on the matrices larger than the cache;
-  pyramid_normalisation  per-launch frames/s of the 92-pixel pyramid with local
-               and with global normalisation;
-  cpu_baseline the CPU oracle on a bounded sample of the same frames.
+A step is a batch of `--frames-per-step` frames (default 50) of that
+configuration served at the paper's 500 Hz: every sensor's pixels arrive as
+16 row chunks spread over a 1.5 ms readout from host memory, each frame goes
+through every stage (calibration, slopes, the split-K MVM, reduction,
+integrator, POLC product), and the commands are published to host memory.
+The chunks are submitted and the commands collected by the library's own
+pacer threads (rtc_pacer_run, pinned to cores), so the figures hold no
+interpreter pause.  W warm-up steps are served first, then exactly K timed
+steps between two device synchronisations.
+
+  value          latency p50 (us) of the LTAO instance: its last chunk handed
+                 to the library -> its commands seen in host memory (PCIe both
+                 ways included); p99, RMS jitter, max and the device part beside
+                 it, and the same for the SCAO instance
+  roofline       the split-K MVM kernel on that configuration's LTAO matrix
+                 (861 MB FP32, beyond the 256 MB Infinity Cache), each launch
+                 after a 1 GiB read-only cache flush: algorithmic bytes per
+                 launch / its average duration from HIP events on its stream
+  cpu_baseline   the CPU oracle on the same workload (both instances per frame),
+                 per-frame time at all host threads and at one thread
+Extras (skipped with --quick): BF16 and FP8 storage of the same
+configuration, MCAO serving, the MVM on every matrix beyond the cache, the
+74x74 SCAO configuration (per-launch throughput, cache-resident MVM),
+telemetry, matrix swap, zero-copy hand-off, the sensor-size scan and the
+pyramid normalisations.
 """
 from __future__ import annotations
 
@@ -48,7 +40,9 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -60,6 +54,8 @@ METRIC = ("frame latency p50/p99 µs + RMS jitter; CM MVM HBM GB/s vs peak, "
 HBM_PEAK_GBS = 8000.0
 MVM_RUN = 16               # per-launch path: k_mvm_next launches per event pair
 ELEM = {"f32": 4, "bf16": 2, "fp8": 1}
+PERIOD_S = 2e-3            # 500 Hz (the paper's MCAO / LTAO frame rate)
+READOUT_S = 1.5e-3
 
 WORKLOAD_TEXT = {
     "scao_sh_74": "ELT SCAO Shack-Hartmann: 74x74 subapertures (3972 valid, 28% obstruction), "
@@ -67,10 +63,14 @@ WORKLOAD_TEXT = {
                   "5318 x 7944 control matrix, gain 0.4, leak 0.01",
     "scao_pyr_92": "ELT SCAO pyramid: four 92x92 pupils (6144 valid px) on a 240x240 uint16 "
                    "frame in 16 row chunks, 5318 x 12288 control matrix",
-    "ltao_68": "LTAO: 6 LGS SH 68x68 @10 px + 1 NGS 8x8 @16 px, 5330 x 40368 control "
-               "matrix, implicit POLC (5330 x 5330 FP32)",
+    "ltao_68": "LTAO: 6 LGS SH 68x68 @10 px (680x680 frames) + 1 NGS 8x8 @16 px, 16 row "
+               "chunks per LGS, 5330 actuators, 5330 x 40368 control matrix, implicit POLC "
+               "(5330 x 5330 FP32), gain/leak 0.4/0.01 switched to 0.3/0.02 mid-run; beside it "
+               "in the same persistent launch the 74x74 SCAO SH instance (5318 x 7944)",
     "mcao_74": "MCAO: 6 LGS SH 74x74 @10 px + 3 NGS 2x2 @16 px, 6318 x 47688 control "
                "matrix, implicit POLC (6318 x 6318 FP32)",
+    "mcao_80": "MCAO at the paper's 80x80 LGS size: 6 LGS SH 80x80 @10 px + 3 NGS 2x2, "
+               "6318 x 55416 control matrix, implicit POLC",
 }
 
 
@@ -110,99 +110,101 @@ def measured_traffic(workload: str, dtype: str, kernel: str):
     return ent.get("hbm_bytes_per_launch")
 
 
-def build_inputs(workload: str, bank: int):
+def polc_matrix_for(wl, i):
+    """POLC matrix of instance i: a stand-in for R.D with its statistics (the FP64
+    product costs TFLOPs on the host at these sizes)."""
+    import numpy as np
     import synth
-    wl = synth.get_workload(workload)
-    inst = wl.instances[0]
-    frames, cals = [], []
-    for w in range(len(inst.wfs)):
-        fr, cal = synth.sensor_inputs(wl, 0, w, n=bank)
-        frames.append(fr)
-        cals.append(cal)
-    R = synth.control_matrix(wl, 0)
-    M = None
-    if inst.polc:
-        import numpy as np
-        na = inst.n_act
-        M = synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na), synth.seed_for(wl.index, 0, 99, 5),
-                                  np.float32)
-    return wl, inst, frames, cals, R, M
+    inst = wl.instances[i]
+    if not inst.polc:
+        return None
+    na = inst.n_act
+    return synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na), synth.seed_for(wl.index, i, 99, 5),
+                                 np.float32)
 
 
-def alg_bytes_per_frame(inst, info, dtype):
-    """Bytes the method must move per frame: matrix (+ FP8 scales), POLC matrix,
-    processed pixels (2 B) and their calibration (dark, flat, bg: 12 B), slopes,
-    commands read and written."""
-    px = 0
-    for w in inst.wfs:
-        px += w.n_units * (w.px * w.px if w.kind == "sh" else 4)
-    b = inst.n_act * info["n_slopes"] * ELEM[dtype] + (4 * inst.n_act if dtype == "fp8" else 0)
-    if inst.polc:
-        b += 4 * inst.n_act * inst.n_act
-    return b + 14 * px + 4 * info["n_slopes"] + 8 * inst.n_act
+def build_inputs(name: str, bank: int):
+    """Per instance: R, M (or None), per-sensor frame banks, calibrations."""
+    import synth
+    wl = synth.get_workload(name)
+    out = []
+    for i, inst in enumerate(wl.instances):
+        frames, cals = [], []
+        for w in range(len(inst.wfs)):
+            fr, cal = synth.sensor_inputs(wl, i, w, n=bank)
+            frames.append(fr)
+            cals.append(cal)
+        out.append({"R": synth.control_matrix(wl, i), "M": polc_matrix_for(wl, i),
+                    "frames": frames, "cals": cals})
+    return wl, out
 
 
-def mvm_next_alg_bytes(inst, info, dtype):
-    """Bytes of one k_mvm_next launch: frame f's MVM (matrix, slopes read,
-    commands read and written) and frame f + 1's slopes (pixels, calibration,
-    slopes written): a frame's bytes less the POLC product, a launch of its own."""
-    b = alg_bytes_per_frame(inst, info, dtype)
-    return b - (4 * inst.n_act * inst.n_act if inst.polc else 0)
-
-
-def make_engine(rtc, inst, dtype, cals, R, M, mode="persistent"):
-    eng = rtc.Engine([(inst, dtype)], ring_depth=4, mode=mode)
-    eng.load_matrices(0, R, M=M)
-    for w, cal in enumerate(cals):
-        eng.load_calibration(0, w, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
+def load_engine(rtc, wl, data, dtype, mode, only=None):
+    idx = list(range(len(wl.instances))) if only is None else [only]
+    eng = rtc.Engine([(wl.instances[i], dtype) for i in idx], ring_depth=4, mode=mode)
+    for k, i in enumerate(idx):
+        eng.load_matrices(k, data[i]["R"], M=data[i]["M"])
+        for w, cal in enumerate(data[i]["cals"]):
+            eng.load_calibration(k, w, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
     return eng
 
 
-def run_steps(eng, dframes, bank, n, stream):
-    done = 0
-    while done < n:
-        k = min(bank, n - done)
-        eng.process_frames(0, dframes, k, stream=stream)
-        done += k
+def _pct(v):
+    import numpy as np
+    v = np.asarray(v, dtype=np.float64)
+    v = v[~np.isnan(v)]
+    if v.size == 0:
+        return None
+    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)),
+            "mean": float(v.mean()), "rms_jitter": float(v.std()), "max": float(v.max()),
+            "frames": int(v.size)}
 
 
-def throughput(torch, eng, dframes, bank, steps, warmup, path):
-    """Wall time of `steps` frames and the average duration of the path's
-    dominant kernel: per launch of `bank` frames of the frame loop (HIP events
-    around each process_frames call on its stream), or per k_mvm_next launch of
-    the per-launch path (HIP events the library records around runs of
-    MVM_RUN consecutive launches)."""
-    st = torch.cuda.current_stream()
-    run_steps(eng, dframes, bank, warmup, st)
-    torch.cuda.synchronize()
-    n_launch = (steps + bank - 1) // bank
-    ev = []
-    if path == "persistent":
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(n_launch)]
-    else:
-        eng.mvm_timing(0, steps, MVM_RUN)
-    t0 = time.perf_counter()
-    done = 0
-    for i in range(n_launch):
-        k = min(bank, steps - done)
-        if ev:
-            ev[i][0].record(st)
-        eng.process_frames(0, dframes, k, stream=st)
-        if ev:
-            ev[i][1].record(st)
-        done += k
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    if ev:
-        full = [a.elapsed_time(b) / 1e3 for a, b in ev[:steps // bank]]
-        return dt, (sum(full) / len(full) if full else None), len(full), bank
-    n, tot = eng.mvm_timing_read(0)
-    eng.mvm_timing(0, 0, 1)
-    return dt, (tot / n if n else None), n, 1
+STEADY_LATE_US = 5.0
 
 
-def mvm_timing(torch, eng, n_iter=200, cold=False):
+def latency_stats(samples):
+    """Statistics of one stream's pacer samples: host latency (last chunk handed
+    over -> commands seen), the device part, the latency from the last chunk
+    that completes a column block, the paper's b)-style steady subset (frames
+    whose first and last chunks the pacer handed over within STEADY_LATE_US of
+    its usual lateness, the median: the last chunks of all sensors fall due
+    together and are copied in one after another), and the pacer's own
+    lateness."""
+    import numpy as np
+    host = samples["host_us"]
+    dev = np.where(samples["dev_us"] >= 0, samples["dev_us"], np.nan)
+    steady = ((samples["late_us"] <= np.median(samples["late_us"]) + STEADY_LATE_US)
+              & (samples["start_late_us"] <= np.median(samples["start_late_us"]) + STEADY_LATE_US))
+    r = _pct(host)
+    r["device"] = _pct(dev)
+    r["from_completing_chunk"] = _pct(samples["complete_us"])
+    r["published_before_last_chunk"] = int((samples["dev_us"] < 0).sum())
+    r["steady_subset"] = _pct(host[steady])
+    r["pacer_late_us"] = {"last_chunk": _pct(samples["late_us"]),
+                          "first_chunk": _pct(samples["start_late_us"])}
+    return r
+
+
+def rnd(d):
+    if isinstance(d, dict):
+        return {k: rnd(v) for k, v in d.items()}
+    if isinstance(d, float):
+        return round(d, 3)
+    return d
+
+
+def serve(eng, data, n_frames, warmup, first=0, switch=None, zero_copy=False, insts=None):
+    """Paced serving run of every instance (or `insts`) through the library's
+    pacer; returns per instance the latency statistics."""
+    insts = list(range(len(data))) if insts is None else insts
+    streams = [(k, data[i]["frames"]) for k, i in enumerate(insts)]
+    s = eng.pace(streams, n_frames + warmup, warmup=warmup, period_s=PERIOD_S,
+                 readout_s=READOUT_S, first_frame=first, zero_copy=zero_copy, switch=switch)
+    return [latency_stats(s[k]) for k in range(len(insts))]
+
+
+def mvm_timing(torch, eng, n_iter=200, cold=False, inst=0):
     """Average MVM kernel duration (s) from HIP events on the launch stream.
 
     warm: n_iter back-to-back launches between two events.  cold: before each
@@ -211,13 +213,13 @@ def mvm_timing(torch, eng, n_iter=200, cold=False):
     launch is bracketed by its own events."""
     st = torch.cuda.current_stream()
     if not cold:
-        eng.run_mvm(0, 10, stream=st)
+        eng.run_mvm(inst, 10, stream=st)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(st)
-        eng.run_mvm(0, n_iter, stream=st)
+        eng.run_mvm(inst, n_iter, stream=st)
         b.record(st)
         torch.cuda.synchronize()
-        return a.elapsed_time(b) / 1e3 / n_iter
+        return a.elapsed_time(b) / 1e3 / n_iter, n_iter
     flush = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
     sink = torch.empty((), dtype=torch.float32, device="cuda")
     tot = 0.0
@@ -226,334 +228,24 @@ def mvm_timing(torch, eng, n_iter=200, cold=False):
         torch.sum(flush, dim=0, out=sink)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(st)
-        eng.run_mvm(0, 1, stream=st)
+        eng.run_mvm(inst, 1, stream=st)
         b.record(st)
         torch.cuda.synchronize()
         tot += a.elapsed_time(b) / 1e3
     del flush
-    return tot / n
+    return tot / n, n
 
 
-def _pct(v):
-    import numpy as np
-    v = np.asarray(v, dtype=np.float64)
-    v = v[~np.isnan(v)]
-    return {"p50": float(np.percentile(v, 50)), "p99": float(np.percentile(v, 99)),
-            "mean": float(v.mean()), "rms_jitter": float(v.std()), "max": float(v.max())}
-
-
-def serving_latency(eng, streams, n_frames, warmup=100, period_s=2e-3, readout_s=1.5e-3,
-                    switch=None, zero_copy=False, swap=None, telemetry=None):
-    """Paced serving loop from host memory for one or more instances of one
-    engine, every sensor read out in parallel: chunk c of each sensor of an
-    instance with n chunks is delivered (c + 1) * readout / n after the frame
-    start.  streams: [(instance index, per-sensor frame banks)].  switch:
-    (instance index, frame, gain, leak) applied through the API before that
-    frame.  Returns per instance: host latency (last chunk submitted -> commands
-    seen on the host) and the device part (the loop's own clock from the
-    sentinel seeing the last chunk to the commands being published).
-    zero_copy: chunks written in place into the lent ring slot (rtc_acquire_chunk,
-    rtc_commit_chunk) instead of copied in by rtc_submit_pixel_chunk.
-    swap: (instance index, frame, R, M): a second matrix set staged by another
-    host thread from that frame on (rtc_stage_matrices, while frames run) and
-    swapped in (rtc_swap_matrices) at the first frame start after the staging
-    returned; adds per-phase latency statistics of that instance.
-    telemetry: (decimation, slots): every instance streams slopes, counts and
-    commands into its telemetry ring, drained by a reader thread per instance
-    (rtc_telemetry_next) while frames run."""
-    import threading
-    plan = []
-    for idx, banks in streams:
-        info = eng.infos[idx]
-        nw = info["n_wfs"]
-        n_ch = [eng.n_chunks(idx, w) for w in range(nw)]
-        for w in range(nw):
-            for c in range(n_ch[w]):
-                r0, r1 = eng.chunk_rows(idx, w, c)
-                plan.append(((c + 1) * readout_s / n_ch[w], idx, w, c, r0, r1))
-    plan.sort(key=lambda x: (x[0], x[1], x[2]))
-    host = {idx: [] for idx, _ in streams}
-    dev = {idx: [] for idx, _ in streams}
-    fno = []
-    banks = dict(streams)
-    sw = {}
-    readers, tel_stop, tel_got = [], threading.Event(), {}
-    if telemetry is not None:
-        for idx, _ in streams:
-            eng.telemetry_enable(idx, telemetry[0], telemetry[1])
-            tel_got[idx] = [0, 0]
-
-            def drain_tel(idx=idx):
-                while not tel_stop.is_set():
-                    try:
-                        _, _, _, ti = eng.telemetry_next(idx, timeout_s=0.05)
-                    except Exception:
-                        continue
-                    tel_got[idx][0] += 1
-                    tel_got[idx][1] += ti["lost"]
-            th_t = threading.Thread(target=drain_tel)
-            th_t.start()
-            readers.append(th_t)
-    t_next = time.perf_counter()
-    for f in range(n_frames + warmup):
-        if switch is not None and f == switch[1]:
-            eng.set_params(switch[0], switch[2], switch[3])
-        if swap is not None and f == swap[1]:
-            def stage():
-                t0 = time.perf_counter()
-                eng.stage_matrices(swap[0], swap[2], M=swap[3])
-                sw["stage_s"] = time.perf_counter() - t0
-            th = threading.Thread(target=stage)
-            th.start()
-        if swap is not None and f > swap[1] and "f_eff" not in sw and not th.is_alive():
-            th.join()
-            sw["f_eff"] = eng.swap_matrices(swap[0])
-        t_frame = t_next
-        for t_c, idx, w, c, r0, r1 in plan:
-            while time.perf_counter() < t_frame + t_c:
-                pass
-            bank = banks[idx][w]
-            if zero_copy:
-                eng.acquire_chunk(idx, w, f, c)[...] = bank[f % bank.shape[0]][r0:r1]
-                eng.commit_chunk(idx, w, f, c)
-            else:
-                eng.submit_chunk(idx, w, f, c, bank[f % bank.shape[0]][r0:r1])
-        for idx, _ in streams:
-            _, info = eng.wait_commands(idx, f, timeout_s=5.0)
-            if f >= warmup:
-                host[idx].append((info["t_ready_ns"] - info["t_last_chunk_ns"]) / 1e3)
-                # a frame published before its last chunk arrived (its last rows
-                # hold no pixel it needs) counts as 0
-                dev[idx].append(max(0, info["dev_ticks_cmd"] - info["dev_ticks_start"]) * 0.01
-                                if info["dev_ticks_start"] else float("nan"))
-        if f >= warmup:
-            fno.append(f)
-        t_next = t_frame + period_s
-    if swap is not None and "f_eff" not in sw:
-        th.join()
-        raise RuntimeError("the staged matrices were not swapped in before the last frame")
-    if telemetry is not None:
-        time.sleep(0.1)
-        tel_stop.set()
-        for th_t in readers:
-            th_t.join()
-        for idx, _ in streams:
-            eng.telemetry_enable(idx, 1, 0)
-    out = {}
-    for idx, _ in streams:
-        r = _pct(host[idx])
-        r["frames"] = len(host[idx])
-        r["device"] = _pct(dev[idx])
-        if telemetry is not None:
-            r["telemetry"] = {"decimation": telemetry[0], "slots": telemetry[1],
-                              "records_read": tel_got[idx][0], "records_lost": tel_got[idx][1]}
-        if swap is not None and swap[0] == idx:
-            import numpy as np
-            fa, h, d = np.asarray(fno), np.asarray(host[idx]), np.asarray(dev[idx])
-            fe = sw["f_eff"]
-            phases = {"before_stage": fa < swap[1],
-                      "during_stage": (fa >= swap[1]) & (fa < fe),
-                      "first_20_after_swap": (fa >= fe) & (fa < fe + 20),
-                      "after_swap": fa >= fe}
-            r["swap"] = {"stage_s": sw["stage_s"], "stage_frame": swap[1], "f_eff": fe}
-            for k, m in phases.items():
-                if m.any():
-                    r["swap"][k] = {"frames": int(m.sum()), "host": _pct(h[m]),
-                                    "device": _pct(d[m])}
-        out[idx] = r
-    return out
-
-
-SERVING_NOTE = {"pacing": "500 Hz frames, every sensor's chunks spread over a 1.5 ms readout",
-                "host": "last chunk submitted (host memcpy into the pinned ring, doorbell) -> "
-                        "commands seen in the pinned mailbox by the host",
-                "device": "device clock (100 MHz): the loop's sentinel seeing the frame's last "
-                          "chunk -> the last tile's commands published"}
-
-
-def latency_suite(torch, rtc, dtypes, n_frames, log):
-    """ELT-scale serving cases in one persistent launch each: MCAO (6 LGS SH 74x74 + 3 NGS
-    2x2, POLC) and LTAO (6 LGS SH 68x68 + 1 NGS 8x8, POLC, gain and leak switched
-    mid-run) running beside the SCAO SH 74x74 instance of uneven size."""
-    import numpy as np
-    import synth
-    res = {}
-    for name in ("mcao_74", "ltao_68", "mcao_80"):
-        wl = synth.get_workload(name)
-        mats, banks = [], []
-        for i, inst in enumerate(wl.instances):
-            R = synth.control_matrix(wl, i)
-            M = None
-            if inst.polc:
-                na = inst.n_act
-                M = synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na),
-                                          synth.seed_for(wl.index, i, 99, 5), np.float32)
-            fr, cal = [], []
-            for w in range(len(inst.wfs)):
-                f_w, c_w = synth.sensor_inputs(wl, i, w, n=16)
-                fr.append(f_w)
-                cal.append(c_w)
-            mats.append((R, M, cal))
-            banks.append(fr)
-        # the paper-size MCAO's FP32 matrix (1.4 GB) is not one of its storage choices
-        for dtype in [d for d in dtypes if name != "mcao_80" or d != "f32"]:
-            log(f"bench: serving {name} {dtype}")
-            eng = rtc.Engine([(inst, dtype) for inst in wl.instances], ring_depth=4,
-                             mode="persistent")
-            for i, (R, M, cal) in enumerate(mats):
-                eng.load_matrices(i, R, M=M)
-                for w, c in enumerate(cal):
-                    eng.load_calibration(i, w, c.dark, c.flat, c.bg, c.thr, c.ref)
-            switch = None
-            sw_inst = [i for i, inst in enumerate(wl.instances) if inst.switch is not None]
-            if sw_inst:
-                i = sw_inst[0]
-                switch = (i, n_frames // 2 + 100, wl.instances[i].switch[1],
-                          wl.instances[i].switch[2])
-            lat = serving_latency(eng, [(i, banks[i]) for i in range(len(wl.instances))],
-                                  n_frames, switch=switch)
-            if name == "mcao_74" and dtype == dtypes[0]:
-                # the same with slopes, counts and commands of every frame streamed
-                eng.set_state(0, None, None, 0)
-                tel = serving_latency(eng, [(0, banks[0])], n_frames, telemetry=(1, 256))[0]
-                res[f"{name}:{wl.instances[0].name}:{dtype}:telemetry_every_frame"] = {
-                    k: (round(v, 3) if isinstance(v, float) else v) for k, v in tel.items()}
-                log(f"bench: {name} {dtype} with telemetry: p50 {tel['p50']:.1f} "
-                    f"p99 {tel['p99']:.1f} us")
-            eng.close()
-            for i, inst in enumerate(wl.instances):
-                key = f"{name}:{inst.name}:{dtype}"
-                r = lat[i]
-                r.update({"n_act": inst.n_act, "n_wfs": len(inst.wfs), "polc": inst.polc,
-                          "instances_in_launch": len(wl.instances)})
-                if switch is not None and switch[0] == i:
-                    r["gain_leak_switch_at_frame"] = switch[1] - 100
-                res[key] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}
-                log(f"bench: {key}: p50 {r['p50']:.1f} p99 {r['p99']:.1f} "
-                    f"jitter {r['rms_jitter']:.2f} us (device p50 {r['device']['p50']:.1f})")
-        del mats, banks
-    return res
-
-
-def wfs_sweep(torch, rtc, n_frames, log):
-    """Serving latency against sensor size at a constant frame size (the paper's
-    scaling study): Shack-Hartmann 74..110 subapertures across on 800x800 frames
-    (10, 10, 8, 8, 7 px per subaperture) and pyramid 80..120 pupil pixels across
-    on 240x240 frames, each with a 5318-actuator FP32 control matrix."""
-    import numpy as np
-    import synth
-    res = {}
-    points = [("sh", n, synth.ShWfs(nsub=n, px=min(10, 800 // n), obs=0.28, frame_h=800,
-                                    frame_w=800, origin=((800 - n * min(10, 800 // n)) // 2,) * 2))
-              for n in (74, 80, 90, 100, 110)]
-    for p in (80, 90, 100, 110, 120):
-        o0, o1 = (120 - p) // 2, 120 + (120 - p) // 2
-        points.append(("pyr", p, synth.PyrWfs(pupil_px=p, quad_origins=((o0, o0), (o1, o0),
-                                                                        (o0, o1), (o1, o1)))))
-    for i, (kind, n, wfs) in enumerate(points):
-        inst = synth.Instance(f"sweep_{kind}{n}", (wfs,), 5318, ("f32",))
-        wl = synth.Workload(200 + i, inst.name, (inst,), n_frames=n_frames, bank=16)
-        synth.workloads.WORKLOADS[wl.name] = wl
-        try:
-            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
-            R = synth.control_matrix(wl, 0)
-        finally:
-            del synth.workloads.WORKLOADS[wl.name]
-        eng = rtc.Engine([(inst, "f32")], ring_depth=4, mode="persistent")
-        eng.load_matrices(0, R)
-        eng.load_calibration(0, 0, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
-        r = serving_latency(eng, [(0, [fr])], n_frames)[0]
-        eng.close()
-        key = f"{kind}_{n}x{n}"
-        res[key] = {"n_slopes": inst.n_slopes, "n_act": inst.n_act,
-                    "px_per_subap": getattr(wfs, "px", None),
-                    **{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}}
-        log(f"bench: sweep {key}: {inst.n_slopes} slopes, p50 {r['p50']:.1f} p99 {r['p99']:.1f} "
-            f"jitter {r['rms_jitter']:.2f} us (device p50 {r['device']['p50']:.1f})")
-    return res
-
-
-def pyramid_norms(torch, rtc, steps, log):
-    """Per-launch batch frames/s of the 92-pixel pyramid (5318 x 12288 FP32
-    matrix) with local and with global normalisation (the latter adds the
-    pupil-sum kernel before each frame's slopes)."""
-    import dataclasses
-    import synth
-    res = {}
-    base = synth.get_workload("scao_pyr_92")
-    for norm in ("local", "global"):
-        wfs = dataclasses.replace(base.instances[0].wfs[0], norm=norm)
-        inst = dataclasses.replace(base.instances[0], wfs=(wfs,))
-        wl = dataclasses.replace(base, name=f"scao_pyr_92_{norm}", instances=(inst,))
-        synth.workloads.WORKLOADS[wl.name] = wl
-        try:
-            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
-            R = synth.control_matrix(wl, 0)
-        finally:
-            del synth.workloads.WORKLOADS[wl.name]
-        eng = rtc.Engine([(inst, "f32")], mode="stream")
-        eng.load_matrices(0, R)
-        eng.load_calibration(0, 0, cal.dark, cal.flat, cal.bg, cal.thr, cal.ref)
-        d = [torch.from_numpy(fr).cuda()]
-        st = torch.cuda.current_stream()
-        run_steps(eng, d, 16, 64, st)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run_steps(eng, d, 16, steps, st)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        eng.close()
-        res[norm] = {"frames_per_s": round(steps / dt, 1), "n_slopes": inst.n_slopes}
-        log(f"bench: pyramid 92 px {norm} normalisation: {steps / dt:.0f} frames/s")
-    return res
-
-
-# matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
-LARGE_MVM = (("mcao_74", "bf16"), ("mcao_74", "fp8"), ("ltao_68", "f32"), ("ltao_68", "bf16"),
-             ("mcao_80", "bf16"), ("mcao_80", "fp8"))
-
-
-def mvm_large(torch, rtc, log):
-    """The standalone MVM on the MCAO and LTAO matrices (each beyond the Infinity
-    Cache), warm (back to back) and after a 1 GiB read-only cache flush."""
-    import numpy as np
-    import synth
-    res = {}
-    done = {}
-    for name, dtype in LARGE_MVM:
-        wl = synth.get_workload(name)
-        inst = wl.instances[0]
-        if name not in done:
-            done.clear()
-            done[name] = synth.control_matrix(wl, 0)
-        R = done[name]
-        na = inst.n_act
-        M = (synth.gaussian_matrix(na, na, 0.5 / np.sqrt(na), synth.seed_for(wl.index, 0, 99, 5),
-                                   np.float32) if inst.polc else None)
-        eng = rtc.Engine([(inst, dtype)], mode="stream")
-        eng.load_matrices(0, R, M=M)
-        info = eng.infos[0]
-        warm = mvm_timing(torch, eng, n_iter=100)
-        cold = mvm_timing(torch, eng, n_iter=100, cold=True)
-        eng.close()
-        alg = (na * info["n_slopes"] * ELEM[dtype] + 4 * info["n_slopes"] + 4 * na
-               + (4 * na if dtype == "fp8" else 0))
-        r = {"n_act": na, "n_slopes": info["n_slopes"], "alg_bytes": alg,
-             "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9, "warm_frac": alg / warm / 1e9 / HBM_PEAK_GBS,
-             "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9, "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS,
-             # HBM bytes of one warm launch from the committed counter summary
-             "traffic": measured_traffic(name, dtype, "k_mvm")}
-        res[f"{name}:{dtype}"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-        log(f"bench: mvm {name} {dtype}: {alg / 1e6:.0f} MB, warm {warm * 1e6:.1f} us "
-            f"({r['warm_gbs']:.0f} GB/s), cold {cold * 1e6:.1f} us ({r['cold_gbs']:.0f} GB/s)")
-    return res
+def mvm_alg_bytes(inst, n_slopes, dtype):
+    """Bytes the MVM must move: the matrix (+ FP8 row scales), slopes read,
+    partial-free result read and written (command vector)."""
+    return (inst.n_act * n_slopes * ELEM[dtype] + 4 * n_slopes + 8 * inst.n_act
+            + (4 * inst.n_act if dtype == "fp8" else 0))
 
 
 def box_reference(torch, reps=10):
     """HBM reference of this particular box: a plain 512 MiB device-to-device
-    copy (read + write bytes per second, median of `reps`).  MI355X boxes in one
-    pool have shown different sustained bandwidths for the same code, so every
-    kernel figure is reported beside this one."""
+    copy (read + write bytes per second, median of `reps`)."""
     src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     st = torch.cuda.current_stream()
@@ -575,53 +267,313 @@ def box_reference(torch, reps=10):
             "what": "median of 10 device-to-device copies of 512 MiB (read + write)"}
 
 
-def cpu_baseline(inst, frames, cals, R, M, budget_s=12.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, data, budget_s=12.0):
+    """The CPU oracle on the same workload: every instance's frame per step,
+    FP64 matrices (binary32 calibration), timed per frame at all host threads
+    and at one thread (threadpoolctl limits numpy's BLAS)."""
     import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
-    Rm = np.asarray(R, np.float64)
-    n = 0
+    from threadpoolctl import threadpool_info, threadpool_limits
+    mats = [(np.asarray(d["R"], np.float64), None if d["M"] is None else d["M"].astype(np.float64))
+            for d in data]
+
+    def run(limit):
+        times = []
+        t_end = time.perf_counter() + budget_s
+        f = 0
+        with threadpool_limits(limits=limit):
+            used = max([x.get("num_threads", 1) for x in threadpool_info()] + [1])
+            while time.perf_counter() < t_end or len(times) < 3:
+                t0 = time.perf_counter()
+                for i, inst in enumerate(wl.instances):
+                    fr = data[i]["frames"]
+                    oracle.run(inst, [b[f % b.shape[0]:f % b.shape[0] + 1] for b in fr],
+                               data[i]["cals"], mats[i][0], 1, M=mats[i][1])
+                times.append((time.perf_counter() - t0) * 1e6)
+                f += 1
+        t = np.asarray(times)
+        return {"median_us": float(np.median(t)), "p99_us": float(np.percentile(t, 99)),
+                "frames": int(t.size), "threads": int(used)}
+    allc = run(None)
+    one = run(1)
+    return {"value": allc["median_us"], "unit": "us", "cores": allc["threads"], "kind": "oracle",
+            "sample": f"{allc['frames']} frames of the same workload (LTAO and SCAO instances, "
+                      f"one frame each per step) through the FP64 numpy oracle (binary32 "
+                      f"calibration), per-frame median over ~{budget_s:.0f} s; no pacing",
+            "p99": allc["p99_us"], "one_thread": one, "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count()}
+
+
+# matrices larger than the 256 MB Infinity Cache: their MVM rate is an HBM rate
+LARGE_MVM = (("ltao_68", "f32"), ("ltao_68", "bf16"), ("ltao_68", "fp8"), ("mcao_74", "bf16"),
+             ("mcao_74", "fp8"), ("mcao_80", "bf16"), ("mcao_80", "fp8"))
+
+
+def mvm_large(torch, rtc, log, cache):
+    """The standalone MVM on the LTAO and MCAO matrices, warm (back to back) and
+    after a 1 GiB read-only cache flush."""
+    import synth
+    res = {}
+    for name, dtype in LARGE_MVM:
+        wl = synth.get_workload(name)
+        inst = wl.instances[0]
+        if name not in cache:
+            cache.clear()
+            cache[name] = (synth.control_matrix(wl, 0), polc_matrix_for(wl, 0))
+        R, M = cache[name]
+        eng = rtc.Engine([(inst, dtype)], mode="stream")
+        eng.load_matrices(0, R, M=M)
+        info = eng.infos[0]
+        warm, _ = mvm_timing(torch, eng, n_iter=100)
+        cold, _ = mvm_timing(torch, eng, n_iter=100, cold=True)
+        eng.close()
+        alg = mvm_alg_bytes(inst, info["n_slopes"], dtype)
+        r = {"n_act": inst.n_act, "n_slopes": info["n_slopes"], "alg_bytes": alg,
+             "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9,
+             "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9,
+             "cold_frac": alg / cold / 1e9 / HBM_PEAK_GBS,
+             "traffic": measured_traffic(name, dtype, "k_mvm")}
+        res[f"{name}:{dtype}"] = rnd(r)
+        log(f"bench: mvm {name} {dtype}: {alg / 1e6:.0f} MB, warm {warm * 1e6:.1f} us "
+            f"({r['warm_gbs']:.0f} GB/s), cold {cold * 1e6:.1f} us ({r['cold_gbs']:.0f} GB/s, "
+            f"{r['cold_frac']:.3f} of peak)")
+    return res
+
+
+def batch_throughput(torch, eng, frames, n, warmup, inst=0, timed_launches=False):
+    """Frames/s of the batch path over device-resident frames, and (per-launch
+    path) the average k_mvm_next launch from the library's HIP events."""
+    st = torch.cuda.current_stream()
+    bank = frames[0].shape[0]
+    def run(k):
+        done = 0
+        while done < k:
+            m = min(bank, k - done)
+            eng.process_frames(inst, frames, m, stream=st)
+            done += m
+    run(warmup)
+    torch.cuda.synchronize()
+    if timed_launches:
+        eng.mvm_timing(inst, n, MVM_RUN)
     t0 = time.perf_counter()
-    while True:
-        oracle.run(inst, [f[n % f.shape[0]:n % f.shape[0] + 1] for f in frames], cals, Rm, 1,
-                   M=None if M is None else M.astype(np.float64))
-        n += 1
-        if time.perf_counter() - t0 > budget_s and n >= 3:
-            break
+    run(n)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{n} frames of the same workload through the FP64 numpy oracle "
-                      f"(binary32 calibration, FP64 slopes/MVM/integrator), {dt:.1f} s"}
+    r = {"frames_per_s": n / dt}
+    if timed_launches:
+        k, tot = eng.mvm_timing_read(inst)
+        eng.mvm_timing(inst, 0, 1)
+        if k:
+            r["k_mvm_next_us"] = tot / k * 1e3
+            r["k_mvm_next_launches_timed"] = k
+    return r
+
+
+def scao_extras(torch, rtc, log):
+    """The 74x74 SCAO configuration: per-launch batch throughput and the MVM
+    warm / cold.  Its matrices (169 / 85 / 42 MB) fit the 256 MB Infinity
+    Cache, so the warm MVM rates are cache rates, not HBM rates (inferred from
+    timing: warm above the box's copy rate, cold well below)."""
+    wl, data = build_inputs("scao_sh_74", 64)
+    inst = wl.instances[0]
+    dfr = [torch.from_numpy(f).cuda() for f in data[0]["frames"]]
+    res = {"infinity_cache_resident": True,
+           "what": "matrix fits the 256 MB Infinity Cache: warm figures are cache rates"}
+    for dtype in ("f32", "bf16", "fp8"):
+        eng = load_engine(rtc, wl, data, dtype, "stream")
+        info = eng.infos[0]
+        r = batch_throughput(torch, eng, dfr, 2000, 200, timed_launches=True)
+        warm, _ = mvm_timing(torch, eng)
+        cold, _ = mvm_timing(torch, eng, cold=True)
+        alg = mvm_alg_bytes(inst, info["n_slopes"], dtype)
+        r.update({"mvm_alg_bytes": alg, "mvm_warm_us": warm * 1e6,
+                  "mvm_warm_gbs_cache": alg / warm / 1e9, "mvm_cold_us": cold * 1e6,
+                  "mvm_cold_gbs": alg / cold / 1e9})
+        eng.close()
+        eng = load_engine(rtc, wl, data, dtype, "persistent")
+        r["frame_loop_batch"] = batch_throughput(torch, eng, dfr, 2000, 200)
+        eng.set_state(0, None, None, 0)        # serving restarts at frame 0
+        lat = serve(eng, data, 1000, 100)[0]
+        eng.set_state(0, None, None, 0)
+        r["serving_latency_us"] = lat
+        r["serving_latency_zero_copy_us"] = serve(eng, data, 1000, 100, zero_copy=True)[0]
+        eng.close()
+        res[dtype] = rnd(r)
+        log(f"bench: scao_sh_74 {dtype}: {r['frames_per_s']:.0f} frames/s per-launch, "
+            f"k_mvm_next {r.get('k_mvm_next_us', 0):.1f} us, serving p50 {lat['p50']:.1f} "
+            f"p99 {lat['p99']:.1f} us")
+    return res
+
+
+def telemetry_and_swap(torch, rtc, log):
+    """SCAO FP32 serving with telemetry of every frame drained by a host thread,
+    and with a second control matrix staged by another thread while frames run
+    and swapped in at a frame boundary."""
+    import numpy as np
+    import synth
+    wl, data = build_inputs("scao_sh_74", 64)
+    inst = wl.instances[0]
+    res = {}
+    eng = load_engine(rtc, wl, data, "f32", "persistent")
+    eng.telemetry_enable(0, 1, 256)
+    got, stop = [0, 0], threading.Event()
+
+    def drain():
+        while not stop.is_set():
+            try:
+                _, _, _, ti = eng.telemetry_next(0, timeout_s=0.05)
+            except Exception:
+                continue
+            got[0] += 1
+            got[1] += ti["lost"]
+    th = threading.Thread(target=drain)
+    th.start()
+    lat = serve(eng, data, 1000, 100)[0]
+    time.sleep(0.1)
+    stop.set()
+    th.join()
+    eng.telemetry_enable(0, 1, 0)
+    lat["telemetry"] = {"decimation": 1, "slots": 256, "records_read": got[0],
+                        "records_lost": got[1]}
+    res["telemetry_every_frame"] = rnd(lat)
+    log(f"bench: scao f32 with telemetry: p50 {lat['p50']:.1f} p99 {lat['p99']:.1f} us")
+    # matrix swap: staging starts 0.2 s into the run, the swap follows at once
+    eng.set_state(0, None, None, 0)
+    R2 = synth.gaussian_matrix(inst.n_act, inst.n_slopes, 1.0 / np.sqrt(inst.n_slopes),
+                               synth.seed_for(wl.index, 0, 77, 1), np.float32)
+    sw = {}
+
+    def stage():
+        time.sleep(0.3)
+        sw["t0"] = time.perf_counter()
+        eng.stage_matrices(0, R2)
+        sw["t1"] = time.perf_counter()
+        sw["f_eff"] = eng.swap_matrices(0)
+    t_run = time.perf_counter()
+    th = threading.Thread(target=stage)
+    th.start()
+    s = eng.pace([(0, data[0]["frames"])], 1100, warmup=0, period_s=PERIOD_S,
+                 readout_s=READOUT_S)[0]
+    th.join()
+    eng.close()
+    fa = s["frame"].astype(np.int64)
+    fs = int((sw["t0"] - t_run) / PERIOD_S)
+    fe = sw["f_eff"]
+    r = {"stage_s": sw["t1"] - sw["t0"], "stage_frame_approx": fs, "f_eff": fe}
+    for k, m in {"before_stage": (fa >= 100) & (fa < fs), "during_stage": (fa >= fs) & (fa < fe),
+                 "first_20_after_swap": (fa >= fe) & (fa < fe + 20), "after_swap": fa >= fe}.items():
+        if m.any():
+            r[k] = {"host": _pct(s["host_us"][m]),
+                    "device": _pct(np.where(s["dev_us"][m] >= 0, s["dev_us"][m], np.nan))}
+    res["matrix_swap"] = rnd(r)
+    log(f"bench: matrix swap: staged in {r['stage_s']:.3f} s, effective frame {fe}")
+    return res
+
+
+def serving_suite(torch, rtc, log, frames_n):
+    """MCAO serving (74x74 and the paper's 80x80 LGS), BF16 and FP8."""
+    res = {}
+    for name in ("mcao_74", "mcao_80"):
+        wl, data = build_inputs(name, 16)
+        for dtype in ("bf16", "fp8"):
+            eng = load_engine(rtc, wl, data, dtype, "persistent")
+            lat = serve(eng, data, frames_n, 100)[0]
+            eng.close()
+            res[f"{name}:{dtype}"] = rnd(lat)
+            log(f"bench: serving {name} {dtype}: p50 {lat['p50']:.1f} p99 {lat['p99']:.1f} "
+                f"jitter {lat['rms_jitter']:.2f} us (device p50 {lat['device']['p50']:.1f})")
+        del data
+    return res
+
+
+def wfs_sweep(torch, rtc, n_frames, log):
+    """Serving latency against sensor size at a constant frame size (the paper's
+    scaling study): Shack-Hartmann 74..110 subapertures across on 800x800 frames
+    (10, 10, 8, 8, 7 px per subaperture) and pyramid 80..120 pupil pixels across
+    on 240x240 frames, each with a 5318-actuator FP32 control matrix.  For the
+    small pyramid pupils the frame's last chunks hold no pupil pixel, so the
+    commands are out before they arrive: latency is also reported from the last
+    chunk that completes a column block."""
+    import synth
+    res = {}
+    points = [("sh", n, synth.ShWfs(nsub=n, px=min(10, 800 // n), obs=0.28, frame_h=800,
+                                    frame_w=800, origin=((800 - n * min(10, 800 // n)) // 2,) * 2))
+              for n in (74, 80, 90, 100, 110)]
+    for p in (80, 90, 100, 110, 120):
+        o0, o1 = (120 - p) // 2, 120 + (120 - p) // 2
+        points.append(("pyr", p, synth.PyrWfs(pupil_px=p, quad_origins=((o0, o0), (o1, o0),
+                                                                        (o0, o1), (o1, o1)))))
+    for i, (kind, n, wfs) in enumerate(points):
+        inst = synth.Instance(f"sweep_{kind}{n}", (wfs,), 5318, ("f32",))
+        wl = synth.Workload(200 + i, inst.name, (inst,), n_frames=n_frames, bank=16)
+        synth.workloads.WORKLOADS[wl.name] = wl
+        try:
+            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
+            R = synth.control_matrix(wl, 0)
+        finally:
+            del synth.workloads.WORKLOADS[wl.name]
+        data = [{"R": R, "M": None, "frames": [fr], "cals": [cal]}]
+        eng = load_engine(rtc, wl, data, "f32", "persistent")
+        r = serve(eng, data, n_frames, 100)[0]
+        eng.close()
+        key = f"{kind}_{n}x{n}"
+        res[key] = {"n_slopes": inst.n_slopes, "n_act": inst.n_act,
+                    "px_per_subap": getattr(wfs, "px", None), **rnd(r)}
+        log(f"bench: sweep {key}: {inst.n_slopes} slopes, p50 {r['p50']:.1f} p99 {r['p99']:.1f} "
+            f"us, from the completing chunk p50 {r['from_completing_chunk']['p50']:.1f} us")
+    return res
+
+
+def pyramid_norms(torch, rtc, steps, log):
+    """Per-launch batch frames/s of the 92-pixel pyramid (5318 x 12288 FP32
+    matrix) with local and with global normalisation."""
+    import dataclasses
+    import synth
+    res = {}
+    base = synth.get_workload("scao_pyr_92")
+    for norm in ("local", "global"):
+        wfs = dataclasses.replace(base.instances[0].wfs[0], norm=norm)
+        inst = dataclasses.replace(base.instances[0], wfs=(wfs,))
+        wl = dataclasses.replace(base, name=f"scao_pyr_92_{norm}", instances=(inst,))
+        synth.workloads.WORKLOADS[wl.name] = wl
+        try:
+            fr, cal = synth.sensor_inputs(wl, 0, 0, n=16)
+            R = synth.control_matrix(wl, 0)
+        finally:
+            del synth.workloads.WORKLOADS[wl.name]
+        data = [{"R": R, "M": None, "frames": [fr], "cals": [cal]}]
+        eng = load_engine(rtc, wl, data, "f32", "stream")
+        r = batch_throughput(torch, eng, [torch.from_numpy(fr).cuda()], steps, 64)
+        eng.close()
+        res[norm] = {"frames_per_s": round(r["frames_per_s"], 1), "n_slopes": inst.n_slopes}
+        log(f"bench: pyramid 92 px {norm} normalisation: {r['frames_per_s']:.0f} frames/s")
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", default="scao_sh_74")
-    ap.add_argument("--dtype", default="f32")
-    ap.add_argument("--path", default="stream", choices=("stream", "persistent"))
-    ap.add_argument("--variants", default="bf16,fp8")
-    ap.add_argument("--bank", type=int, default=64)
-    ap.add_argument("--latency-frames", type=int, default=1000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-latency", action="store_true")
-    ap.add_argument("--no-latency-suite", action="store_true",
-                    help="skip the MCAO / LTAO+SCAO serving cases")
-    ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the serving-latency sweep over sensor sizes")
-    ap.add_argument("--sweep-frames", type=int, default=500)
-    ap.add_argument("--no-mvm-large", action="store_true",
-                    help="skip the standalone MVM on the MCAO / LTAO matrices")
-    ap.add_argument("--mvm-large-only", action="store_true",
-                    help="only the standalone MVM on the MCAO / LTAO matrices (for profiling)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--frames-per-step", type=int, default=50)
+    ap.add_argument("--dtype", default="f32", choices=("f32", "bf16", "fp8"))
     ap.add_argument("--quick", action="store_true",
-                    help="the chosen path and storage type only (for profiling)")
+                    help="the headline, its roofline and the CPU baseline only")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra-frames", type=int, default=1000,
+                    help="frames per serving extra")
+    ap.add_argument("--mvm-large-only", action="store_true",
+                    help="only the standalone MVM on the matrices beyond the cache (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -630,16 +582,13 @@ def main():
               "controller's hot path runs on a single MI355X", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_1903_01852_amd import rtc
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     rtc.lib()
-
-    log(f"bench: building inputs for {args.workload} (bank {args.bank})")
-    wl, inst, frames, cals, R, M = build_inputs(args.workload, args.bank)
-    dframes = [torch.from_numpy(f).cuda() for f in frames]
 
     if args.copy_probe:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
@@ -650,136 +599,107 @@ def main():
         log(f"bench: copy probe: 5 x {src.numel() * 4} bytes read and written")
         del src, dst
 
-    def mvm_alg_bytes(info, dtype):
-        return (inst.n_act * info["n_slopes"] * ELEM[dtype] + 4 * info["n_slopes"]
-                + 4 * inst.n_act + (4 * inst.n_act if dtype == "fp8" else 0))
-
-    def run_path(eng, dtype, path):
-        info = eng.infos[0]
-        dt, kern_s, n_timed, per = throughput(torch, eng, dframes, args.bank, args.steps,
-                                              args.warmup, path)
-        per_frame = alg_bytes_per_frame(inst, info, dtype)
-        res = {"frames_per_s": args.steps / dt, "ms_per_step": dt * 1e3 / args.steps,
-               "alg_bytes_per_frame": per_frame}
-        if kern_s:
-            kb = (per_frame * per if path == "persistent"
-                  else mvm_next_alg_bytes(inst, info, dtype))
-            res.update({"kernel": ("k_frame_loop" if path == "persistent"
-                                   else f"k_mvm_next<{dtype}>"),
-                        "kernel_us": kern_s * 1e6, "kernel_launches_timed": n_timed,
-                        "kernel_alg_bytes": kb, "kernel_gbs": kb / kern_s / 1e9})
-        log(f"bench: {dtype} {path}: {res}")
-        return res
-
-    def mvm_standalone(eng, dtype):
-        info = eng.infos[0]
-        warm = mvm_timing(torch, eng)
-        cold = mvm_timing(torch, eng, cold=True)
-        alg = mvm_alg_bytes(info, dtype)
-        return {"alg_bytes": alg, "cm_bytes_stored": info["cm_bytes"],
-                "warm_us": warm * 1e6, "warm_gbs": alg / warm / 1e9,
-                "cold_us": cold * 1e6, "cold_gbs": alg / cold / 1e9}
-
     ref = box_reference(torch)
     log(f"bench: box reference {ref}")
     if args.mvm_large_only:
-        print(json.dumps({"box_reference": ref, "mvm_large": mvm_large(torch, rtc, log)}), flush=True)
+        print(json.dumps({"box_reference": ref, "mvm_large": mvm_large(torch, rtc, log, {})}),
+              flush=True)
         return
 
-    dtypes = [args.dtype] + ([] if args.quick else
-                             [v for v in args.variants.split(",") if v and v != args.dtype])
-    paths = {"stream": {}, "persistent": {}}
-    mvm = {}
-    latency = {}
-    for dtype in dtypes:
-        for path in ("stream", "persistent"):
-            if args.quick and path != args.path:
-                continue
-            eng = make_engine(rtc, inst, dtype, cals, R, M, mode=path)
-            paths[path][dtype] = run_path(eng, dtype, path)
-            if path == "stream":
-                mvm[dtype] = mvm_standalone(eng, dtype)
-                log(f"bench: {dtype} mvm: {mvm[dtype]}")
-            elif not args.quick and not args.no_latency:
-                eng.set_state(0, None, None, 0)
-                latency[dtype] = serving_latency(eng, [(0, frames)], args.latency_frames)[0]
-                eng.set_state(0, None, None, 0)
-                latency[dtype]["zero_copy"] = serving_latency(
-                    eng, [(0, frames)], args.latency_frames, zero_copy=True)[0]
-                if dtype == args.dtype:
-                    # slopes, counts and commands of every frame streamed to the host
-                    eng.set_state(0, None, None, 0)
-                    latency[dtype]["telemetry_every_frame"] = serving_latency(
-                        eng, [(0, frames)], args.latency_frames, telemetry=(1, 256))[0]
-                    # a second control matrix staged and swapped in while frames run
-                    import numpy as np
-                    import synth
-                    eng.set_state(0, None, None, 0)
-                    R2 = synth.gaussian_matrix(inst.n_act, R.shape[1], 1.0 / np.sqrt(R.shape[1]),
-                                               synth.seed_for(wl.index, 0, 77, 1), np.float32)
-                    M2 = None if M is None else synth.gaussian_matrix(
-                        inst.n_act, inst.n_act, 0.5 / np.sqrt(inst.n_act),
-                        synth.seed_for(wl.index, 0, 77, 2), np.float32)
-                    latency[dtype]["matrix_swap"] = serving_latency(
-                        eng, [(0, frames)], args.latency_frames,
-                        swap=(0, 100 + args.latency_frames // 5, R2, M2))[0]["swap"]
-                log(f"bench: {dtype} latency: {latency[dtype]}")
+    # ---------------------------------------------------------------- headline
+    name = "ltao_68"
+    log(f"bench: building inputs for {name}")
+    wl, data = build_inputs(name, 64)
+    ltao = wl.instances[0]
+    fps = args.frames_per_step
+    eng = load_engine(rtc, wl, data, args.dtype, "persistent")
+    infos = eng.infos
+    sw_run = args.steps * fps // 2
+    switch = (0, sw_run, ltao.switch[1], ltao.switch[2])
+    log(f"bench: {args.warmup} warm-up steps of {fps} frames")
+    serve(eng, data, args.warmup * fps, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = eng.pace([(k, d["frames"]) for k, d in enumerate(data)], args.steps * fps, warmup=0,
+                 period_s=PERIOD_S, readout_s=READOUT_S, first_frame=args.warmup * fps,
+                 switch=switch)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat = {inst.name: latency_stats(s[k]) for k, inst in enumerate(wl.instances)}
+    eng.close()
+    head = lat[ltao.name]
+    log(f"bench: {name} {args.dtype}: LTAO p50 {head['p50']:.1f} p99 {head['p99']:.1f} "
+        f"jitter {head['rms_jitter']:.2f} us (device p50 {head['device']['p50']:.1f}); "
+        f"SCAO p50 {lat['scao_sh']['p50']:.1f} us; {dt:.2f} s")
+
+    # ---------------------------------------------------------------- roofline
+    # the LTAO matrix alone, cold: every launch after a 1 GiB cache flush
+    eng = load_engine(rtc, wl, data, args.dtype, "stream", only=0)
+    n_slopes = eng.infos[0]["n_slopes"]
+    cold, n_cold = mvm_timing(torch, eng, n_iter=200, cold=True)
+    extras = {}
+    if not args.quick:
+        # back-to-back launches and the per-launch batch path (inputs resident
+        # in HBM): extras, outside the launches the roofline averages
+        warm, _ = mvm_timing(torch, eng, n_iter=100)
+        thr = batch_throughput(torch, eng,
+                               [torch.from_numpy(f).cuda() for f in data[0]["frames"]], 256, 32)
+        extras["ltao_mvm_warm_back_to_back_us"] = round(warm * 1e6, 3)
+        extras["ltao_batch_throughput"] = rnd({**thr, "what": "LTAO instance alone, per-launch "
+                                               "batch path over device-resident frames"})
+    eng.close()
+    alg = mvm_alg_bytes(ltao, n_slopes, args.dtype)
+    roof = {"bound": "hbm", "achieved": round(alg / cold / 1e9, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(alg / cold / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name, args.dtype, "k_mvm"),
+            "kernel": f"k_mvm<{args.dtype}>",
+            "what": f"split-K MVM on the LTAO matrix {ltao.n_act} x {n_slopes} "
+                    f"({alg / 1e6:.0f} MB, beyond the 256 MB Infinity Cache), each launch after "
+                    "a 1 GiB read-only cache flush",
+            "avg_launch_us": round(cold * 1e6, 3), "launches_timed": n_cold,
+            "algorithmic_bytes_per_launch": alg}
+    log(f"bench: roofline {roof}")
+
+    if not args.quick:
+        for dt2 in [d for d in ("f32", "bf16", "fp8") if d != args.dtype]:
+            eng = load_engine(rtc, wl, data, dt2, "persistent")
+            l2 = serve(eng, data, args.extra_frames, 100,
+                       switch=(0, args.extra_frames // 2 + 100, ltao.switch[1], ltao.switch[2]))
             eng.close()
-
-    large = None
-    if not args.quick and not args.no_mvm_large:
-        large = mvm_large(torch, rtc, log)
-
-    suite = None
-    if not args.quick and not args.no_latency and not args.no_latency_suite:
-        suite = latency_suite(torch, rtc, dtypes, args.latency_frames, log)
-
-    sweep = None
-    if not args.quick and not args.no_latency and not args.no_sweep:
-        sweep = wfs_sweep(torch, rtc, args.sweep_frames, log)
-    pyr_norm = None if args.quick else pyramid_norms(torch, rtc, 2000, log)
-
+            extras[f"{name}:{dt2}"] = {inst.name: rnd(l2[k]) for k, inst in enumerate(wl.instances)}
+            log(f"bench: {name} {dt2}: LTAO p50 {l2[0]['p50']:.1f} p99 {l2[0]['p99']:.1f} us")
     cpu = None
-    if not args.quick and not args.no_cpu_baseline:
+    if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline")
-        cpu = cpu_baseline(inst, frames, cals, R, M)
-
-    main_res = paths[args.path][args.dtype]
-    achieved = main_res["kernel_gbs"]
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(args.workload, args.dtype, main_res["kernel"]),
-            "kernel": main_res["kernel"],
-            "avg_launch_us": round(main_res["kernel_us"], 3),
-            "launches_timed": main_res["kernel_launches_timed"],
-            "algorithmic_bytes_per_launch": main_res["kernel_alg_bytes"]}
-
-    def rnd(d):
-        return {k: (round(v, 3) if isinstance(v, float) else rnd(v) if isinstance(v, dict)
-                    else v) for k, v in d.items()}
+        cpu = rnd(cpu_baseline(wl, data))
+        log(f"bench: cpu {cpu}")
+    del data
+    if not args.quick:
+        extras["mvm_beyond_infinity_cache"] = mvm_large(torch, rtc, log, {})
+        extras["serving_mcao_us"] = serving_suite(torch, rtc, log, args.extra_frames)
+        extras["scao_sh_74"] = scao_extras(torch, rtc, log)
+        extras["scao_sh_74_f32_serving_features"] = telemetry_and_swap(torch, rtc, log)
+        extras["latency_sweep_us"] = wfs_sweep(torch, rtc, 500, log)
+        extras["pyramid_normalisation"] = pyramid_norms(torch, rtc, 2000, log)
 
     out = {
-        "metric": METRIC, "value": round(main_res["frames_per_s"], 1), "unit": "frames/s",
+        "metric": METRIC, "value": round(head["p50"], 3), "unit": "us",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(main_res["ms_per_step"], 5), "higher_is_better": True,
+        "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
-        "data": "synthetic (seeded SH spots / pyramid images with the paper's shapes, "
-                "Gaussian control matrix)",
-        "config": {"workload": args.workload, "description": WORKLOAD_TEXT.get(args.workload),
-                   "path": {"stream": "per-launch kernels",
-                            "persistent": "persistent frame loop"}[args.path],
-                   "frames_in_bank": args.bank, "cm_storage": args.dtype},
+        "data": "synthetic (seeded SH spots with photon and read noise, Gaussian control and "
+                "POLC matrices; shapes of the paper's LTAO and SCAO systems)",
+        "config": {"workload": name, "description": WORKLOAD_TEXT[name],
+                   "instances_in_launch": [inst.name for inst in wl.instances],
+                   "frames_per_step": fps, "frame_rate_hz": 1 / PERIOD_S,
+                   "readout_ms": READOUT_S * 1e3, "cm_storage": args.dtype,
+                   "gain_leak_switch_at_timed_frame": sw_run,
+                   "path": "persistent frame loop, pixels from pinned host memory"},
+        "latency_us": {k: rnd(v) for k, v in lat.items()},
         "roofline": roof,
-        "box_reference": ref,
-        "latency_us": ({k: rnd(v) for k, v in latency.items()} | {"what": SERVING_NOTE}
-                       if latency else None),
-        "latency_suite_us": ({**suite, "what": SERVING_NOTE} if suite else None),
-        "paths": {p: {k: rnd(v) for k, v in d.items()} for p, d in paths.items() if d},
-        "mvm": {k: rnd(v) for k, v in mvm.items()},
-        "mvm_beyond_infinity_cache": large,
-        "latency_sweep_us": ({**sweep, "what": SERVING_NOTE} if sweep else None),
-        "pyramid_normalisation": pyr_norm,
         "cpu_baseline": cpu,
+        "box_reference": ref,
+        "extras": extras or None,
     }
     print(json.dumps(out), flush=True)
 

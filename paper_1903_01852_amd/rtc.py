@@ -32,7 +32,8 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_process_frames", "rtc_read_slopes", "rtc_read_matrix", "rtc_run_mvm",
            "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read",
            "rtc_acquire_chunk", "rtc_commit_chunk", "rtc_stage_matrices",
-           "rtc_swap_matrices", "rtc_telemetry_enable", "rtc_telemetry_next")
+           "rtc_swap_matrices", "rtc_telemetry_enable", "rtc_telemetry_next",
+           "rtc_pacer_run")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -69,6 +70,24 @@ class FrameInfoC(C.Structure):
     _fields_ = [("frame", C.c_uint64), ("t_last_chunk_ns", C.c_int64),
                 ("t_ready_ns", C.c_int64), ("dev_ticks_start", C.c_uint64),
                 ("dev_ticks_cmd", C.c_uint64), ("drops", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class PacerStreamC(C.Structure):
+    _fields_ = [("inst", C.c_int32), ("n_bank", C.c_int32), ("banks", C.POINTER(C.c_void_p))]
+
+
+class PacerDescC(C.Structure):
+    _fields_ = [("period_s", C.c_double), ("readout_s", C.c_double), ("n_frames", C.c_int32),
+                ("warmup", C.c_int32), ("first_frame", C.c_uint64), ("zero_copy", C.c_int32),
+                ("switch_stream", C.c_int32), ("switch_frame", C.c_int32),
+                ("switch_gain", C.c_float), ("switch_leak", C.c_float), ("pin", C.c_int32),
+                ("timeout_s", C.c_double)]
+
+
+class PacerSampleC(C.Structure):
+    _fields_ = [("frame", C.c_uint64), ("host_us", C.c_double), ("dev_us", C.c_double),
+                ("complete_us", C.c_double), ("late_us", C.c_double),
+                ("start_late_us", C.c_double)]
 
 
 class TelemetryInfoC(C.Structure):
@@ -121,6 +140,8 @@ def lib() -> C.CDLL:
         L.rtc_run_mvm.argtypes = [vp, i32, i32, vp]
         L.rtc_mvm_timing.argtypes = [vp, i32, i32, i32]
         L.rtc_mvm_timing_read.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(C.c_double)]
+        L.rtc_pacer_run.argtypes = [vp, C.POINTER(PacerDescC), i32, C.POINTER(PacerStreamC),
+                                    C.POINTER(PacerSampleC), C.POINTER(i32)]
         L.rtc_trace_enable.argtypes = [vp, i32]
         L.rtc_trace_read.argtypes = [vp, vp, i64, C.POINTER(i32), C.POINTER(i32)]
         for name in EXPORTS:
@@ -358,6 +379,44 @@ class Engine:
         _ok(lib().rtc_process_frames(self._h, inst, ptrs, strides, n_frames, _ptr(cmds),
                                      _ptr(slopes), _ptr(counts), _stream_ptr(stream)),
             "rtc_process_frames")
+
+    def pace(self, streams, n_frames: int, warmup: int = 0, period_s: float = 2e-3,
+             readout_s: float = 1.5e-3, first_frame: int = 0, zero_copy: bool = False,
+             switch=None, pin: bool = True, timeout_s: float = 5.0):
+        """Paced serving run in the library's own threads (rtc_pacer_run).
+        streams: [(instance, [bank per sensor: uint16 numpy (B, H, W)])];
+        switch: (stream index, run index, gain, leak) or None.  Returns a
+        structured numpy array (n_streams, n_frames - warmup) with fields
+        frame, host_us, dev_us (negative: published before the last chunk),
+        complete_us (from the last chunk that completes a column block), late_us,
+        start_late_us."""
+        keep = []
+        cs = (PacerStreamC * len(streams))()
+        for k, (inst, banks) in enumerate(streams):
+            arr = [np.ascontiguousarray(b, dtype=np.uint16) for b in banks]
+            keep.append(arr)
+            ptrs = (C.c_void_p * len(arr))(*[a.ctypes.data for a in arr])
+            keep.append(ptrs)
+            cs[k].inst = inst
+            cs[k].n_bank = min(a.shape[0] for a in arr)
+            cs[k].banks = ptrs
+        d = PacerDescC(period_s=period_s, readout_s=readout_s, n_frames=n_frames, warmup=warmup,
+                       first_frame=first_frame, zero_copy=int(zero_copy),
+                       switch_stream=-1 if switch is None else switch[0],
+                       switch_frame=-1 if switch is None else switch[1],
+                       switch_gain=0.0 if switch is None else switch[2],
+                       switch_leak=0.0 if switch is None else switch[3],
+                       pin=int(pin), timeout_s=timeout_s)
+        n_rec = n_frames - warmup
+        out = (PacerSampleC * (len(streams) * n_rec))()
+        failed = C.c_int32(-1)
+        st = lib().rtc_pacer_run(self._h, C.byref(d), len(streams), cs, out, C.byref(failed))
+        if st != RTC_OK:
+            raise RtcError(st, f"rtc_pacer_run (frame index {failed.value})")
+        dt = np.dtype([("frame", np.uint64), ("host_us", np.float64), ("dev_us", np.float64),
+                       ("complete_us", np.float64), ("late_us", np.float64),
+                       ("start_late_us", np.float64)])
+        return np.frombuffer(bytes(out), dtype=dt).reshape(len(streams), n_rec).copy()
 
     def run_mvm(self, inst: int, n_iter: int, stream=None):
         _ok(lib().rtc_run_mvm(self._h, inst, n_iter, _stream_ptr(stream)), "rtc_run_mvm")

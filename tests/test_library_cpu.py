@@ -58,8 +58,11 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"rtc_wfs_desc": rtc.WfsDescC, "rtc_instance_desc": rtc.InstanceDescC,
                "rtc_create_desc": rtc.CreateDescC, "rtc_frame_info": rtc.FrameInfoC,
-               "rtc_instance_info": rtc.InstanceInfoC, "rtc_telemetry_info": rtc.TelemetryInfoC}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtc.h"', "int main(void){"]
+               "rtc_instance_info": rtc.InstanceInfoC, "rtc_telemetry_info": rtc.TelemetryInfoC,
+               "rtc_pacer_stream": rtc.PacerStreamC, "rtc_pacer_desc": rtc.PacerDescC,
+               "rtc_pacer_sample": rtc.PacerSampleC}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rtc.h"', '#include "rtc_pacer.h"',
+             "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for fname, _ in py._fields_:
