@@ -55,7 +55,8 @@ typedef enum {
     RTC_E_TIMEOUT = -4,        /* wait expired before the frame completed */
     RTC_E_STATE = -5,          /* call not valid in the current state */
     RTC_E_RING_FULL = -6,      /* pixel ring has no free slot */
-    RTC_E_FRAME_DROPPED = -7   /* the frame was superseded before completing */
+    RTC_E_FRAME_DROPPED = -7,  /* the frame was superseded before completing */
+    RTC_E_SCRATCH = -8         /* the work exceeds the library's static scratch */
 } rtc_status;
 
 enum { RTC_WFS_SH = 0, RTC_WFS_PYR = 1 };
@@ -309,6 +310,26 @@ rtc_status rtc_telemetry_next(rtc_engine *e, int32_t inst, float *slopes, int32_
 rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const *frames,
                               const int64_t *frame_stride, int32_t n_frames,
                               float *cmds, float *slopes, int32_t *counts, void *stream);
+
+/* rtc_process_frames for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and command-state update as
+ * rtc_process_frames in RTC_MODE_STREAM (bit for bit: the same kernels in the
+ * same order), but the matrix products' partial sums and per-tile arrival
+ * counters live in a static device array of the library (16 MiB, one copy
+ * per device, held until the process ends) instead of the engine's buffers;
+ * the call allocates nothing and clears the counters with a kernel, not a
+ * memset.  Every call on one device shares that device's array: calls that
+ * overlap on one device (two streams, two engines or two threads) race, so
+ * order them.  Errors: RTC_E_STATE in RTC_MODE_PERSISTENT or before
+ * rtc_load_matrices; RTC_E_SCRATCH when the instance's partials and counters
+ * (n_segments x n_act + POLC segments x n_act floats, plus 2 x 256 B per
+ * 64-row tile) exceed the array; otherwise as rtc_process_frames. */
+rtc_status rtc_process_frames_noalloc(rtc_engine *e, int32_t inst,
+                                      const uint16_t *const *frames,
+                                      const int64_t *frame_stride, int32_t n_frames,
+                                      float *cmds, float *slopes, int32_t *counts,
+                                      void *stream);
 
 /* Slopes, per-unit counts of thresholded pixels and the thresholded-pixel
  * masks of the most recent frame (host, each nullable).  masks: mask_words

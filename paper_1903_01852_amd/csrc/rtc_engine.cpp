@@ -470,13 +470,25 @@ void enqueue_centroid(Instance *I, hipStream_t st, const FrameSet &fs, int w, in
 // Epilogue of the reconstruction MVM: integrate the commands of the frame at
 // index seq of the sequence (matrix slot ms: its FP8 row scales).  Odd indices
 // stream each segment backwards.
-MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t seq, float c1, float g, float *out) {
+// Partials and per-tile arrival counters the per-launch MVMs of a frame use:
+// the engine's own buffers, or the library's static scratch
+// (rtc_process_frames_noalloc).
+struct MvmScratch {
+    float *ypart;          // reconstruction partials [segment][row]
+    uint32_t *count;       // reconstruction tile counters
+    float *ppart;          // POLC partials
+    uint32_t *count_m;     // POLC tile counters
+};
+MvmScratch engine_scratch(Instance *I) { return {I->d_ypart, I->d_count, I->d_ppart, I->d_count_m}; }
+
+MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t seq, float c1, float g, float *out,
+                          uint32_t *count) {
     MvmEpilogue E{};
     E.mode = EPI_INTEGRATE;
     E.rev = (int32_t)(seq & 1);
     E.n_parts = (int)I->seg.size();
     E.seg_ends = I->d_seg_ends;
-    E.count = I->d_count;
+    E.count = count;
     E.p = I->d.polc ? I->d_p : nullptr;
     E.scale = I->d.cm_dtype == RTC_CM_FP8 ? I->d_scale_s[ms] : nullptr;
     E.a = I->d_a;
@@ -489,16 +501,16 @@ MvmEpilogue integrate_epi(Instance *I, int ms, uint64_t seq, float c1, float g, 
 // POLC term for the next frame: p = M a (section 3.4: formed after the
 // command is ready, off the latency path of the next frame), with the POLC
 // matrix of slot ms (the slot of the frame whose commands a holds).
-void enqueue_polc(Instance *I, hipStream_t st, int ms) {
+void enqueue_polc(Instance *I, hipStream_t st, int ms, float *ppart, uint32_t *count_m) {
     if (!I->d.polc) return;
     MvmEpilogue E{};
     E.mode = EPI_REDUCE;
     E.n_parts = (int)I->segm.size();
     E.seg_ends = I->d_segm_ends;
-    E.count = I->d_count_m;
+    E.count = count_m;
     E.y = I->d_p;
     launch_mvm(st, RTC_CM_F32, I->stream_nt, I->d_M_s[ms], I->d_runm, 0, (int)I->segm.size(),
-               I->n_act, I->d_a, I->d_ppart, E);
+               I->n_act, I->d_a, ppart, E);
 }
 
 rtc_status check(rtc_engine *e, int32_t inst, Instance **out) {
@@ -657,6 +669,104 @@ rtc_status put_matrices(rtc_engine *e, Instance *I, int slot, const float *R, co
     return RTC_OK;
 }
 
+// Per-launch batch of device-resident frames (stream mode) with the given MVM
+// scratch.  The caller holds I->mu and has checked the arguments.
+rtc_status process_frames_stream(rtc_engine *e, Instance *I, const uint16_t *const *frames,
+                                 const int64_t *frame_stride, int32_t n_frames, float *cmds,
+                                 float *slopes, int32_t *counts, hipStream_t st,
+                                 const MvmScratch &sc) {
+    // Frame f's MVM runs in one grid with the slopes of frame f + 1 (into the
+    // other slope buffer), so only frame 0's slopes are a launch of their own.
+    auto frame_set = [&](int f) {
+        FrameSet fs{};
+        for (size_t w = 0; w < I->wfs.size(); ++w) fs.f[w] = frames[w] + (int64_t)f * frame_stride[w];
+        return fs;
+    };
+    auto copy_out = [&](int f) -> rtc_status {
+        if (slopes)
+            HIP_TRY(hipMemcpyAsync(slopes + (size_t)f * I->n_slopes, I->d_sout, I->n_slopes * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        if (counts)
+            HIP_TRY(hipMemcpyAsync(counts + (size_t)f * I->n_units, I->d_counts, I->n_units * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        return RTC_OK;
+    };
+    float *spad[2] = {I->d_spad, I->d_spad2};
+    if (n_frames > 0) {
+        const FrameSet fs = frame_set(0);
+        if (I->n_sh > 0)
+            launch_sh_centroid(st, I->d_sh, 0, I->n_sh, fs, I->params, I->d_sh_dark,
+                               I->d_sh_flat, I->d_sh_bg, I->d_sh_thr, I->d_ref, spad[0],
+                               I->d_sout, I->d_counts, I->d_masks);
+        if (I->n_pyr > 0) {
+            launch_pyr_sum(st, I->d_py, I->n_pyr, fs, I->params, I->d_py_dark, I->d_py_flat,
+                           I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
+            launch_pyr_slopes(st, I->d_py, 0, I->n_pyr, I->n_pyr, fs, I->params, I->d_py_dark,
+                              I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, spad[0],
+                              I->d_sout, I->d_counts, I->d_masks, I->d_pyr_sum);
+        }
+        TRY(copy_out(0));
+    }
+    for (int f = 0; f < n_frames; ++f) {
+        float *x = spad[f & 1];
+        float c1, g;
+        coeffs(I, I->next_frame, &c1, &g);
+        settle_params(I, I->next_frame);
+        const int ms = mat_slot(I, I->next_frame);
+        settle_matrices(I, I->next_frame);
+        const MvmEpilogue E =
+            integrate_epi(I, ms, I->seq++, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr,
+                          sc.count);
+        if (f + 1 < n_frames) {
+            NextSlopes N{};
+            N.sh = I->d_sh;
+            N.py = I->d_py;
+            N.n_sh = I->n_sh;
+            N.n_pyr = I->n_pyr;
+            N.frames = frame_set(f + 1);
+            N.sh_dark = I->d_sh_dark;
+            N.sh_flat = I->d_sh_flat;
+            N.sh_bg = I->d_sh_bg;
+            N.sh_thr = I->d_sh_thr;
+            N.py_dark = I->d_py_dark;
+            N.py_flat = I->d_py_flat;
+            N.py_bg = I->d_py_bg;
+            N.py_thr = I->d_py_thr;
+            N.py_gsum = I->d_pyr_sum;
+            // frame f + 1's pupil sums before the grid that forms its slopes
+            launch_pyr_sum(st, I->d_py, I->n_pyr, N.frames, I->params, I->d_py_dark,
+                           I->d_py_flat, I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
+            N.ref = I->d_ref;
+            N.s_pad = spad[(f + 1) & 1];
+            N.s_out = I->d_sout;
+            N.counts = I->d_counts;
+            N.masks = I->d_masks;
+            // the timer brackets runs of these launches (all alike): one event
+            // pair per run of mvm_ev_every, or up to the batch's last of them
+            if (!I->mvm_open && 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size()) {
+                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
+                I->mvm_open = true;
+                I->mvm_run = 0;
+            }
+            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
+                            (int)I->seg.size(), I->n_act, x, sc.ypart, E, N, I->params);
+            if (I->mvm_open && (++I->mvm_run == I->mvm_ev_every || f + 2 >= n_frames)) {
+                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used + 1], st));
+                I->mvm_ev_len[I->mvm_ev_used++] = I->mvm_run;
+                I->mvm_open = false;
+            }
+        } else {
+            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run, 0,
+                       (int)I->seg.size(), I->n_act, x, sc.ypart, E);
+        }
+        enqueue_polc(I, st, ms, sc.ppart, sc.count_m);
+        if (f + 1 < n_frames) TRY(copy_out(f + 1));
+        I->next_frame++;
+    }
+    return last_error(e);
+}
+
+
 // =========================================================================
 extern "C" {
 
@@ -670,6 +780,7 @@ const char *rtc_strerror(rtc_status s) {
     case RTC_E_STATE: return "invalid state";
     case RTC_E_RING_FULL: return "pixel ring full";
     case RTC_E_FRAME_DROPPED: return "frame dropped";
+    case RTC_E_SCRATCH: return "work exceeds the static scratch";
     }
     return "unknown status";
 }
@@ -701,6 +812,17 @@ rtc_status rtc_create(const rtc_create_desc *desc, rtc_engine **out) {
         return s;
     };
     if (hipSetDevice(e->device) != hipSuccess) return bail(RTC_E_DEVICE);
+    // the device address of the static scratch (rtc_process_frames_noalloc),
+    // taken with the engine's device current: each device has its own copy
+    {
+        void *sp = nullptr;
+        const hipError_t se = scratch_address(&sp);
+        if (se != hipSuccess || sp == nullptr) {
+            std::fprintf(stderr, "rtc: static scratch address: %s\n", hipGetErrorString(se));
+            return bail(RTC_E_DEVICE);
+        }
+        e->scratch = static_cast<uint8_t *>(sp);
+    }
     if (hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking) != hipSuccess)
         return bail(RTC_E_DEVICE);
     if (hipStreamCreateWithFlags(&e->up_stream, hipStreamNonBlocking) != hipSuccess)
@@ -1047,94 +1169,44 @@ rtc_status rtc_process_frames(rtc_engine *e, int32_t inst, const uint16_t *const
         TRY(persist_batch(e, I, frames, frame_stride, n_frames, cmds, slopes, counts, st));
         return last_error(e);
     }
-    // Frame f's MVM runs in one grid with the slopes of frame f + 1 (into the
-    // other slope buffer), so only frame 0's slopes are a launch of their own.
-    auto frame_set = [&](int f) {
-        FrameSet fs{};
-        for (size_t w = 0; w < I->wfs.size(); ++w) fs.f[w] = frames[w] + (int64_t)f * frame_stride[w];
-        return fs;
-    };
-    auto copy_out = [&](int f) -> rtc_status {
-        if (slopes)
-            HIP_TRY(hipMemcpyAsync(slopes + (size_t)f * I->n_slopes, I->d_sout, I->n_slopes * 4,
-                                   hipMemcpyDeviceToDevice, st));
-        if (counts)
-            HIP_TRY(hipMemcpyAsync(counts + (size_t)f * I->n_units, I->d_counts, I->n_units * 4,
-                                   hipMemcpyDeviceToDevice, st));
-        return RTC_OK;
-    };
-    float *spad[2] = {I->d_spad, I->d_spad2};
-    if (n_frames > 0) {
-        const FrameSet fs = frame_set(0);
-        if (I->n_sh > 0)
-            launch_sh_centroid(st, I->d_sh, 0, I->n_sh, fs, I->params, I->d_sh_dark,
-                               I->d_sh_flat, I->d_sh_bg, I->d_sh_thr, I->d_ref, spad[0],
-                               I->d_sout, I->d_counts, I->d_masks);
-        if (I->n_pyr > 0) {
-            launch_pyr_sum(st, I->d_py, I->n_pyr, fs, I->params, I->d_py_dark, I->d_py_flat,
-                           I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
-            launch_pyr_slopes(st, I->d_py, 0, I->n_pyr, I->n_pyr, fs, I->params, I->d_py_dark,
-                              I->d_py_flat, I->d_py_bg, I->d_py_thr, I->d_ref, spad[0],
-                              I->d_sout, I->d_counts, I->d_masks, I->d_pyr_sum);
-        }
-        TRY(copy_out(0));
+    return process_frames_stream(e, I, frames, frame_stride, n_frames, cmds, slopes, counts, st,
+                                 engine_scratch(I));
+}
+
+rtc_status rtc_process_frames_noalloc(rtc_engine *e, int32_t inst, const uint16_t *const *frames,
+                                      const int64_t *frame_stride, int32_t n_frames,
+                                      float *cmds, float *slopes, int32_t *counts,
+                                      void *stream) {
+    Instance *I;
+    TRY(check(e, inst, &I));
+    if (!I->loaded) return RTC_E_STATE;
+    if (e->mode != RTC_MODE_STREAM) return RTC_E_STATE;
+    if (!frames || !frame_stride || n_frames < 0) return RTC_E_INVAL;
+    for (size_t w = 0; w < I->wfs.size(); ++w) {
+        if (!frames[w]) return RTC_E_INVAL;
+        if (n_frames > 1 && frame_stride[w] < (int64_t)I->wfs[w].d.frame_h * I->wfs[w].d.frame_w)
+            return RTC_E_INVAL;
     }
-    for (int f = 0; f < n_frames; ++f) {
-        float *x = spad[f & 1];
-        float c1, g;
-        coeffs(I, I->next_frame, &c1, &g);
-        settle_params(I, I->next_frame);
-        const int ms = mat_slot(I, I->next_frame);
-        settle_matrices(I, I->next_frame);
-        const MvmEpilogue E =
-            integrate_epi(I, ms, I->seq++, c1, g, cmds ? cmds + (size_t)f * I->n_act : nullptr);
-        if (f + 1 < n_frames) {
-            NextSlopes N{};
-            N.sh = I->d_sh;
-            N.py = I->d_py;
-            N.n_sh = I->n_sh;
-            N.n_pyr = I->n_pyr;
-            N.frames = frame_set(f + 1);
-            N.sh_dark = I->d_sh_dark;
-            N.sh_flat = I->d_sh_flat;
-            N.sh_bg = I->d_sh_bg;
-            N.sh_thr = I->d_sh_thr;
-            N.py_dark = I->d_py_dark;
-            N.py_flat = I->d_py_flat;
-            N.py_bg = I->d_py_bg;
-            N.py_thr = I->d_py_thr;
-            N.py_gsum = I->d_pyr_sum;
-            // frame f + 1's pupil sums before the grid that forms its slopes
-            launch_pyr_sum(st, I->d_py, I->n_pyr, N.frames, I->params, I->d_py_dark,
-                           I->d_py_flat, I->d_py_bg, I->d_py_thr, I->pyr_global, I->d_pyr_sum);
-            N.ref = I->d_ref;
-            N.s_pad = spad[(f + 1) & 1];
-            N.s_out = I->d_sout;
-            N.counts = I->d_counts;
-            N.masks = I->d_masks;
-            // the timer brackets runs of these launches (all alike): one event
-            // pair per run of mvm_ev_every, or up to the batch's last of them
-            if (!I->mvm_open && 2 * (I->mvm_ev_used + 1) <= I->mvm_ev.size()) {
-                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used], st));
-                I->mvm_open = true;
-                I->mvm_run = 0;
-            }
-            launch_mvm_next(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run,
-                            (int)I->seg.size(), I->n_act, x, I->d_ypart, E, N, I->params);
-            if (I->mvm_open && (++I->mvm_run == I->mvm_ev_every || f + 2 >= n_frames)) {
-                HIP_TRY(hipEventRecord(I->mvm_ev[2 * I->mvm_ev_used + 1], st));
-                I->mvm_ev_len[I->mvm_ev_used++] = I->mvm_run;
-                I->mvm_open = false;
-            }
-        } else {
-            launch_mvm(st, I->d.cm_dtype, I->stream_nt, I->d_cm_s[ms], I->d_run, 0,
-                       (int)I->seg.size(), I->n_act, x, I->d_ypart, E);
-        }
-        enqueue_polc(I, st, ms);
-        if (f + 1 < n_frames) TRY(copy_out(f + 1));
-        I->next_frame++;
-    }
-    return last_error(e);
+    // carve the static scratch: partials, then counters, each 256-byte aligned
+    auto up256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t n_cnt = (size_t)I->n_tiles * kCountStride;
+    const size_t b_ypart = up256(I->seg.size() * (size_t)I->n_act * 4);
+    const size_t b_ppart = I->d.polc ? up256(I->segm.size() * (size_t)I->n_act * 4) : 0;
+    const size_t b_cnt = up256(n_cnt * 4);
+    if (b_ypart + b_ppart + 2 * b_cnt > kScratchBytes) return RTC_E_SCRATCH;
+    MvmScratch sc;
+    sc.ypart = reinterpret_cast<float *>(e->scratch);
+    sc.ppart = I->d.polc ? reinterpret_cast<float *>(e->scratch + b_ypart) : nullptr;
+    sc.count = reinterpret_cast<uint32_t *>(e->scratch + b_ypart + b_ppart);
+    sc.count_m = reinterpret_cast<uint32_t *>(e->scratch + b_ypart + b_ppart + b_cnt);
+    HIP_TRY(hipSetDevice(e->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(I->mu);
+    // the array keeps the last call's contents (an earlier call may also have
+    // stopped half way): the counters start from zero, by a kernel
+    launch_fill_u32(st, sc.count, 2 * b_cnt / 4, 0u);
+    return process_frames_stream(e, I, frames, frame_stride, n_frames, cmds, slopes, counts, st,
+                                 sc);
 }
 
 rtc_status rtc_run_mvm(rtc_engine *e, int32_t inst, int32_t n_iter, void *stream) {
@@ -1362,7 +1434,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         launch_mvm(e->stream, I->d.cm_dtype, I->stream_nt, I->d_cm_s[I->frame_mslot], I->d_run,
                    I->kb_seg0[kb], I->kb_nseg[kb], I->n_act, I->d_spad, I->d_ypart,
                    integrate_epi(I, I->frame_mslot, I->frame_seq, I->frame_c1, I->frame_g,
-                                 nullptr));
+                                 nullptr, I->d_count));
     }
     S.next_chunk++;
     bool all = true;
@@ -1374,7 +1446,7 @@ rtc_status rtc_submit_pixel_chunk(rtc_engine *e, int32_t inst, int32_t wfs, uint
         settle_matrices(I, frame);
         HIP_TRY(hipMemcpyAsync(mail, I->d_a, I->n_act * 4, hipMemcpyDeviceToHost, e->stream));
         HIP_TRY(hipEventRecord(sl.done, e->stream));
-        enqueue_polc(I, e->stream, I->frame_mslot);
+        enqueue_polc(I, e->stream, I->frame_mslot, I->d_ppart, I->d_count_m);
         sl.t_last_chunk = t_in;
         sl.complete = true;
         I->next_frame = frame + 1;

@@ -224,6 +224,7 @@ struct rtc_engine {
     std::vector<void *> pinned;
     std::atomic<int> sticky{RTC_OK};
     PersistEngine pe;
+    uint8_t *scratch = nullptr;        // this device's copy of the library's static scratch
 };
 
 #define HIP_TRY(expr)                                                                \

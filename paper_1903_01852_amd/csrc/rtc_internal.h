@@ -346,6 +346,12 @@ void launch_mvm_next(hipStream_t st, int dtype, bool stream_nt, const void *cm,
                      const SegRun *runs, int n_segs, int n_rows, const float *x_pad,
                      float *y_part, const MvmEpilogue &epi, const NextSlopes &next,
                      const WfsParamSet &params);
+// Static scratch of rtc_process_frames_noalloc (rtc_kernels.hip): its size,
+// the device address of the current device's copy (call with the device
+// current), and a fill kernel for its counters.
+constexpr size_t kScratchBytes = 16ull << 20;
+hipError_t scratch_address(void **ptr);
+void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v);
 void launch_dgemm_rd(hipStream_t st, const float *R, const double *D, double *M, int n_act,
                      int n_s);
 

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rtc_device.h"
 
 namespace rtc {
@@ -368,7 +370,33 @@ __global__ __launch_bounds__(256) void k_dgemm_rd(const float *__restrict__ R,
 }
 
 // ---------------------------------------------------------------------------
+// Static scratch of the allocation-free batch entry point: MVM partials and
+// per-tile arrival counters.  Every device the library runs on holds its own
+// copy for the life of the process; host code takes its address from
+// scratch_address (the name itself is a host-side stand-in, not a device
+// address).
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+// Fill n uint32 with v (counters that must start at zero; a kernel rather
+// than a memset, so that the work can be captured in a graph).
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *__restrict__ p, size_t n, uint32_t v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
+
+hipError_t scratch_address(void **ptr) {
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
+void launch_fill_u32(hipStream_t st, uint32_t *p, size_t n, uint32_t v) {
+    if (n == 0) return;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, st, p, n, v);
+}
 void launch_sh_centroid(hipStream_t st, const ShUnit *units, int u0, int u1,
                         const FrameSet &frames, const WfsParamSet &params, const float *dark,
                         const float *flat, const float *bg, const float *thr, const float *ref,

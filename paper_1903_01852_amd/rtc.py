@@ -17,7 +17,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librtc.so"
 RTC_OK = 0
 STATUS = {0: "RTC_OK", -1: "RTC_E_INVAL", -2: "RTC_E_NOMEM", -3: "RTC_E_DEVICE",
           -4: "RTC_E_TIMEOUT", -5: "RTC_E_STATE", -6: "RTC_E_RING_FULL",
-          -7: "RTC_E_FRAME_DROPPED"}
+          -7: "RTC_E_FRAME_DROPPED", -8: "RTC_E_SCRATCH"}
 WFS_KIND = {"sh": 0, "pyr": 1}
 CM_DTYPE = {"f32": 0, "bf16": 1, "fp8": 2}
 CM_ELEM = {"f32": 4, "bf16": 2, "fp8": 1}
@@ -33,7 +33,7 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_mvm_timing", "rtc_mvm_timing_read", "rtc_trace_enable", "rtc_trace_read",
            "rtc_acquire_chunk", "rtc_commit_chunk", "rtc_stage_matrices",
            "rtc_swap_matrices", "rtc_telemetry_enable", "rtc_telemetry_next",
-           "rtc_pacer_run")
+           "rtc_process_frames_noalloc", "rtc_pacer_run")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
                 "chain_blocks", "frame_end")
 
@@ -135,6 +135,8 @@ def lib() -> C.CDLL:
         L.rtc_commit_chunk.argtypes = [vp, i32, i32, u64, i32]
         L.rtc_process_frames.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64), i32, vp, vp,
                                          vp, vp]
+        L.rtc_process_frames_noalloc.argtypes = [vp, i32, C.POINTER(vp), C.POINTER(i64), i32,
+                                                 vp, vp, vp, vp]
         L.rtc_read_slopes.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_read_matrix.argtypes = [vp, i32, vp, vp]
         L.rtc_run_mvm.argtypes = [vp, i32, i32, vp]
@@ -366,8 +368,9 @@ class Engine:
 
     # -- batch over device-resident frames
     def process_frames(self, inst: int, frames, n_frames: int, cmds=None, slopes=None,
-                       counts=None, stream=None):
-        """frames: one uint16 CUDA tensor (n, H, W) per sensor."""
+                       counts=None, stream=None, noalloc: bool = False):
+        """frames: one uint16 CUDA tensor (n, H, W) per sensor.  noalloc: the
+        allocation-free entry point (rtc_process_frames_noalloc)."""
         nw = len(frames)
         ptrs = (C.c_void_p * nw)(*[f.data_ptr() for f in frames])
         strides = (C.c_int64 * nw)(*[f.shape[-1] * f.shape[-2] for f in frames])
@@ -376,9 +379,10 @@ class Engine:
                 raise ValueError("frames must be contiguous uint16 device tensors")
             if f.shape[0] < n_frames:
                 raise ValueError("not enough frames")
-        _ok(lib().rtc_process_frames(self._h, inst, ptrs, strides, n_frames, _ptr(cmds),
-                                     _ptr(slopes), _ptr(counts), _stream_ptr(stream)),
-            "rtc_process_frames")
+        fn = lib().rtc_process_frames_noalloc if noalloc else lib().rtc_process_frames
+        _ok(fn(self._h, inst, ptrs, strides, n_frames, _ptr(cmds), _ptr(slopes), _ptr(counts),
+               _stream_ptr(stream)),
+            "rtc_process_frames_noalloc" if noalloc else "rtc_process_frames")
 
     def pace(self, streams, n_frames: int, warmup: int = 0, period_s: float = 2e-3,
              readout_s: float = 1.5e-3, first_frame: int = 0, zero_copy: bool = False,
