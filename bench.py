@@ -172,14 +172,17 @@ def latency_stats(samples):
     together and are copied in one after another), and the pacer's own
     lateness."""
     import numpy as np
-    host = samples["host_us"]
+    # a frame whose commands were out before its last chunk was handed over
+    # (its last rows hold no pixel it needs) has latency 0 from the last pixel
+    host = np.maximum(samples["host_us"], 0.0)
     dev = np.where(samples["dev_us"] >= 0, samples["dev_us"], np.nan)
     steady = ((samples["late_us"] <= np.median(samples["late_us"]) + STEADY_LATE_US)
               & (samples["start_late_us"] <= np.median(samples["start_late_us"]) + STEADY_LATE_US))
     r = _pct(host)
     r["device"] = _pct(dev)
     r["from_completing_chunk"] = _pct(samples["complete_us"])
-    r["published_before_last_chunk"] = int((samples["dev_us"] < 0).sum())
+    r["published_before_last_chunk"] = int(((samples["dev_us"] < 0)
+                                            | (samples["host_us"] < 0)).sum())
     r["steady_subset"] = _pct(host[steady])
     r["pacer_late_us"] = {"last_chunk": _pct(samples["late_us"]),
                           "first_chunk": _pct(samples["start_late_us"])}
@@ -374,7 +377,7 @@ def batch_throughput(torch, eng, frames, n, warmup, inst=0, timed_launches=False
         k, tot = eng.mvm_timing_read(inst)
         eng.mvm_timing(inst, 0, 1)
         if k:
-            r["k_mvm_next_us"] = tot / k * 1e3
+            r["k_mvm_next_us"] = tot / k * 1e6     # mvm_timing_read returns seconds
             r["k_mvm_next_launches_timed"] = k
     return r
 

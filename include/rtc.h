@@ -118,7 +118,9 @@ typedef struct {
 
 typedef struct {
     uint64_t frame;               /* frame number the commands belong to */
-    int64_t t_last_chunk_ns;      /* host CLOCK_MONOTONIC at the last chunk's submission */
+    int64_t t_last_chunk_ns;      /* host CLOCK_MONOTONIC at the last chunk's submission
+                                     (0 if the commands were published and collected
+                                     before the frame's last chunk was submitted) */
     int64_t t_ready_ns;           /* host CLOCK_MONOTONIC when the commands were seen */
     uint64_t dev_ticks_start;     /* device 100 MHz clock: last chunk seen (persistent
                                      mode; 0 if not seen: a frame whose last chunks

@@ -46,7 +46,9 @@ typedef struct {
 
 typedef struct {
     uint64_t frame;                  /* frame number */
-    double host_us;                  /* last chunk handed to the library -> commands seen */
+    double host_us;                  /* last chunk handed to the library -> commands seen
+                                        (negative when they were seen first: the frame's
+                                        last chunks hold no pixel it needs) */
     double dev_us;                   /* device clock: last chunk seen -> commands published;
                                         negative when published before the last chunk arrived
                                         (its last rows hold no pixel the frame needs) */

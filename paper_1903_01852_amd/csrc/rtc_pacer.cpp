@@ -91,6 +91,7 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
     // per stream and frame: host clock of the last block-completing chunk's
     // hand-over and of the commands being seen
     std::vector<int64_t> t_complete((size_t)n_streams * d->n_frames, 0),
+        t_last((size_t)n_streams * d->n_frames, 0),
         t_ready((size_t)n_streams * d->n_frames, 0);
     std::atomic<int> status{RTC_OK};
     std::atomic<int> failed{-1};
@@ -121,6 +122,11 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
                 }
                 const rtc_pacer_stream &S = streams[C.stream];
                 const Instance *I = e->inst[S.inst];
+                const size_t k = (size_t)C.stream * d->n_frames + f;
+                // the hand-over starts now (the library stamps its entry alike)
+                const int64_t t_in = mono_ns();
+                t_last[k] = t_in;
+                if (C.completes) t_complete[k] = t_in;
                 const rtc_wfs_desc &wd = I->wfs[C.wfs].d;
                 const uint16_t *img = S.banks[C.wfs] + (size_t)(f % S.n_bank) * wd.frame_h * wd.frame_w;
                 const uint16_t *rows = img + (size_t)C.row0 * wd.frame_w;
@@ -143,8 +149,6 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
                     break;
                 }
                 const double late = (double)(now - due) * 1e-3;
-                const size_t k = (size_t)C.stream * d->n_frames + f;
-                if (C.completes) t_complete[k] = now;
                 if (first_of[C.stream]) {
                     late_first[k] = late;
                     first_of[C.stream] = 0;
@@ -171,7 +175,6 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
                 if (f < d->warmup) continue;
                 rtc_pacer_sample &o = out[(size_t)s * n_rec + (f - d->warmup)];
                 o.frame = info.frame;
-                o.host_us = (double)(info.t_ready_ns - info.t_last_chunk_ns) * 1e-3;
                 t_ready[(size_t)s * d->n_frames + f] = info.t_ready_ns;
                 o.dev_us = info.dev_ticks_start
                                ? ((double)info.dev_ticks_cmd - (double)info.dev_ticks_start) * 0.01
@@ -187,6 +190,9 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
             const size_t k = (size_t)s * d->n_frames + d->warmup + i;
             out[(size_t)s * n_rec + i].late_us = late_last[k];
             out[(size_t)s * n_rec + i].complete_us = (double)(t_ready[k] - t_complete[k]) * 1e-3;
+            // negative when the commands were out before the last chunk was
+            // handed over (its rows hold no pixel the frame needs)
+            out[(size_t)s * n_rec + i].host_us = (double)(t_ready[k] - t_last[k]) * 1e-3;
             out[(size_t)s * n_rec + i].start_late_us = late_first[k];
         }
     if (failed_frame) *failed_frame = failed.load();
