@@ -278,7 +278,8 @@ rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float 
  * Persistent mode only (RTC_E_STATE otherwise).  rtc_telemetry_enable makes
  * every `decimation`-th frame started on the instance (frames counted from
  * the last rtc_load_matrices or rtc_set_state) write its slopes, its counts
- * of thresholded pixels and its commands into a ring of n_slots records in
+ * of thresholded pixels, its commands and its thresholded-pixel masks into a
+ * ring of n_slots records in
  * pinned host memory owned by the engine; decimation and n_slots are powers
  * of two up to 65536, n_slots 0 turns telemetry off.  It stops the serving
  * loop between frames (RTC_E_STATE while a frame is half delivered) and
@@ -286,7 +287,9 @@ rtc_status rtc_wait_commands(rtc_engine *e, int32_t inst, uint64_t frame, float 
  *
  * rtc_telemetry_next copies the next record in frame order (host arrays,
  * each nullable: slopes n_slopes FP32 as rtc_read_slopes orders them, counts
- * n_units int32, cmds n_act FP32) once its frame is published, waiting at
+ * n_units int32, cmds n_act FP32, masks mask_words uint64 laid out as
+ * rtc_read_slopes lays them out: the thresholded-pixel masks of the frame,
+ * the paper's pixel telemetry in one bit per pixel) once its frame is published, waiting at
  * most timeout_ns (RTC_E_TIMEOUT).  A record is overwritten when the frame
  * decimation * n_slots later starts; records overwritten before being read
  * are skipped and counted in info->lost.  A dropped frame's record has
@@ -300,7 +303,8 @@ typedef struct {
 rtc_status rtc_telemetry_enable(rtc_engine *e, int32_t inst, int32_t decimation,
                                 int32_t n_slots);
 rtc_status rtc_telemetry_next(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
-                              float *cmds, int64_t timeout_ns, rtc_telemetry_info *info);
+                              float *cmds, uint64_t *masks, int64_t timeout_ns,
+                              rtc_telemetry_info *info);
 
 /* Batch path over device-resident frames: runs n_frames consecutive frames
  * through the whole hot path, in order, updating the command state exactly as

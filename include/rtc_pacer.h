@@ -28,6 +28,8 @@ typedef struct {
     int32_t n_bank;                  /* frames in each sensor's bank */
     const uint16_t *const *banks;    /* host, one per sensor of the instance: n_bank frames of
                                         frame_h x frame_w uint16, frame f uses bank frame f % n_bank */
+    float *cmds;                     /* host, nullable: the commands of every recorded frame,
+                                        (n_frames - warmup) x n_act FP32 */
 } rtc_pacer_stream;
 
 typedef struct {

@@ -199,7 +199,7 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
         }
         const uint64_t bal = __ballot(m);
         cnt += __popcll(bal);
-        if (o.masks != nullptr && lane == 0 && j * kWave < npx) gbl(o.masks)[d.mask + j] = bal;
+        if (o.masks != nullptr && lane == 0 && j * kWave < npx) put_out(o, o.masks + d.mask + j, bal);
     }
     sw = wave_sum(sw);
     sx = wave_sum(sx);
@@ -307,7 +307,7 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
         put_out(o, o.s_out + 2 * d.unit + 1, sy);
     }
     if (o.counts != nullptr) put_out(o, o.counts + d.unit, (int32_t)__popcll(bits));
-    if (o.masks != nullptr) gbl(o.masks)[d.mask] = bits;
+    if (o.masks != nullptr) put_out(o, o.masks + d.mask, bits);
 }
 
 // ---------------------------------------------------------------------------

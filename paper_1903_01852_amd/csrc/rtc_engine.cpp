@@ -1022,11 +1022,12 @@ rtc_status rtc_telemetry_enable(rtc_engine *e, int32_t inst, int32_t decimation,
 }
 
 rtc_status rtc_telemetry_next(rtc_engine *e, int32_t inst, float *slopes, int32_t *counts,
-                              float *cmds, int64_t timeout_ns, rtc_telemetry_info *info) {
+                              float *cmds, uint64_t *masks, int64_t timeout_ns,
+                              rtc_telemetry_info *info) {
     Instance *I;
     TRY(check(e, inst, &I));
     if (e->mode != RTC_MODE_PERSISTENT) return RTC_E_STATE;
-    return persist_telemetry_next(e, I, slopes, counts, cmds, timeout_ns, info);
+    return persist_telemetry_next(e, I, slopes, counts, cmds, masks, timeout_ns, info);
 }
 
 rtc_status rtc_load_calibration(rtc_engine *e, int32_t inst, int32_t wfs, const float *dark,

@@ -101,6 +101,7 @@ struct PersistInstState {
     float *tel_host = nullptr;     // pinned, the same layout
     uint64_t *tel_flags = nullptr; // pinned, [slots][kTelMaxTasks]: q + 1 per copied part
     int tel_rec = 0;               // 4-byte words per record (a multiple of 4)
+    int tel_mask_off = 0;          // word offset of the masks in a record
     int tel_dshift = 0;            // decimation 2^tel_dshift
     int tel_slots = 0;             // 0: telemetry off
     uint64_t tel_next = 0;         // sequence number of the next record to read
@@ -305,7 +306,8 @@ void persist_mswap(Instance *I, uint64_t q_switch, int slot);
 void persist_telemetry_free(Instance *I);
 rtc_status persist_telemetry(rtc_engine *e, Instance *I, int decimation, int n_slots);
 rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int32_t *counts,
-                                  float *cmds, int64_t timeout_ns, rtc_telemetry_info *info);
+                                  float *cmds, uint64_t *masks, int64_t timeout_ns,
+                                  rtc_telemetry_info *info);
 rtc_status persist_wait_matrix_free(rtc_engine *e, Instance *I);
 rtc_status persist_quiesce(rtc_engine *e);
 rtc_status persist_acquire(rtc_engine *e, Instance *I, int w, uint64_t frame, int chunk,

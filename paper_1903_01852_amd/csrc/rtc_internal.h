@@ -242,13 +242,15 @@ struct PersistInst {
     // telemetry (serving): frames q with q % 2^tel_dshift == 0 write their
     // slopes, counts and commands into device ring slot (q >> tel_dshift) &
     // tel_smask, one record of tel_rec words (a multiple of 4): slopes, then
-    // counts, then commands; once the frame is published, workers copy the
+    // counts, then commands, then from word tel_mask_off the thresholded-pixel
+    // masks (mask_words uint64); once the frame is published, workers copy the
     // record into the same slot of the pinned host ring, task j setting
     // tel_flags[slot][j] = q + 1 after its part
     float *tel_ring;                       // null: off
     float *tel_host;
     uint64_t *tel_flags;                   // pinned, [slots][kTelMaxTasks]
     int32_t tel_rec;
+    int32_t tel_mask_off, r8;              // word offset of the masks (uint64, 16-byte aligned)
     int32_t tel_dshift, tel_smask;
     // outputs
     float *mail;                           // pinned, ring_depth x n_act (serving)

@@ -164,9 +164,12 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
             std::vector<float> cmds(n_act[s]);
             for (int f = 0; f < d->n_frames; ++f) {
                 rtc_frame_info info;
+                float *dst = (streams[s].cmds != nullptr && f >= d->warmup)
+                                 ? streams[s].cmds + (size_t)(f - d->warmup) * n_act[s]
+                                 : cmds.data();
                 const rtc_status st =
-                    rtc_wait_commands(e, streams[s].inst, d->first_frame + (uint64_t)f,
-                                      cmds.data(), (int64_t)(1e9 * d->timeout_s), &info);
+                    rtc_wait_commands(e, streams[s].inst, d->first_frame + (uint64_t)f, dst,
+                                      (int64_t)(1e9 * d->timeout_s), &info);
                 if (status.load() != RTC_OK) return;
                 if (st != RTC_OK) {
                     fail_at(st, f);

@@ -813,6 +813,7 @@ __device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, 
         if (tel_frame(I, q)) {
             so.s_out = tel_rec(I, q);
             so.counts = reinterpret_cast<int32_t *>(so.s_out + I.n_slopes);
+            so.masks = reinterpret_cast<uint64_t *>(so.s_out + I.tel_mask_off);
         }
         FrameTasks ft = frame_tasks(I, q, rank, nw);
         int ing = first_task(rank, nw, rot(q, I.n_ing_all, nw));

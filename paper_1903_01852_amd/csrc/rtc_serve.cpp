@@ -117,6 +117,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
         d.tel_host = P.tel_host;
         d.tel_flags = P.tel_flags;
         d.tel_rec = P.tel_rec;
+        d.tel_mask_off = P.tel_mask_off;
         d.tel_dshift = P.tel_dshift;
         d.tel_smask = P.tel_slots - 1;
     }
@@ -508,7 +509,9 @@ rtc_status persist_telemetry(rtc_engine *e, Instance *I, int decimation, int n_s
     HIP_TRY(hipDeviceSynchronize());
     persist_telemetry_free(I);
     if (n_slots == 0) return RTC_OK;
-    P.tel_rec = (I->n_slopes + I->n_units + I->n_act + 3) & ~3;
+    // slopes, counts, commands, then the masks on a 16-byte boundary
+    P.tel_mask_off = (I->n_slopes + I->n_units + I->n_act + 3) & ~3;
+    P.tel_rec = (P.tel_mask_off + 2 * I->mask_words + 3) & ~3;
     if (tel_tasks(I) > kTelMaxTasks) return RTC_E_INVAL;
     const size_t ring_bytes = (size_t)P.tel_rec * 4 * n_slots;
     const size_t flag_bytes = (size_t)n_slots * kTelMaxTasks * 8;
@@ -539,7 +542,8 @@ rtc_status persist_telemetry(rtc_engine *e, Instance *I, int decimation, int n_s
 // The next telemetry record, in frame order: waits for its frame to be
 // published; records overwritten before they were read are skipped (counted).
 rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int32_t *counts,
-                                  float *cmds, int64_t timeout_ns, rtc_telemetry_info *info) {
+                                  float *cmds, uint64_t *masks, int64_t timeout_ns,
+                                  rtc_telemetry_info *info) {
     PersistInstState &P = I->ps;
     const int64_t t0 = now_ns();
     uint32_t lost = 0;
@@ -584,6 +588,7 @@ rtc_status persist_telemetry_next(rtc_engine *e, Instance *I, float *slopes, int
         if (slopes) std::memcpy(slopes, rec, (size_t)I->n_slopes * 4);
         if (counts) std::memcpy(counts, rec + I->n_slopes, (size_t)I->n_units * 4);
         if (cmds) std::memcpy(cmds, rec + I->n_slopes + I->n_units, (size_t)I->n_act * 4);
+        if (masks) std::memcpy(masks, rec + P.tel_mask_off, (size_t)I->mask_words * 8);
         std::lock_guard<std::mutex> lk(I->mu);
         if (P.seq > q + span) continue;     // overwritten while copied: skip ahead
         if (info) {

@@ -73,7 +73,8 @@ class FrameInfoC(C.Structure):
 
 
 class PacerStreamC(C.Structure):
-    _fields_ = [("inst", C.c_int32), ("n_bank", C.c_int32), ("banks", C.POINTER(C.c_void_p))]
+    _fields_ = [("inst", C.c_int32), ("n_bank", C.c_int32), ("banks", C.POINTER(C.c_void_p)),
+                ("cmds", C.c_void_p)]
 
 
 class PacerDescC(C.Structure):
@@ -122,7 +123,8 @@ def lib() -> C.CDLL:
         L.rtc_load_matrices.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_stage_matrices.argtypes = [vp, i32, vp, vp, vp]
         L.rtc_telemetry_enable.argtypes = [vp, i32, i32, i32]
-        L.rtc_telemetry_next.argtypes = [vp, i32, vp, vp, vp, i64, C.POINTER(TelemetryInfoC)]
+        L.rtc_telemetry_next.argtypes = [vp, i32, vp, vp, vp, vp, i64,
+                                         C.POINTER(TelemetryInfoC)]
         L.rtc_swap_matrices.argtypes = [vp, i32, C.POINTER(u64)]
         L.rtc_load_calibration.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
         L.rtc_set_params.argtypes = [vp, i32, C.c_float, C.c_float, C.POINTER(u64)]
@@ -288,16 +290,19 @@ class Engine:
         _ok(lib().rtc_telemetry_enable(self._h, inst, decimation, n_slots),
             "rtc_telemetry_enable")
 
-    def telemetry_next(self, inst: int = 0, timeout_s: float = 5.0):
-        """Next telemetry record: (slopes, counts, cmds, info dict)."""
+    def telemetry_next(self, inst: int = 0, timeout_s: float = 5.0, masks: bool = False):
+        """Next telemetry record: (slopes, counts, cmds, info dict), and with
+        masks=True the thresholded-pixel masks (uint64 words) as a fifth item."""
         info = self.infos[inst]
         s = np.empty(info["n_slopes"], np.float32)
         c = np.empty(info["n_units"], np.int32)
         a = np.empty(info["n_act"], np.float32)
+        m = np.empty(info["mask_words"], np.uint64) if masks else None
         ti = TelemetryInfoC()
-        _ok(lib().rtc_telemetry_next(self._h, inst, _ptr(s), _ptr(c), _ptr(a),
+        _ok(lib().rtc_telemetry_next(self._h, inst, _ptr(s), _ptr(c), _ptr(a), _ptr(m),
                                      int(timeout_s * 1e9), C.byref(ti)), "rtc_telemetry_next")
-        return s, c, a, {"frame": ti.frame, "dropped": ti.dropped, "lost": ti.lost}
+        d = {"frame": ti.frame, "dropped": ti.dropped, "lost": ti.lost}
+        return (s, c, a, d, m) if masks else (s, c, a, d)
 
     def load_calibration(self, inst: int, wfs: int, dark=None, flat=None, bg=None, thr=None,
                          ref=None):
@@ -386,15 +391,18 @@ class Engine:
 
     def pace(self, streams, n_frames: int, warmup: int = 0, period_s: float = 2e-3,
              readout_s: float = 1.5e-3, first_frame: int = 0, zero_copy: bool = False,
-             switch=None, pin: bool = True, timeout_s: float = 5.0):
+             switch=None, pin: bool = True, timeout_s: float = 5.0, cmds: bool = False):
         """Paced serving run in the library's own threads (rtc_pacer_run).
         streams: [(instance, [bank per sensor: uint16 numpy (B, H, W)])];
         switch: (stream index, run index, gain, leak) or None.  Returns a
         structured numpy array (n_streams, n_frames - warmup) with fields
         frame, host_us, dev_us (negative: published before the last chunk),
         complete_us (from the last chunk that completes a column block), late_us,
-        start_late_us."""
+        start_late_us.  cmds=True: also every recorded frame's commands, one
+        (n_frames - warmup, n_act) float32 array per stream (returned second)."""
         keep = []
+        n_rec = n_frames - warmup
+        cmd_out = []
         cs = (PacerStreamC * len(streams))()
         for k, (inst, banks) in enumerate(streams):
             arr = [np.ascontiguousarray(b, dtype=np.uint16) for b in banks]
@@ -404,6 +412,10 @@ class Engine:
             cs[k].inst = inst
             cs[k].n_bank = min(a.shape[0] for a in arr)
             cs[k].banks = ptrs
+            if cmds:
+                buf = np.zeros((n_rec, self.infos[inst]["n_act"]), np.float32)
+                cmd_out.append(buf)
+                cs[k].cmds = buf.ctypes.data
         d = PacerDescC(period_s=period_s, readout_s=readout_s, n_frames=n_frames, warmup=warmup,
                        first_frame=first_frame, zero_copy=int(zero_copy),
                        switch_stream=-1 if switch is None else switch[0],
@@ -411,7 +423,6 @@ class Engine:
                        switch_gain=0.0 if switch is None else switch[2],
                        switch_leak=0.0 if switch is None else switch[3],
                        pin=int(pin), timeout_s=timeout_s)
-        n_rec = n_frames - warmup
         out = (PacerSampleC * (len(streams) * n_rec))()
         failed = C.c_int32(-1)
         st = lib().rtc_pacer_run(self._h, C.byref(d), len(streams), cs, out, C.byref(failed))
@@ -420,7 +431,8 @@ class Engine:
         dt = np.dtype([("frame", np.uint64), ("host_us", np.float64), ("dev_us", np.float64),
                        ("complete_us", np.float64), ("late_us", np.float64),
                        ("start_late_us", np.float64)])
-        return np.frombuffer(bytes(out), dtype=dt).reshape(len(streams), n_rec).copy()
+        samples = np.frombuffer(bytes(out), dtype=dt).reshape(len(streams), n_rec).copy()
+        return (samples, cmd_out) if cmds else samples
 
     def run_mvm(self, inst: int, n_iter: int, stream=None):
         _ok(lib().rtc_run_mvm(self._h, inst, n_iter, _stream_ptr(stream)), "rtc_run_mvm")

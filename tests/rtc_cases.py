@@ -49,10 +49,13 @@ class Case:
                 self.D = synth.interaction_matrix(self.wl, inst_index)
 
     def oracle_M(self):
+        """The oracle's POLC matrix (the FP64 product R.D is formed once)."""
         if self.M is not None:
             return self.M.astype(np.float64)
         if self.D is not None:
-            return oracle.polc_matrix(self.R, self.D)
+            if getattr(self, "_M_rd", None) is None:
+                self._M_rd = oracle.polc_matrix(self.R, self.D)
+            return self._M_rd
         return None
 
     def load(self, eng, idx: int = 0):
