@@ -577,6 +577,8 @@ def main():
                     help="frames per serving extra")
     ap.add_argument("--mvm-large-only", action="store_true",
                     help="only the standalone MVM on the matrices beyond the cache (profiling)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the roofline's cold MVM launches (hardware-counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -615,6 +617,15 @@ def main():
     wl, data = build_inputs(name, 64)
     ltao = wl.instances[0]
     fps = args.frames_per_step
+    if args.roofline_only:
+        eng = load_engine(rtc, wl, data, args.dtype, "stream", only=0)
+        cold, n_cold = mvm_timing(torch, eng, n_iter=200, cold=True)
+        alg = mvm_alg_bytes(ltao, eng.infos[0]["n_slopes"], args.dtype)
+        eng.close()
+        print(json.dumps({"roofline_only": {"avg_launch_us": round(cold * 1e6, 3),
+                                            "launches": n_cold, "alg_bytes": alg,
+                                            "gbs": round(alg / cold / 1e9, 1)}}), flush=True)
+        return
     eng = load_engine(rtc, wl, data, args.dtype, "persistent")
     infos = eng.infos
     sw_run = args.steps * fps // 2

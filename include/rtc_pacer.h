@@ -61,6 +61,8 @@ typedef struct {
     double late_us;                  /* the frame's last chunk handed over this late against
                                         its schedule (the pacer's own jitter) */
     double start_late_us;            /* the frame's first chunk this late against its schedule */
+    uint64_t dev_ticks_start;        /* device clock (100 MHz) of the last chunk seen, 0 if not */
+    uint64_t dev_ticks_cmd;          /* device clock of the commands' publication */
 } rtc_pacer_sample;
 
 /* Runs d->n_frames paced frames through every stream and writes, for each

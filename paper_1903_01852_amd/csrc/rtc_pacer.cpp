@@ -179,6 +179,8 @@ extern "C" rtc_status rtc_pacer_run(rtc_engine *e, const rtc_pacer_desc *d, int3
                 rtc_pacer_sample &o = out[(size_t)s * n_rec + (f - d->warmup)];
                 o.frame = info.frame;
                 t_ready[(size_t)s * d->n_frames + f] = info.t_ready_ns;
+                o.dev_ticks_start = info.dev_ticks_start;
+                o.dev_ticks_cmd = info.dev_ticks_cmd;
                 o.dev_us = info.dev_ticks_start
                                ? ((double)info.dev_ticks_cmd - (double)info.dev_ticks_start) * 0.01
                                : -1.0;

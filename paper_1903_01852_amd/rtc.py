@@ -88,7 +88,8 @@ class PacerDescC(C.Structure):
 class PacerSampleC(C.Structure):
     _fields_ = [("frame", C.c_uint64), ("host_us", C.c_double), ("dev_us", C.c_double),
                 ("complete_us", C.c_double), ("late_us", C.c_double),
-                ("start_late_us", C.c_double)]
+                ("start_late_us", C.c_double), ("dev_ticks_start", C.c_uint64),
+                ("dev_ticks_cmd", C.c_uint64)]
 
 
 class TelemetryInfoC(C.Structure):
@@ -430,7 +431,8 @@ class Engine:
             raise RtcError(st, f"rtc_pacer_run (frame index {failed.value})")
         dt = np.dtype([("frame", np.uint64), ("host_us", np.float64), ("dev_us", np.float64),
                        ("complete_us", np.float64), ("late_us", np.float64),
-                       ("start_late_us", np.float64)])
+                       ("start_late_us", np.float64), ("dev_ticks_start", np.uint64),
+                       ("dev_ticks_cmd", np.uint64)])
         samples = np.frombuffer(bytes(out), dtype=dt).reshape(len(streams), n_rec).copy()
         return (samples, cmd_out) if cmds else samples
 
