@@ -455,6 +455,72 @@ __device__ __forceinline__ float stream_segment_dir(const uint4 *__restrict__ pg
     return a0 + a1;
 }
 
+// ---------------------------------------------------------------------------
+// Double-buffered segment stream (per-launch MVM and frame loop).  The
+// segment's part of a tile is one buffer resource (nv vectors of nr rows, 16
+// bytes each); lane l reads row l of each vector (1 KiB contiguous per
+// wavefront load).  Offsets are scalar, and a vector past the segment's end
+// reads as zeros without a memory access, so every batch issues exactly U
+// loads and the compiler's memory-counter waits stay exact instead of
+// draining the stream.
+constexpr int kBufNT = 2;      // buffer-load cache policy: non-temporal
+
+// Batches are taken in pairs, so that no loop exit sits between a batch's
+// loads and their use (the compiler would otherwise sink the prefetch past
+// it).  An odd batch count ends with one batch past the end: its loads return
+// zeros without touching memory and its slopes in LDS are zeros, so it adds
+// exact zeros after every real product.
+template <int U, bool NT>
+struct SegStream {
+    __amdgpu_buffer_rsrc_t rs;
+    int nb, voff, vstride;
+    __device__ __forceinline__ int bmap(int b) const { return (b < 0 || b >= nb) ? nb : b; }
+    __device__ __forceinline__ void load(vec16_t (&q)[U], int b) const {
+        const int o = bmap(b) * U * vstride;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            q[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, o + u * vstride,
+                                                         NT ? kBufNT : 0);
+    }
+};
+
+// The double-buffered stream of one segment's vectors against its slopes in
+// LDS (xl: padded to whole batches plus one zero batch), the first batch
+// already loaded into qa.  Returns this lane's partial.
+template <int DT, int U, bool NT, bool REV>
+__device__ __forceinline__ float seg_stream(const SegStream<U, NT> &ss, vec16_t (&qa)[U],
+                                            const RTC_LDS lds4_t *xl) {
+    constexpr int step = REV ? -1 : 1;
+    int b = REV ? ss.nb - 1 : 0;
+    vec16_t qb[U];
+    float a0 = 0.0f, a1 = 0.0f;
+    auto compute = [&](const vec16_t (&q)[U], int bb) {
+        const int v0 = ss.bmap(bb) * U;
+        if constexpr (!REV) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
+        } else {
+#pragma unroll
+            for (int u = U - 1; u >= 0; --u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
+        }
+    };
+    // the scheduler barriers keep each batch's loads ahead of the previous
+    // batch's products (left to itself, the scheduler sinks them to save
+    // registers, which drains the stream at every batch)
+    for (int i = 0; i < (ss.nb + 1) / 2; ++i) {
+        ss.load(qb, b + step);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(qa, b);
+        __builtin_amdgcn_sched_barrier(0);
+        ss.load(qa, b + 2 * step);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(qb, b + step);
+        __builtin_amdgcn_sched_barrier(0);
+        b += 2 * step;
+    }
+    return a0 + a1;
+}
+
 // The partials were written by wavefronts on any XCD; agent-scope atomic loads
 // read them past this XCD's (non-coherent) L2.
 __device__ __forceinline__ float load_agent(const float *p) {

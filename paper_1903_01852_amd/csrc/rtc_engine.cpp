@@ -280,7 +280,6 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         if (I->kb_nseg[b] == 0) I->kb_seg0[b] = (int)i;
         I->kb_nseg[b]++;
     }
-    for (size_t b = 0; b < I->kb.size(); ++b) I->kb_segs.push_back(int2{I->kb_seg0[b], I->kb_nseg[b]});
     if (I->seg.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
     I->seg_ends = segment_ends(I->seg);
     // POLC column blocks of kPolcBlock commands, F32
@@ -303,13 +302,6 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                      (int64_t)last_nr * L.kv * 16;
         I->a_len = nb * kPolcBlock;
         build_segments(I->kbm, kMaxSegVectors, I->segm);
-        std::vector<int> s0(I->kbm.size(), 0), ns(I->kbm.size(), 0);
-        for (size_t i = 0; i < I->segm.size(); ++i) {
-            const int b = I->segm[i].kb;
-            if (ns[b] == 0) s0[b] = (int)i;
-            ns[b]++;
-        }
-        for (size_t b = 0; b < I->kbm.size(); ++b) I->kbm_segs.push_back(int2{s0[b], ns[b]});
         if (I->segm.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
         I->segm_ends = segment_ends(I->segm);
     } else {
@@ -326,8 +318,6 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_kb, nkb));
     TRY(dev_alloc(e, &I->d_kbm, std::max<size_t>(I->kbm.size(), 1)));
     TRY(dev_alloc(e, &I->d_seg, I->seg.size()));
-    TRY(dev_alloc(e, &I->d_kb_segs, I->kb_segs.size()));
-    TRY(dev_alloc(e, &I->d_kbm_segs, std::max<size_t>(I->kbm_segs.size(), 1)));
     TRY(dev_alloc(e, &I->d_seg_ends, I->seg_ends.size()));
     TRY(dev_alloc(e, &I->d_segm_ends, std::max<size_t>(I->segm_ends.size(), 1)));
     TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
@@ -376,8 +366,6 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
         return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
     HIP_TRY(up(I->d_seg, I->seg.data(), I->seg.size() * sizeof(Segment)));
-    HIP_TRY(up(I->d_kb_segs, I->kb_segs.data(), I->kb_segs.size() * sizeof(int2)));
-    HIP_TRY(up(I->d_kbm_segs, I->kbm_segs.data(), I->kbm_segs.size() * sizeof(int2)));
     HIP_TRY(up(I->d_seg_ends, I->seg_ends.data(), I->seg_ends.size() * 4));
     HIP_TRY(up(I->d_segm_ends, I->segm_ends.data(), I->segm_ends.size() * 4));
     HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));

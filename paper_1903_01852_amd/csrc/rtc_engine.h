@@ -64,12 +64,10 @@ struct PersistInstState {
     // per-launch path's)
     float *spad_x[rtc::kDepth - 1] = {}, *ypart_x[rtc::kDepth - 1] = {},
           *ppart_x[rtc::kDepth - 1] = {};
-    float *bsum = nullptr;         // serving block sums [kDepth][n_kb][n_act]
     uint64_t *ctr = nullptr;       // every frame-loop counter, zeroed on reset
     size_t n_ctr = 0;
     uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
-    uint64_t *kbt_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
-    uint64_t *blk_cnt = nullptr;
+    uint64_t *tile_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
     int n_cen_all = 0;             // centroid tasks of a frame
     int n_ing_all = 0;             // ingest pieces of a frame (serving)
     uint64_t *ing_cnt = nullptr;   // [kDepth][n_steps] ingest counters
@@ -128,7 +126,6 @@ struct Instance {
     std::vector<KBlock> kbm;       // POLC column blocks
     std::vector<Segment> seg, segm;            // segments: reconstruction, POLC
     std::vector<int> kb_seg0, kb_nseg;         // segments of each column block
-    std::vector<int2> kb_segs, kbm_segs;       // the same as {first, count}, recon / POLC
     std::vector<uint32_t> seg_ends, segm_ends; // bit j: segment j ends its block (recon / POLC)
     int spad_len = 0;
     int64_t cm_bytes = 0, m_bytes = 0;
@@ -141,7 +138,6 @@ struct Instance {
     KBlock *d_kb = nullptr, *d_kbm = nullptr;
     Segment *d_seg = nullptr, *d_segm = nullptr;
     rtc::SegRun *d_run = nullptr, *d_runm = nullptr;   // the segments, block fields folded in
-    int2 *d_kb_segs = nullptr, *d_kbm_segs = nullptr;   // per block {first segment, count}
     uint32_t *d_seg_ends = nullptr, *d_segm_ends = nullptr;
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;

@@ -184,7 +184,7 @@ struct PersistInst {
     const KBlock *kbs;
     const KbWork *kbw;
     const Segment *segs;
-    const int2 *kb_segs;
+    const uint32_t *seg_ends;      // bit j: segment j ends its column block
     const Step *steps;
     int32_t n_kb, n_seg, n_steps, n_wfs;
     int32_t n_cen_all, r5;         // centroid tasks of a frame (every block)
@@ -203,13 +203,12 @@ struct PersistInst {
     const uint8_t *M[2];           // slot s pairs with cm[s]
     const KBlock *kbm;
     const Segment *segm;
-    const int2 *kbm_segs;
+    const uint32_t *segm_ends;
     int32_t n_kbm, n_segm;
     // state and scratch
     float *s_pad[kDepth];          // frame q uses buffer q % kDepth
     float *y_part[kDepth];
     float *p_part[kDepth];
-    float *bsum;                   // serving: [kDepth][n_kb][n_act] block sums
     float *p;
     float *a;                      // two command buffers of a_stride floats (frame parity)
     int32_t a_stride, r4;
@@ -217,9 +216,8 @@ struct PersistInst {
     uint64_t *cen_fan;             // [kDepth][n_kb] fan-in: centroid tasks of a block
     uint64_t *tile_fan;            // [kDepth] fan-in: tiles whose commands are out
     uint64_t *pol_fan;             // [kDepth] fan-in: tiles whose POLC term is formed
-    uint64_t *kbt_cnt;             // [kDepth][n_kb][n_tiles] partials of a block on a tile
+    uint64_t *tile_cnt;            // [kDepth][n_tiles] segment partials of a tile formed
     uint64_t *join;                // [kDepth][n_tiles] accumulation joins
-    uint64_t *blk_cnt;             // [kDepth][n_tiles] serving: block sums of a tile
     uint64_t *pol_cnt;             // [kDepth][n_tiles] POLC partials of a tile
     uint64_t *p_done;              // [n_tiles] q + 1 of the last POLC term reduced
     uint64_t *db_mirror;           // device copy of the doorbells, per sensor
@@ -297,10 +295,12 @@ constexpr int kCtrSlot = 32;                      // uint64 per counter slot
 constexpr int kFanStripes = 32;
 constexpr int kFanSlots = kFanStripes + 1;        // stripes, then the top
 
-void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args);
+// serving: the indefinitely running form (2 waves per SIMD, so up to 256
+// VGPRs a lane); otherwise the batch form (4 waves per SIMD)
+void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args, bool serving);
 void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_off, int n_tiles,
                           int par, int polc);
-int frame_loop_max_blocks_per_cu();
+int frame_loop_max_blocks_per_cu(bool serving);
 
 // Launchers (defined in rtc_kernels.hip).
 void launch_sh_centroid(hipStream_t st, const ShUnit *units, int u0, int u1,

@@ -122,50 +122,19 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
 // The split-K MVM.  A workgroup streams one segment (part of one column
 // block) for four consecutive 64-row tiles, one tile per wavefront, one row
 // per lane; the segment's slope values are staged once in LDS and read by
-// every lane as broadcasts.
+// every lane as broadcasts, and each wavefront streams its tile's part with
+// seg_stream (double-buffered batches of U 16-byte vectors).  Odd frames
+// (REV) visit the vectors last to first; the accumulation order is the frame
+// loop's, so the partials equal its own bit for bit.
 //
-// Each wavefront streams its segment in batches of U 16-byte vectors,
-// double-buffered: the loads of batch i + 1 are in flight while batch i's
-// products run, so every lane keeps 2U loads outstanding.  Loads are buffer
-// loads over the segment's part of the tile: the offsets are scalar, and a
-// vector past the segment's end reads as zeros without a memory access (its
-// slopes in LDS are zero too), so every batch issues exactly U loads and the
-// compiler's memory-counter waits stay exact instead of draining the stream.
-// Odd frames (REV) visit the vectors last to first.  Products accumulate in
-// visiting order into two running sums (even and odd elements of each
-// vector), exactly as stream_segment does, so the partial equals the frame
-// loop's bit for bit.
-constexpr int kBufNT = 2;      // buffer-load cache policy: non-temporal
-
-// Batches are taken in pairs, so that no loop exit sits between a batch's
-// loads and their use (the compiler would otherwise sink the prefetch past
-// it).  An odd batch count ends with one batch past the end: its loads return
-// zeros without touching memory and its slopes in LDS are zeros, so it adds
-// exact zeros after every real product.
-template <int U, bool NT>
-struct SegStream {
-    __amdgpu_buffer_rsrc_t rs;
-    int nb, voff, vstride;
-    __device__ __forceinline__ int bmap(int b) const { return (b < 0 || b >= nb) ? nb : b; }
-    __device__ __forceinline__ void load(vec16_t (&q)[U], int b) const {
-        const int o = bmap(b) * U * vstride;
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            q[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, o + u * vstride,
-                                                         NT ? kBufNT : 0);
-    }
-};
-
-// A segment's slope values staged in LDS by the whole workgroup (zero past
-// its last vector, one zero batch beyond), with this wavefront's first matrix
-// batch issued before the copy's wait, so that the two round trips overlap;
-// then the double-buffered stream.  Returns this lane's partial.
+// The segment's slopes are staged by the whole workgroup (zero past its last
+// vector, one zero batch beyond), with this wavefront's first matrix batch
+// issued before the copy's wait, so that the two round trips overlap.
 template <int DT, int U, bool NT, bool REV>
 __device__ __forceinline__ float seg_partial_buf(const SegStream<U, NT> &ss, const float *x,
                                                  int nx, int n4, bool live, RTC_LDS float *lds) {
     constexpr int EL = Elem<DT>::E;
     constexpr int kStage = (((kMaxSegVectors + U - 1) / U + 1) * U * EL / 4 + 255) / 256;
-    constexpr int step = REV ? -1 : 1;
     lds4_t sv[kStage];
     const lds4_t *__restrict__ xs4 = reinterpret_cast<const lds4_t *>(x);
 #pragma unroll
@@ -173,9 +142,8 @@ __device__ __forceinline__ float seg_partial_buf(const SegStream<U, NT> &ss, con
         const int i = j * 256 + (int)threadIdx.x;
         sv[j] = xs4[4 * i < nx ? i : 0];
     }
-    int b = REV ? ss.nb - 1 : 0;
-    vec16_t qa[U], qb[U];
-    ss.load(qa, b);
+    vec16_t qa[U];
+    ss.load(qa, REV ? ss.nb - 1 : 0);
 #pragma unroll
     for (int j = 0; j < kStage; ++j) {
         const int i = j * 256 + (int)threadIdx.x;
@@ -187,32 +155,7 @@ __device__ __forceinline__ float seg_partial_buf(const SegStream<U, NT> &ss, con
     __builtin_amdgcn_s_barrier();
     if (!live) return 0.0f;
     const RTC_LDS lds4_t *xl = (const RTC_LDS lds4_t *)lds;
-    float a0 = 0.0f, a1 = 0.0f;
-    auto compute = [&](const vec16_t (&q)[U], int bb) {
-        const int v0 = ss.bmap(bb) * U;
-        if constexpr (!REV) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
-        } else {
-#pragma unroll
-            for (int u = U - 1; u >= 0; --u) dot16<DT>(q[u], xl, v0 + u, a0, a1);
-        }
-    };
-    // the scheduler barriers keep each batch's loads ahead of the previous
-    // batch's products (left to itself, the scheduler sinks them to save
-    // registers, which drains the stream at every batch)
-    for (int i = 0; i < (ss.nb + 1) / 2; ++i) {
-        ss.load(qb, b + step);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(qa, b);
-        __builtin_amdgcn_sched_barrier(0);
-        ss.load(qa, b + 2 * step);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(qb, b + step);
-        __builtin_amdgcn_sched_barrier(0);
-        b += 2 * step;
-    }
-    return a0 + a1;
+    return seg_stream<DT, U, NT, REV>(ss, qa, xl);
 }
 
 template <int DT, int U, bool NT>

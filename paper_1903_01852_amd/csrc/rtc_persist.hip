@@ -84,7 +84,7 @@ __device__ void watchdog_expired(ArgsRef A) {
 
 // Spin until *ctr >= target.  False when the loop must exit (stop request or
 // watchdog expiry); the stop flag and the clock are checked every 32 polls.
-__device__ bool wait_geq(const uint64_t *ctr, uint64_t target, ArgsRef A,
+__device__ __forceinline__ bool wait_geq(const uint64_t *ctr, uint64_t target, ArgsRef A,
                          uint64_t limit) {
     if (ld_agent64(ctr) >= target) return true;
     const uint64_t t0 = wall_clock64();
@@ -106,34 +106,6 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
     return dq > q || (dq == q && (db & kDbChunkMask) >= chunks);
 }
 
-// Stage n floats written by other wavefronts of this kernel into this
-// wavefront's LDS slice (two floats per agent-scope atomic load).
-__device__ __forceinline__ void stage_lds(RTC_LDS float *lds, const float *src, int n, int lane) {
-    const uint64_t *s2 = reinterpret_cast<const uint64_t *>(src);
-    RTC_LDS uint64_t *d2 = (RTC_LDS uint64_t *)lds;
-    const int n2 = (n + 1) >> 1;
-    constexpr int kPer = (kMaxSegVectors * 16 / 2 + kWave - 1) / kWave;   // worst case (FP8)
-    uint64_t v[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int i = j * kWave + lane;
-        v[j] = i < n2 ? __hip_atomic_load(gbl(s2 + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-    }
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int i = j * kWave + lane;
-        if (i < n2) d2[i] = v[j];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void lds_done() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Timeline record (rtc_trace_enable): this wavefront's events of one frame.
 struct Trace {
@@ -222,38 +194,72 @@ __device__ __forceinline__ int vec_elems(int dtype) {
     return dtype == RTC_CM_F32 ? 4 : dtype == RTC_CM_BF16 ? 8 : 16;
 }
 
-// Vectors in flight per lane.  Slope values come from LDS into VGPRs here, so
-// the batch is smaller than in the per-launch kernel (scalar slope loads);
-// 16 resident wavefronts per CU keep ~32 MB of matrix loads in flight.
-template <int DT> struct LoopBatch { static constexpr int U = 8; };
-template <> struct LoopBatch<RTC_CM_FP8> { static constexpr int U = 4; };
-
-// Partial of one segment on tile t for this lane's row (0 past the tile's rows);
-// rev streams it backwards.  Ordinary loads whatever the matrix size: the
-// non-temporal variants double the loop's streaming code and push the kernel
-// into spills.
-template <int DT>
-__device__ __forceinline__ float mvm_partial(const uint8_t *cm, const KBlock &K, const Segment &S,
-                                             int t, int nr, int lane, const RTC_LDS float *lds,
-                                             bool rev) {
-    if (lane >= nr) return 0.0f;
-    const uint4 *p = reinterpret_cast<const uint4 *>(cm + K.base + (int64_t)t * kTileRows * K.kv * 16) +
-                     (int64_t)S.v0 * nr + lane;
-    return stream_segment_dir<DT, LoopBatch<DT>::U, const RTC_LDS lds4_t *>(
-        p, nr, (const RTC_LDS lds4_t *)lds, S.nv, rev);
+// MVM task of the loop: segment S of column block K on tile t for this
+// wavefront, with the double-buffered stream of the per-launch MVM
+// (seg_stream, batches of kLoopBatch vectors).  The segment's slopes, written
+// by other wavefronts of this kernel during the frame, are staged in this
+// wavefront's LDS slice with agent-scope 16-byte buffer loads (a value past
+// the segment reads as zero, which pads the slice to whole batches plus a
+// zero batch); the first matrix batch is issued before the copy's wait so the
+// two round trips overlap.  rev streams the vectors last to first.
+constexpr int kLoopBatch = 8;
+constexpr int kLoopLdsFloats = ((kMaxSegVectors + kLoopBatch - 1) / kLoopBatch + 1) * kLoopBatch * 16;
+constexpr int kBufAgent = 16;      // buffer-access cache policy: agent coherent (sc1)
+template <int DT, bool REV>
+__device__ __forceinline__ float loop_task(const uint8_t *cm, const KBlock &K, const Segment &S,
+                                           int t, int nr, int lane, const float *xs,
+                                           RTC_LDS float *lds) {
+    constexpr int EL = Elem<DT>::E, U = kLoopBatch;
+    constexpr int kPer = (kLoopLdsFloats / 4 + kWave - 1) / kWave;
+    const int nb = (S.nv + U - 1) / U;
+    const int n4 = (nb + 1) * U * EL / 4;
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void *)xs, (short)0, S.nv * EL * 4, 0x00020000);
+    lds4_t sv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kWave + lane;
+        const vec16_t w = __builtin_amdgcn_raw_buffer_load_b128(rx, i * 16, 0, kBufAgent);
+        sv[j] = lds4_t{__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+                       __uint_as_float(w.w)};
+    }
+    SegStream<U, false> ss;
+    ss.rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(cm + K.base + ((int64_t)t * kTileRows * K.kv + (int64_t)S.v0 * nr) * 16),
+        (short)0, S.nv * nr * 16, 0x00020000);
+    ss.nb = nb;
+    ss.voff = lane * 16;
+    ss.vstride = nr * 16;
+    vec16_t qa[U];
+    ss.load(qa, REV ? nb - 1 : 0);
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kWave + lane;
+        if (i < n4) ((RTC_LDS lds4_t *)lds)[i] = sv[j];
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): this wavefront's LDS writes done
+    __builtin_amdgcn_wave_barrier();
+    return seg_stream<DT, U, false, REV>(ss, qa, (const RTC_LDS lds4_t *)lds);
 }
 
-// Reconstruction partial of frame q: odd frames stream the segment backwards,
-// as the per-launch kernels do.
+// Partial of segment S on tile t for this lane's row (rows past the tile read
+// as zero rows and are not stored): storage type at run time, direction by
+// frame parity (odd frames backwards, as the per-launch kernels).
 __device__ __forceinline__ float seg_partial(InstRef I, int ms, uint64_t q, const KBlock &K,
                                              const Segment &S, int t, int nr, int lane,
-                                             const RTC_LDS float *lds) {
+                                             const float *xs, RTC_LDS float *lds) {
     const uint8_t *cm = I.cm[ms];   // read from the descriptor at use: no registers held
     const bool rev = (q & 1) != 0;
     switch (I.dtype) {
-    case RTC_CM_F32: return mvm_partial<RTC_CM_F32>(cm, K, S, t, nr, lane, lds, rev);
-    case RTC_CM_BF16: return mvm_partial<RTC_CM_BF16>(cm, K, S, t, nr, lane, lds, rev);
-    default: return mvm_partial<RTC_CM_FP8>(cm, K, S, t, nr, lane, lds, rev);
+    case RTC_CM_F32:
+        return rev ? loop_task<RTC_CM_F32, true>(cm, K, S, t, nr, lane, xs, lds)
+                   : loop_task<RTC_CM_F32, false>(cm, K, S, t, nr, lane, xs, lds);
+    case RTC_CM_BF16:
+        return rev ? loop_task<RTC_CM_BF16, true>(cm, K, S, t, nr, lane, xs, lds)
+                   : loop_task<RTC_CM_BF16, false>(cm, K, S, t, nr, lane, xs, lds);
+    default:
+        return rev ? loop_task<RTC_CM_FP8, true>(cm, K, S, t, nr, lane, xs, lds)
+                   : loop_task<RTC_CM_FP8, false>(cm, K, S, t, nr, lane, xs, lds);
     }
 }
 
@@ -467,19 +473,12 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
     }
 }
 
-// The tile's reconstruction sum for row r: batch adds the segment partials
-// block by block, serving the block sums (one value per block).
-constexpr int kSumBatch = 16;
-__device__ float tile_sum(InstRef I, uint64_t q, int r) {
-    const int n_kb = I.n_kb, n_act = I.n_act;
-    if (I.serving)
-        return sum_in_blocks<kSumBatch>(I.bsum + (size_t)dslot(q) * n_kb * n_act, n_kb, n_kb,
-                                        n_act, r, [](int b) { return b + 1; });
-    const int2 *kb_segs = I.kb_segs;
-    return sum_in_blocks<kSumBatch>(I.y_part[dslot(q)], I.n_seg, n_kb, n_act, r, [&](int b) {
-        const int2 sb = ldc(kb_segs + b);
-        return sb.x + sb.y;
-    });
+// The tile's reconstruction sum for row r: its segment partials of the frame,
+// block by block in readout order, the block ends from the mask (every lane
+// holds its words; r of lanes past a short tile is clamped).
+constexpr int kSumBatch = 64;
+__device__ __forceinline__ float tile_sum(InstRef I, uint64_t q, int r, const SegEnds &ends) {
+    return sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, r, ends);
 }
 
 // Commands of tile t for frame q, then of every following frame whose join
@@ -487,8 +486,9 @@ __device__ float tile_sum(InstRef I, uint64_t q, int r) {
 __device__ int finish_chain(InstRef I, uint64_t q, int t, int lane) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
+    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
     for (int done = 1;; ++done) {
-        const float y = lane < nr ? tile_sum(I, q, r) : 0.0f;
+        const float y = tile_sum(I, q, t * kTileRows + (lane < nr ? lane : 0), ends);
         tile_commands(I, q, t, r, lane < nr, y, lane);
         ++q;
         if (q >= I.q_end || !join(I, q, t, lane)) return done;
@@ -507,7 +507,7 @@ __device__ __forceinline__ void accumulate(InstRef I, uint64_t q, int t, int lan
 
 // POLC term of frame q + 1: p = M a_q, partials per POLC segment, reduced by
 // the wavefront completing a tile.
-__device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
+__device__ __forceinline__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
                            int nw, int lane, RTC_LDS float *lds, Trace &tr) {
     const int n_tasks = I.n_segm * I.n_tiles;
     int j = first_task(rank, nw, rot(q, n_tasks, nw));
@@ -524,30 +524,24 @@ __device__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int rank,
         const int t = j - sg * I.n_tiles;
         const Segment S = ldc(I.segm + sg);
         const KBlock K = ldc(I.kbm + S.kb);
-        stage_lds(lds, aq + K.spad + S.v0 * 4, S.nv * 4, lane);
+        const int nr = min(kTileRows, I.n_act - t * kTileRows);
+        const float v = loop_task<RTC_CM_F32, false>(I.M[ms], K, S, t, nr, lane,
+                                                     aq + K.spad + S.v0 * 4, lds);
         // p_part copy of frame q is free once frame q - kDepth's term of the tile
         // is reduced
         if (q >= I.q_begin + kDepth &&
             !wait_geq(slot(I.p_done, t), q - kDepth + 1, A, A.dep_watchdog))
             return false;
-        const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = mvm_partial<RTC_CM_F32>(I.M[ms], K, S, t, nr, lane, lds, false);
         if (lane < nr) st_agent(part + (size_t)sg * I.n_act + t * kTileRows + lane, v);
-        lds_done();
         drain();
         uint64_t old = 0;
         if (lane == 0) old = add_agent64(slot(I.pol_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
         old = __shfl(old, 0, kWave);
         if (old + 1 != par_target(I, q, (uint64_t)I.n_segm)) continue;
-        const int r = t * kTileRows + lane;
-        if (lane < nr) {
-            float y = 0.0f;
-            for (int b = 0; b < I.n_kbm; ++b) {
-                const int2 sb = ldc(I.kbm_segs + b);
-                y += sum_parts(part, sb.x, sb.y, I.n_act, r);
-            }
-            st_agent(I.p + r, y);
-        }
+        const SegEnds ends = load_seg_ends(I.segm_ends, I.n_segm, lane);
+        const int r = t * kTileRows + (lane < nr ? lane : 0);
+        const float y = sum_partials<kSumBatch>(part, I.n_segm, I.n_act, r, ends);
+        if (lane < nr) st_agent(I.p + r, y);
         drain();
         if (lane == 0) st_agent64(slot(I.p_done, t), q + 1);
         const bool all = fan_arrive(I, fan_grp(I.pol_fan, q, 1, 0), q, I.n_tiles,
@@ -578,7 +572,7 @@ __device__ __forceinline__ FrameTasks frame_tasks(InstRef I, uint64_t q, int ran
 // index j (into the frame's task list) advances past the block.  Lane s
 // accumulates in cnt this worker's tasks on stripe s, counting tasks by their
 // frame index (global_idx: one barrier for the frame) or their block index.
-__device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, int lane,
+__device__ __forceinline__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, int lane,
                                const SlopeOut &so, bool global_idx, int &j, uint32_t &cnt) {
     const int end = W.cen_base + W.n_cen;
     if (j >= end) return;
@@ -627,9 +621,10 @@ __device__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, i
 }
 
 // MVM tasks (segment x tile) of this worker in column block kb of frame q;
-// the block's slopes must be complete.  A tile's last partial joins its
-// accumulation (serving: of the block; batch: of the whole frame).
-__device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw, int lane,
+// the block's slopes must be complete.  Each task counts on its tile's
+// counter; the arrival completing the tile's partials of the frame (every
+// segment of every block) is the tile's (E) party.
+__device__ __forceinline__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw, int lane,
                           RTC_LDS float *lds, int &m, Trace &tr, int budget = 1 << 30) {
     const int n_tiles = I.n_tiles;
     const int end = W.mvm_base + W.nseg * n_tiles;
@@ -640,47 +635,23 @@ __device__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw
     const int E = vec_elems(I.dtype);
     const KBlock K = ldc(I.kbs + kb);
     const int ms = mat_slot(I, q);
-    int staged = -1;
     for (; m < end && budget > 0; m += nw, --budget) {
         const int jm = m - W.mvm_base;
         const int sl = jm / n_tiles;
         const int t = jm - sl * n_tiles;
         const int sg = W.seg0 + sl;
         const Segment Sg = ldc(I.segs + sg);
-        if (staged != sg) {
-            if (staged >= 0) lds_done();
-            stage_lds(lds, spad + K.spad + Sg.v0 * E, Sg.nv * E, lane);
-            staged = sg;
-        }
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = seg_partial(I, ms, q, K, Sg, t, nr, lane, lds);
+        const float v = seg_partial(I, ms, q, K, Sg, t, nr, lane, spad + K.spad + Sg.v0 * E, lds);
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
-        const int jkb = I.serving ? kb : 0;
-        const uint64_t need = I.serving ? (uint64_t)W.nseg : (uint64_t)I.n_seg;
         uint64_t old = 0;
-        if (lane == 0)
-            old = add_agent64(slot(I.kbt_cnt, ((size_t)dslot(q) * I.n_kb + jkb) * I.n_tiles + t), 1);
+        if (lane == 0) old = add_agent64(slot(I.tile_cnt, (size_t)dslot(q) * n_tiles + t), 1);
         old = __shfl(old, 0, kWave);
-        if (old + 1 != par_target(I, q, need)) continue;
-        if (I.serving) {
-            // the block's last partial on this tile: its block sum
-            const int r = t * kTileRows + lane;
-            if (lane < nr) {
-                const int2 sb = ldc(I.kb_segs + kb);
-                st_agent(I.bsum + ((size_t)dslot(q) * I.n_kb + kb) * I.n_act + r,
-                         sum_parts(I.y_part[dslot(q)], sb.x, sb.y, I.n_act, r));
-            }
-            drain();
-            uint64_t ob = 0;
-            if (lane == 0) ob = add_agent64(slot(I.blk_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
-            ob = __shfl(ob, 0, kWave);
-            if (ob + 1 != par_target(I, q, (uint64_t)I.n_kb)) continue;
-        }
+        if (old + 1 != par_target(I, q, (uint64_t)I.n_seg)) continue;
         // (E) party: the tile's reconstruction sum is ready
         if (join(I, q, t, lane)) accumulate(I, q, t, lane, tr);
     }
-    lds_done();
     tr.stamp(RTC_TRACE_MVM_LAST, lane);
 }
 
@@ -801,7 +772,7 @@ __device__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb) {
     return ld_agent64(fan_top(fan_grp(I.cen_fan, q, I.n_kb, kb))) >= fan_target(I, q, W.n_cen);
 }
 
-__device__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
+__device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                                RTC_LDS float *lds) {
     for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
         if (stopping(A)) return;
@@ -923,7 +894,7 @@ __device__ __forceinline__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q
 // frames ahead would gate on the frame multiplied just before, which measured
 // slower).  Every wait of iteration q is on work each worker did in an earlier
 // iteration, so the loop cannot deadlock.
-__device__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
+__device__ __forceinline__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                              RTC_LDS float *lds) {
     constexpr int kAhead = 1;
     const uint64_t q0 = I.q_begin, q1 = I.q_end;
@@ -954,29 +925,43 @@ __device__ void batch_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, in
 
 }  // namespace
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_frame_loop(PersistArgs args) {
-    // the explicit arguments open the kernel-argument segment
-    (void)args;
-    ArgsRef A = *(const RTC_CONST PersistArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-    __shared__ __attribute__((aligned(16))) float lds_all[4][kMaxSegVectors * 16];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
-    RTC_LDS float *lds = (RTC_LDS float *)lds_all[threadIdx.x >> 6];
-    for (int i = 0; i < A.n_inst; ++i) {
-        InstRef I = ((volatile const RTC_CONST PersistInst *)A.inst)[i];
-        if (wid < I.w0 || wid >= I.w1) continue;
-        if (I.serving) {
-            if (wid == I.w0) {
-                sentinel(I, A, lane);
-                return;
-            }
-            serving_worker(I, A, wid, wid - I.w0 - 1, I.w1 - I.w0 - 1, lane, lds);
-        } else {
-            batch_worker(I, A, wid, wid - I.w0, I.w1 - I.w0, lane, lds);
-        }
-        return;
+// The kernel arguments open the kernel-argument segment; each wavefront finds
+// its instance by its index in the grid.
+#define RTC_FRAME_LOOP_BODY(SERVING)                                                     \
+    (void)args;                                                                          \
+    ArgsRef A = *(const RTC_CONST PersistArgs *)__builtin_amdgcn_kernarg_segment_ptr();  \
+    __shared__ __attribute__((aligned(16))) float lds_all[4][kLoopLdsFloats];            \
+    const int lane = threadIdx.x & (kWave - 1);                                          \
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)); \
+    RTC_LDS float *lds = (RTC_LDS float *)lds_all[threadIdx.x >> 6];                     \
+    for (int i = 0; i < A.n_inst; ++i) {                                                 \
+        InstRef I = ((volatile const RTC_CONST PersistInst *)A.inst)[i];                 \
+        if (wid < I.w0 || wid >= I.w1) continue;                                         \
+        if (SERVING) {                                                                   \
+            if (wid == I.w0)                                                             \
+                sentinel(I, A, lane);                                                    \
+            else                                                                         \
+                serving_worker(I, A, wid, wid - I.w0 - 1, I.w1 - I.w0 - 1, lane, lds);   \
+        } else {                                                                         \
+            batch_worker(I, A, wid, wid - I.w0, I.w1 - I.w0, lane, lds);                 \
+        }                                                                                \
+        return;                                                                          \
     }
+
+// Serving form: it runs until stopped beside whatever else the device runs,
+// at two workgroups per CU, so a lane may hold up to 256 VGPRs.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_frame_loop_serve(PersistArgs args) {
+    RTC_FRAME_LOOP_BODY(true)
 }
+
+// Batch form: a finite launch over frames already in device memory, at the
+// whole occupancy.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+k_frame_loop_batch(PersistArgs args) {
+    RTC_FRAME_LOOP_BODY(false)
+}
+#undef RTC_FRAME_LOOP_BODY
 
 // Counters of one instance at the start of a launch: zero, except the joins
 // of the first frame (copy par), which find their (A) part, and with POLC
@@ -1001,15 +986,19 @@ void launch_seed_counters(hipStream_t st, uint64_t *ctr, size_t n, size_t join_o
                        par, polc);
 }
 
-void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args) {
-    hipLaunchKernelGGL(k_frame_loop, dim3(n_blocks), dim3(256), 0, st, args);
+void launch_frame_loop(hipStream_t st, int n_blocks, const PersistArgs &args, bool serving) {
+    if (serving)
+        hipLaunchKernelGGL(k_frame_loop_serve, dim3(n_blocks), dim3(256), 0, st, args);
+    else
+        hipLaunchKernelGGL(k_frame_loop_batch, dim3(n_blocks), dim3(256), 0, st, args);
 }
 
-int frame_loop_max_blocks_per_cu() {
+int frame_loop_max_blocks_per_cu(bool serving) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frame_loop, 256, 0) != hipSuccess)
-        return 0;
-    return n;
+    const hipError_t err =
+        serving ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frame_loop_serve, 256, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_frame_loop_batch, 256, 0);
+    return err == hipSuccess ? n : 0;
 }
 
 }  // namespace rtc

@@ -51,7 +51,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.kbs = I->d_kb;
     d.kbw = P.kbw;
     d.segs = I->d_seg;
-    d.kb_segs = I->d_kb_segs;
+    d.seg_ends = I->d_seg_ends;
     d.steps = nullptr;
     d.n_kb = (int)I->kb.size();
     d.n_cen_all = P.n_cen_all;
@@ -82,7 +82,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.polc = I->d.polc;
     d.kbm = I->d_kbm;
     d.segm = I->d_segm;
-    d.kbm_segs = I->d_kbm_segs;
+    d.segm_ends = I->d_segm_ends;
     d.n_kbm = (int)I->kbm.size();
     d.n_segm = (int)I->segm.size();
     d.s_pad[0] = I->d_spad;
@@ -93,15 +93,13 @@ PersistInst describe(rtc_engine *e, Instance *I) {
         d.y_part[k] = P.ypart_x[k - 1];
         d.p_part[k] = P.ppart_x[k - 1];
     }
-    d.bsum = P.bsum;
-    d.blk_cnt = P.blk_cnt;
     d.p = I->d_p;
     d.a = I->d_a;
     d.a_stride = I->a_len;
     d.cen_fan = P.cen_fan;
     d.tile_fan = P.tile_fan;
     d.pol_fan = P.pol_fan;
-    d.kbt_cnt = P.kbt_cnt;
+    d.tile_cnt = P.tile_cnt;
     d.join = P.join;
     d.pol_cnt = P.pol_cnt;
     d.p_done = P.p_done;
@@ -182,7 +180,7 @@ rtc_status upload_and_launch(rtc_engine *e, const std::vector<Instance *> &insts
         HIP_TRY(hipMemsetAsync(pe.trace, 0,
                                (size_t)pe.trace_frames * A.n_waves * RTC_TRACE_EVENTS * 8, st));
     }
-    launch_frame_loop(st, n_blocks, A);
+    launch_frame_loop(st, n_blocks, A, !batch);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) {
         std::fprintf(stderr, "rtc: frame loop launch failed: %s\n", hipGetErrorString(err));
@@ -274,10 +272,11 @@ rtc_status persist_alloc(rtc_engine *e) {
     // the grid must be entirely resident: a serving loop runs indefinitely and
     // leaves room on every CU for whatever else shares the device; a batch
     // launch is finite and takes the whole occupancy
-    const int occ = frame_loop_max_blocks_per_cu();
-    if (occ < 1) return RTC_E_DEVICE;
-    pe.n_blocks = dev_cus * std::min(2, occ);
-    pe.n_blocks_batch = dev_cus * occ;
+    const int occ_serve = frame_loop_max_blocks_per_cu(true);
+    const int occ_batch = frame_loop_max_blocks_per_cu(false);
+    if (occ_serve < 1 || occ_batch < 1) return RTC_E_DEVICE;
+    pe.n_blocks = dev_cus * std::min(2, occ_serve);
+    pe.n_blocks_batch = dev_cus * occ_batch;
     for (Instance *I : e->inst) {
         PersistInstState &P = I->ps;
         const size_t nkb = I->kb.size(), nt = (size_t)I->n_tiles;
@@ -287,24 +286,21 @@ rtc_status persist_alloc(rtc_engine *e) {
             TRY(dev_alloc(e, &P.ppart_x[k],
                           std::max<size_t>(I->segm.size(), 1) * (size_t)I->n_act));
         }
-        TRY(dev_alloc(e, &P.bsum, (size_t)kDepth * I->kb.size() * I->n_act));
         // counters, each in a slot of its own; arrival counters kDepth times:
-        // fan-in barriers cen [D][nkb], tile [D], pol [D]; kbt_cnt and join
-        // [D][nkb][nt]; pol_cnt [D][nt]; p_done [nt] once
+        // fan-in barriers cen [D][nkb], tile [D], pol [D]; tile_cnt, join and
+        // pol_cnt [D][nt]; p_done [nt] once; ing_cnt [D][n_steps]
         const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size();
-        const size_t n_slots =
-            D * nkb * fan + 2 * D * fan + D * nkb * nt + D * nt + D * nt + nt + D * nst + D * nt;
+        const size_t n_slots = D * nkb * fan + 2 * D * fan + 3 * D * nt + nt + D * nst;
         P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_fan = P.ctr;
         P.tile_fan = P.cen_fan + D * nkb * fan * kCtrSlot;
         P.pol_fan = P.tile_fan + D * fan * kCtrSlot;
-        P.kbt_cnt = P.pol_fan + D * fan * kCtrSlot;
-        P.join = P.kbt_cnt + D * nkb * nt * kCtrSlot;
+        P.tile_cnt = P.pol_fan + D * fan * kCtrSlot;
+        P.join = P.tile_cnt + D * nt * kCtrSlot;
         P.pol_cnt = P.join + D * nt * kCtrSlot;
         P.p_done = P.pol_cnt + D * nt * kCtrSlot;
         P.ing_cnt = P.p_done + nt * kCtrSlot;
-        P.blk_cnt = P.ing_cnt + D * nst * kCtrSlot;
         // serving ingest: each readout step's rows as 16-byte units of a ring
         // slot, in pieces, numbered in readout order; the buffer accesses take
         // 32-bit byte offsets
