@@ -374,16 +374,22 @@ rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *
  * frames of that launch, overwriting the previous launch's record; 0 turns the
  * record off (its cost is then one test per frame).  Synchronises the engine;
  * the loop must not be running (RTC_E_STATE otherwise). */
-#define RTC_TRACE_EVENTS 8
+#define RTC_TRACE_EVENTS 14
 enum {
     RTC_TRACE_FRAME_START = 0,   /* the wavefront reached the frame */
     RTC_TRACE_GATE = 1,          /* frame q - 2 published: the frame may start */
-    RTC_TRACE_CENTROIDS = 2,     /* its centroid tasks of the frame done */
+    RTC_TRACE_CENTROIDS = 2,     /* its last centroid tasks of the frame done and counted */
     RTC_TRACE_MVM_FIRST = 3,     /* its first MVM task starts (slopes ready) */
     RTC_TRACE_MVM_LAST = 4,      /* its last MVM task (and accumulation) done */
-    RTC_TRACE_CHAIN_TICKS = 5,   /* ticks it spent accumulating blocks (a count) */
-    RTC_TRACE_CHAIN_BLOCKS = 6,  /* blocks it accumulated (a count) */
-    RTC_TRACE_FRAME_END = 7      /* POLC tasks done, leaving the frame */
+    RTC_TRACE_INGEST = 5,        /* serving: its last ingest pieces copied and counted */
+    RTC_TRACE_ACCUM = 6,         /* its last tile accumulation done (commands counted) */
+    RTC_TRACE_FRAME_END = 7,     /* POLC tasks done, leaving the frame */
+    RTC_TRACE_CEN_START = 8,     /* its last centroid tasks start (their pixels are in) */
+    RTC_TRACE_LAST_BLOCK = 9,    /* its first MVM task of the frame's last block starts */
+    RTC_TRACE_TILE_READY = 10,   /* it completed a tile's partials (the sum starts) */
+    RTC_TRACE_CMDS = 11,         /* its last tile's commands written (before counting) */
+    RTC_TRACE_INGEST_START = 12, /* serving: its last ingest pieces start (doorbell seen) */
+    RTC_TRACE_SUMMED = 13        /* its last tile sum (and command operands) in registers */
 };
 rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames);
 /* Copies the record of the last launch into out (host): value

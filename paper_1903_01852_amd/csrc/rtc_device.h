@@ -162,24 +162,22 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
     const int p = P.p;
     const int npx = p * p;
     const int mode = P.thr_mode;
+    // every load is issued at once, without a condition (lanes past the
+    // unit's pixels read its last pixel and drop it), so the unit costs one
+    // round trip to memory; the reference slopes come with them
     uint32_t raw[kMaxShPasses];
     float dk[kMaxShPasses], fl[kMaxShPasses], bgv[kMaxShPasses];
 #pragma unroll
     for (int j = 0; j < kMaxShPasses; ++j) {
-        const int i = j * kWave + lane;
-        raw[j] = 0;
-        dk[j] = 0.0f;
-        fl[j] = 0.0f;
-        bgv[j] = 0.0f;
-        if (i < npx) {
-            const int r = i / p;
-            const int c = i - r * p;
-            raw[j] = load_px<LP>(fr + (size_t)(d.row0 + r) * P.W + (d.col0 + c));
-            dk[j] = gbl(dark)[d.cal + i];
-            fl[j] = gbl(flat)[d.cal + i];
-            bgv[j] = gbl(bg)[d.cal + i];
-        }
+        const int i = min(j * kWave + lane, npx - 1);
+        const int r = i / p;
+        const int c = i - r * p;
+        raw[j] = load_px<LP>(fr + (size_t)(d.row0 + r) * P.W + (d.col0 + c));
+        dk[j] = gbl(dark)[d.cal + i];
+        fl[j] = gbl(flat)[d.cal + i];
+        bgv[j] = gbl(bg)[d.cal + i];
     }
+    const float rx = gbl(ref)[2 * d.unit], ry = gbl(ref)[2 * d.unit + 1];
     float sw = 0.0f, sx = 0.0f, sy = 0.0f;
     int cnt = 0;
 #pragma unroll
@@ -207,8 +205,8 @@ __device__ __forceinline__ void sh_unit(const ShUnit &d, float T, const uint16_t
     if (lane == 0) {
         float ox = 0.0f, oy = 0.0f;
         if (sw > 0.0f) {
-            ox = sx / sw - gbl(ref)[2 * d.unit];
-            oy = sy / sw - gbl(ref)[2 * d.unit + 1];
+            ox = sx / sw - rx;
+            oy = sy / sw - ry;
         }
         put<SP>(o.s_pad + d.pad, ox);
         put<SP>(o.s_pad + d.pad + 1, oy);
@@ -231,15 +229,20 @@ __device__ __forceinline__ uint64_t pyr_intensities(const PyrUnit &d, int k, int
                                                     const float *__restrict__ dark4,
                                                     const float *__restrict__ flat4,
                                                     const float *__restrict__ bg4, float (&I)[4]) {
+    // every load first, so the unit costs one round trip to memory
     uint32_t raw[4];
+    float dk[4], fl[4], bgv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
         raw[q] = load_px<LP>(fr + (size_t)(P.qrow[q] + d.i) * P.W + (P.qcol[q] + d.j));
+        dk[q] = gbl(dark4)[q * n_pyr + k];
+        fl[q] = gbl(flat4)[q * n_pyr + k];
+        bgv[q] = gbl(bg4)[q * n_pyr + k];
+    }
     uint64_t bits = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float cv = calibrate_px((float)raw[q], gbl(dark4)[q * n_pyr + k],
-                                      gbl(flat4)[q * n_pyr + k], gbl(bg4)[q * n_pyr + k]);
+        const float cv = calibrate_px((float)raw[q], dk[q], fl[q], bgv[q]);
         bool m;
         I[q] = threshold_px(cv, T, P.thr_mode, m);
         bits |= (uint64_t)m << q;
@@ -292,13 +295,14 @@ __device__ __forceinline__ void pyr_unit(const PyrUnit &d, int k, int n_pyr, flo
                                          const float *__restrict__ bg4,
                                          const float *__restrict__ ref, const SlopeOut &o,
                                          float gS) {
+    const float rx = gbl(ref)[2 * d.unit], ry = gbl(ref)[2 * d.unit + 1];
     float I[4];
     const uint64_t bits = pyr_intensities<LP>(d, k, n_pyr, T, fr, P, dark4, flat4, bg4, I);
     const float S = P.norm == RTC_PYR_NORM_GLOBAL ? gS : (I[0] + I[1]) + (I[2] + I[3]);
     float sx = 0.0f, sy = 0.0f;
     if (S > 0.0f) {
-        sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - gbl(ref)[2 * d.unit];
-        sy = ((I[0] + I[2]) - (I[1] + I[3])) / S - gbl(ref)[2 * d.unit + 1];
+        sx = ((I[0] + I[1]) - (I[2] + I[3])) / S - rx;
+        sy = ((I[0] + I[2]) - (I[1] + I[3])) / S - ry;
     }
     put<SP>(o.s_pad + d.pad, sx);
     put<SP>(o.s_pad + d.pad + 1, sy);
@@ -527,55 +531,6 @@ __device__ __forceinline__ float load_agent(const float *p) {
     return __hip_atomic_load(gbl(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum of partials [s0, s0 + n) of row r, in increasing order.
-__device__ __forceinline__ float sum_parts(const float *__restrict__ part, int s0, int n,
-                                          int n_rows, int r) {
-    float y = 0.0f;
-    int j = 0;
-    for (; j + 8 <= n; j += 8) {
-        float v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = load_agent(part + (size_t)(s0 + j + u) * n_rows + r);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) y += v[u];
-    }
-    for (; j < n; ++j) y += load_agent(part + (size_t)(s0 + j) * n_rows + r);
-    return y;
-}
-
-// Sum of one row over a tile's column blocks, in block order, each block's
-// values in order: y = ((B_0 + B_1) + B_2) + ..., B_k = ((0 + v_a) + v_b) + ...
-// for vals[j * n_rows + r], j in [0, n); block k ends before index
-// end_of(k).  Up to BATCH loads are in flight however short the blocks are (a
-// per-block loop would wait for memory once per block: ~100 round trips for
-// six laser guide stars).
-template <int BATCH, class EndOf>
-__device__ __forceinline__ float sum_in_blocks(const float *vals, int n, int n_kb, int n_rows,
-                                               int r, EndOf end_of) {
-    float y = 0.0f, blk = 0.0f;
-    int kb = 0;
-    int blk_end = n_kb > 0 ? end_of(0) : n;
-    for (int s0 = 0; s0 < n; s0 += BATCH) {
-        float v[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u)
-            v[u] = s0 + u < n ? load_agent(vals + (size_t)(s0 + u) * n_rows + r) : 0.0f;
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            const int j = s0 + u;
-            if (j < n) {
-                blk += v[u];
-                if (j + 1 == blk_end) {
-                    y = kb == 0 ? blk : y + blk;
-                    blk = 0.0f;
-                    if (++kb < n_kb) blk_end = end_of(kb);
-                }
-            }
-        }
-    }
-    return y;
-}
-
 // Block ends of a segment list as a bitmask: bit j of word j / 32 is set when
 // segment j is the last of its column block.  A wavefront holds the mask in
 // registers, lane l holding words l, l + 64, ... (kEndWordsPerLane of them:
@@ -607,18 +562,31 @@ __device__ __forceinline__ uint32_t seg_end_word(const SegEnds &m, int wi) {
 // Sum of one row over a tile's column blocks, in block order, each block's
 // segment partials in order: y = ((B_0 + B_1) + B_2) + ..., B_k = ((0 + p_a)
 // + p_b) + ... for part[j * n_rows + r], j in [0, n), block ends from the mask.
-// BATCH (a multiple of 32) loads in flight.
-template <int BATCH>
+// The partials were stored by wavefronts on any XCD: agent-coherent buffer
+// loads (cache policy sc1) read them past this XCD's L2.  BATCH (a multiple of
+// 32) loads are issued back to back with no condition (an index past the
+// last partial reads zero from the buffer's range check), so one round trip
+// to memory covers a batch.  The first batch is peeled: after its loads are
+// issued, after_first() issues whatever else the caller needs from memory
+// (those round trips then overlap) and returns false to abandon the sum
+// (the result is then 0).  r must be below n_rows.
+constexpr int kBufAgent = 16;
+template <int BATCH, class After>
 __device__ __forceinline__ float sum_partials(const float *part, int n, int n_rows, int r,
-                                              const SegEnds &ends) {
+                                              const SegEnds &ends, After &&after_first) {
     static_assert(BATCH % 32 == 0, "batches cover whole mask words");
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)part, (short)0, n * n_rows * (int)sizeof(float), 0x00020000);
     float y = 0.0f, blk = 0.0f;
     bool first = true;
-    for (int s0 = 0; s0 < n; s0 += BATCH) {
-        float v[BATCH];
+    float v[BATCH];
+    auto load = [&](int s0) {
 #pragma unroll
         for (int u = 0; u < BATCH; ++u)
-            v[u] = s0 + u < n ? load_agent(part + (size_t)(s0 + u) * n_rows + r) : 0.0f;
+            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                rs, ((s0 + u) * n_rows + r) * 4, 0, kBufAgent));
+    };
+    auto fold = [&](int s0) {
 #pragma unroll
         for (int h = 0; h < BATCH / 32; ++h) {
             const uint32_t w = seg_end_word(ends, (s0 >> 5) + h);
@@ -635,6 +603,13 @@ __device__ __forceinline__ float sum_partials(const float *part, int n, int n_ro
                 }
             }
         }
+    };
+    load(0);
+    if (!after_first()) return 0.0f;
+    fold(0);
+    for (int s0 = BATCH; s0 < n; s0 += BATCH) {
+        load(s0);
+        fold(s0);
     }
     return y;
 }

@@ -80,12 +80,15 @@ rtc_status validate_wfs(const rtc_wfs_desc &w) {
 }
 
 // Segments of a matrix: each column block cut into nearly equal parts of at
-// most max_seg vectors, in block order.  A segment is one wavefront's work on
+// most max_seg vectors (and at least n_min[b] parts, when given), in block
+// order.  A segment is one wavefront's work on
 // one 64-row tile (per-launch MVM and frame loop alike) and owns one partial.
-void build_segments(const std::vector<KBlock> &kbs, int max_seg, std::vector<Segment> &seg) {
+void build_segments(const std::vector<KBlock> &kbs, int max_seg, std::vector<Segment> &seg,
+                    const std::vector<int> *n_min) {
     for (size_t b = 0; b < kbs.size(); ++b) {
         const int kv = kbs[b].kv;
-        const int n = (kv + max_seg - 1) / max_seg;
+        int n = (kv + max_seg - 1) / max_seg;
+        if (n_min != nullptr) n = std::max(n, std::min((*n_min)[b], kv));
         for (int i = 0; i < n; ++i) {
             const int a = (int)((int64_t)kv * i / n), z = (int)((int64_t)kv * (i + 1) / n);
             seg.push_back(Segment{(int32_t)b, a, z - a, 0});
@@ -272,7 +275,30 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
                       (int64_t)last_nr * L.kv * 16;
     }
     I->spad_len = spad;
-    build_segments(I->kb, std::min(segment_vectors(I->d.cm_dtype), kMaxSegVectors), I->seg);
+    // The last block of each sensor is multiplied after the frame's last chunk,
+    // on the latency path, while the earlier blocks had the readout to run:
+    // those last blocks are cut into more segments, so that their tasks
+    // (segments x tiles) cover the device's wavefronts (two workgroups of four
+    // per CU), down to kMinLastSegVectors vectors a segment.
+    std::vector<int> n_min(I->kb.size(), 1);
+    {
+        std::vector<int> last(I->wfs.size(), -1);
+        for (size_t b = 0; b < I->kb.size(); ++b) last[I->kb[b].wfs] = (int)b;
+        int n_last = 0;
+        for (int b : last) n_last += b >= 0 ? 1 : 0;
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, e->device) !=
+                hipSuccess ||
+            cus < 1)
+            return RTC_E_DEVICE;
+        const int want = (8 * cus + n_last * n_tiles - 1) / std::max(1, n_last * n_tiles);
+        for (int b : last)
+            if (b >= 0)
+                n_min[b] = std::min(want, (I->kb[b].kv + kMinLastSegVectors - 1) /
+                                              kMinLastSegVectors);
+    }
+    build_segments(I->kb, std::min(segment_vectors(I->d.cm_dtype), kMaxSegVectors), I->seg,
+                   &n_min);
     I->kb_seg0.assign(I->kb.size(), 0);
     I->kb_nseg.assign(I->kb.size(), 0);
     for (size_t i = 0; i < I->seg.size(); ++i) {
@@ -301,13 +327,12 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
         I->m_bytes = L.base + (int64_t)(n_tiles - 1) * kTileRows * L.kv * 16 +
                      (int64_t)last_nr * L.kv * 16;
         I->a_len = nb * kPolcBlock;
-        build_segments(I->kbm, kMaxSegVectors, I->segm);
+        build_segments(I->kbm, kMaxSegVectors, I->segm, nullptr);
         if (I->segm.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
         I->segm_ends = segment_ends(I->segm);
     } else {
         I->a_len = I->n_act;
     }
-    (void)e;
     return RTC_OK;
 }
 

@@ -68,6 +68,7 @@ struct PersistInstState {
     size_t n_ctr = 0;
     uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
     uint64_t *tile_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
+    uint64_t *tile_pub = nullptr, *pol_seg = nullptr;
     int n_cen_all = 0;             // centroid tasks of a frame
     int n_ing_all = 0;             // ingest pieces of a frame (serving)
     uint64_t *ing_cnt = nullptr;   // [kDepth][n_steps] ingest counters

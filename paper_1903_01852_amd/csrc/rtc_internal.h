@@ -12,6 +12,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kTileRows = 64;      // matrix rows per MVM tile: one row per lane
 constexpr int kPolcBlock = 512;    // command elements per POLC column block
 constexpr int kMaxSegVectors = 128; // longest MVM segment (16-byte vectors per row; its slopes sit in LDS)
+constexpr int kMinLastSegVectors = 16;  // shortest segment of a sensor's last column block
 constexpr int kEndWordsPerLane = 4; // block-end mask words each lane holds in a reduction
 constexpr int kMaxSegments = kEndWordsPerLane * kWave * 32;   // segments of one matrix
 constexpr int kMaxShPx = 16;       // largest SH subaperture side (pixels)
@@ -220,6 +221,8 @@ struct PersistInst {
     uint64_t *join;                // [kDepth][n_tiles] accumulation joins
     uint64_t *pol_cnt;             // [kDepth][n_tiles] POLC partials of a tile
     uint64_t *p_done;              // [n_tiles] q + 1 of the last POLC term reduced
+    uint64_t *tile_pub;            // [n_tiles] q + 1 of the last commands written
+    uint64_t *pol_seg;             // [kDepth][n_segm] POLC tasks of a segment done reading a_q
     uint64_t *db_mirror;           // device copy of the doorbells, per sensor
     uint64_t *drop_mirror;         // per mailbox slot: q + 1 of a dropped frame
     // frame source

@@ -101,12 +101,17 @@ __device__ __forceinline__ void tile_epilogue(const MvmEpilogue &E, const float 
     // across lanes); lanes past a short tile read row 0's partials
     const SegEnds ends = load_seg_ends(E.seg_ends, E.n_parts, lane);
     const int r = t * kTileRows + (lane < nr ? lane : 0);
-    // the integrator's operands load beside the partials
+    // the integrator's operands load beside the first partials
     const bool integ = E.mode == EPI_INTEGRATE;
-    const float sc = integ && E.scale != nullptr ? E.scale[r] : 1.0f;
-    const float pp = integ && E.p != nullptr ? E.p[r] : 0.0f;
-    const float ap = integ ? E.a[r] : 0.0f;
-    float y = sum_partials<64>(part, E.n_parts, n_rows, r, ends);
+    float sc = 1.0f, pp = 0.0f, ap = 0.0f;
+    float y = sum_partials<64>(part, E.n_parts, n_rows, r, ends, [&] {
+        if (integ) {
+            if (E.scale != nullptr) sc = E.scale[r];
+            if (E.p != nullptr) pp = E.p[r];
+            ap = E.a[r];
+        }
+        return true;
+    });
     if (lane >= nr) return;
     if (!integ) {
         E.y[r] = y;

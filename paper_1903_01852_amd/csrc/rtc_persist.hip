@@ -76,7 +76,7 @@ __device__ __forceinline__ void drain() {
 __device__ __forceinline__ bool stopping(ArgsRef A) {
     return __hip_atomic_load(gbl(A.stop_dev), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
-__device__ void watchdog_expired(ArgsRef A) {
+__device__ __forceinline__ void watchdog_expired(ArgsRef A) {
     __hip_atomic_store(gbl(A.status), (uint32_t)PERSIST_WATCHDOG, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(gbl(A.stop_dev), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -110,13 +110,8 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
 // Timeline record (rtc_trace_enable): this wavefront's events of one frame.
 struct Trace {
     uint64_t *rec = nullptr;        // null when not recorded
-    uint64_t chain_ticks = 0;
-    uint64_t chain_blocks = 0;
-    __device__ void stamp(int ev, int lane) const {
+    __device__ __forceinline__ void stamp(int ev, int lane) const {
         if (rec != nullptr && lane == 0) gbl(rec)[ev] = wall_clock64();
-    }
-    __device__ void put(int ev, uint64_t v, int lane) const {
-        if (rec != nullptr && lane == 0) gbl(rec)[ev] = v;
     }
 };
 
@@ -152,7 +147,7 @@ __device__ __forceinline__ uint64_t fan_target(InstRef I, uint64_t q, int n) {
 // == s (a stripe's quota is the number of such j below n).  The wavefront's
 // stores must be drained.  True, on every lane, for the arrival that
 // completes the barrier.
-__device__ bool fan_arrive(InstRef I, uint64_t *grp, uint64_t q, int n, uint32_t cnt, int lane) {
+__device__ __forceinline__ bool fan_arrive(InstRef I, uint64_t *grp, uint64_t q, int n, uint32_t cnt, int lane) {
     bool done = false;
     if (cnt != 0) {
         const uint64_t quota = (uint64_t)((n - lane + kFanStripes - 1) / kFanStripes);
@@ -165,6 +160,16 @@ __device__ bool fan_arrive(InstRef I, uint64_t *grp, uint64_t q, int n, uint32_t
 // The lane holding task j's stripe count.
 __device__ __forceinline__ bool stripe_lane(int j, int lane) {
     return lane == (int)((unsigned)j % kFanStripes);
+}
+
+// Tiles of frame q whose commands are out: one counter (a frame has at most a
+// few hundred tiles, and they arrive over microseconds), so the last tile
+// publishes after a single atomic.
+__device__ __forceinline__ uint64_t *tiles_out(InstRef I, uint64_t q) {
+    return fan_top(fan_grp(I.tile_fan, q, 1, 0));
+}
+__device__ __forceinline__ uint64_t tiles_target(InstRef I, uint64_t q) {
+    return par_target(I, q, (uint64_t)I.n_tiles);
 }
 
 // First task index of this worker among n tasks whose task 0 goes to `base`.
@@ -204,7 +209,6 @@ __device__ __forceinline__ int vec_elems(int dtype) {
 // two round trips overlap.  rev streams the vectors last to first.
 constexpr int kLoopBatch = 8;
 constexpr int kLoopLdsFloats = ((kMaxSegVectors + kLoopBatch - 1) / kLoopBatch + 1) * kLoopBatch * 16;
-constexpr int kBufAgent = 16;      // buffer-access cache policy: agent coherent (sc1)
 template <int DT, bool REV>
 __device__ __forceinline__ float loop_task(const uint8_t *cm, const KBlock &K, const Segment &S,
                                            int t, int nr, int lane, const float *xs,
@@ -293,13 +297,21 @@ __device__ __forceinline__ void frame_coef(InstRef I, uint64_t q, float &c1, flo
     if (I.serving) {
         // device mirror, refreshed by the sentinel before it mirrors any
         // doorbell that follows a host parameter change
+        // (both slots are read with the word, not after it: a slot a frame
+        // selects was mirrored before the doorbells of that frame, which this
+        // wavefront has already seen)
         const ParamBlock *pb = I.param_mirror;
         const uint64_t word = ld_agent64(&pb->word);
+        float c1s[2], gs[2];
+        for (int k = 0; k < 2; ++k) {
+            c1s[k] = __hip_atomic_load(gbl(&pb->c1[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            gs[k] = __hip_atomic_load(gbl(&pb->g[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         const uint64_t qs = word >> 1;
         const int staged = (int)(word & 1);
         const int s = q >= qs ? staged : 1 - staged;
-        c1 = __hip_atomic_load(gbl(&pb->c1[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        g = __hip_atomic_load(gbl(&pb->g[s]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        c1 = s ? c1s[1] : c1s[0];
+        g = s ? gs[1] : gs[0];
     } else {
         const int s = q >= I.coef.q_switch ? 1 : 0;
         c1 = I.coef.c1[s];
@@ -311,7 +323,7 @@ __device__ __forceinline__ void frame_coef(InstRef I, uint64_t q, float &c1, flo
 // Sentinel of a serving instance: mirror the host doorbells, parameters and
 // drop marks into device memory, stamp each frame's last chunk, relay a stop
 // request.
-__device__ void sentinel(InstRef I, ArgsRef A, int lane) {
+__device__ __forceinline__ void sentinel(InstRef I, ArgsRef A, int lane) {
     const int nw = I.n_wfs;
     int nch = 0;          // lane w: chunks per frame of sensor w
     for (int st = 0; st < I.n_steps; ++st) {
@@ -387,11 +399,12 @@ __device__ void sentinel(InstRef I, ArgsRef A, int lane) {
                 const uint64_t na = (uint64_t)min(I.n_tiles, kFanStripes);
                 uint64_t pub = 0, pol = 0;
                 for (int k = 0; k < kDepth; ++k) {
-                    pub += ld_agent64(fan_top(fan_grp(I.tile_fan, k, 1, 0)));
+                    pub += ld_agent64(tiles_out(I, k));
                     pol += ld_agent64(fan_top(fan_grp(I.pol_fan, k, 1, 0)));
                 }
                 const uint64_t nf = seen_q - I.q_begin;   // counters start at the launch
-                quiet = __all(none) && pub == nf * na && (!I.polc || pol == nf * na);
+                quiet = __all(none) && pub == nf * (uint64_t)I.n_tiles &&
+                        (!I.polc || pol == nf * na);
             }
             if (stop != 0 || quiet) {
                 __hip_atomic_store(gbl(A.stop_dev), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -440,20 +453,51 @@ __device__ __forceinline__ bool join(InstRef I, uint64_t q, int t, int lane) {
     return (old + 1) % join_need(I) == 0;
 }
 
+// Operands of row r's commands for frame q other than its reconstruction sum.
+// The frame's coefficients, FP8 row scale and drop mark are settled before
+// any wavefront starts the frame, so they may be loaded early (beside the
+// sum); the previous commands and the POLC term come from the join's other
+// parties and are loaded only once the join is complete.
+struct RowOps {
+    float c1, g, scale, p, aprev;
+    bool dropped;
+    uint64_t a_free;   // POLC: tasks of frame q - 2 done reading the tile's columns
+};
+// With POLC, the tile's commands of frame q overwrite those of frame q - 2,
+// which the POLC tasks of frame q - 2 on the tile's columns (one segment: a
+// POLC block is one segment and a whole number of tiles) may still read.
+static_assert(kPolcBlock / 4 <= kMaxSegVectors && kPolcBlock % kTileRows == 0,
+              "a tile's columns lie in one POLC segment");
+__device__ __forceinline__ uint64_t *a_free_ctr(InstRef I, uint64_t q, int t) {
+    return slot(I.pol_seg, (size_t)dslot(q) * I.n_segm + t * kTileRows / kPolcBlock);
+}
+__device__ __forceinline__ void row_ops_early(InstRef I, uint64_t q, int r, RowOps &o) {
+    o.a_free = I.polc && q >= I.q_begin + 2 ? ld_agent64(a_free_ctr(I, q - 2, r / kTileRows))
+                                             : ~0ull;
+    frame_coef(I, q, o.c1, o.g);
+    const float *scale = I.dtype == RTC_CM_FP8 ? I.scale[mat_slot(I, q)] : nullptr;
+    o.scale = scale != nullptr ? gbl(scale)[r] : 1.0f;
+    o.dropped = I.serving && ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
+}
+__device__ __forceinline__ void row_ops_joined(InstRef I, uint64_t q, int r, RowOps &o) {
+    o.p = I.polc ? load_agent(I.p + r) : 0.0f;
+    o.aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
+}
+
 // Commands of tile t for frame q from the reconstruction sum y of row r: the
 // FP8 row scale, the POLC term and the leaky integrator (a dropped serving
 // frame keeps the previous commands), then publication.
-__device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, float y, int lane) {
+__device__ __forceinline__ void tile_commands(InstRef I, ArgsRef A, uint64_t q, int t, int r,
+                                              bool row, float y, const RowOps &o, int lane,
+                                              const Trace &tr) {
+    if (o.a_free != ~0ull && o.a_free < par_target(I, q - 2, (uint64_t)I.n_tiles) &&
+        !wait_geq(a_free_ctr(I, q - 2, t), par_target(I, q - 2, (uint64_t)I.n_tiles), A,
+                  A.dep_watchdog))
+        return;
     if (row) {
-        float c1, g;
-        frame_coef(I, q, c1, g);
-        const float *scale = I.dtype == RTC_CM_FP8 ? I.scale[mat_slot(I, q)] : nullptr;
-        if (scale != nullptr) y *= gbl(scale)[r];
-        if (I.polc) y += load_agent(I.p + r);
-        const float aprev = load_agent(a_buf(I, q ^ 1) + r);   // buffer of frame q - 1
-        bool dropped = false;
-        if (I.serving) dropped = ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
-        const float an = dropped ? aprev : fmaf(c1, aprev, g * y);
+        if (I.dtype == RTC_CM_FP8) y *= o.scale;
+        if (I.polc) y += o.p;
+        const float an = o.dropped ? o.aprev : fmaf(o.c1, o.aprev, o.g * y);
         st_agent(a_buf(I, q) + r, an);
         if (I.serving) {
             st_sys(I.mail + (size_t)(q % (uint64_t)I.ring_depth) * I.n_act + r, an);
@@ -463,9 +507,9 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
             gbl(I.cmds_out)[(size_t)(q - I.q_begin) * I.n_act + r] = an;
     }
     drain();
-    const bool all = fan_arrive(I, fan_grp(I.tile_fan, q, 1, 0), q, I.n_tiles,
-                                stripe_lane(t, lane) ? 1u : 0u, lane);
-    if (all && I.serving && lane == 0) {
+    tr.stamp(RTC_TRACE_CMDS, lane);
+    if (lane == 0) st_agent64(slot(I.tile_pub, t), q + 1);
+    if (lane == 0 && add_agent64(tiles_out(I, q), 1) + 1 == tiles_target(I, q) && I.serving) {
         FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
         __hip_atomic_store(gbl(&tel->ticks_publish), wall_clock64(), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_SYSTEM);
@@ -475,33 +519,94 @@ __device__ void tile_commands(InstRef I, uint64_t q, int t, int r, bool row, flo
 
 // The tile's reconstruction sum for row r: its segment partials of the frame,
 // block by block in readout order, the block ends from the mask (every lane
-// holds its words; r of lanes past a short tile is clamped).
+// holds its words; r of lanes past a short tile is clamped); the row's other
+// operands are loaded with the first partials.
 constexpr int kSumBatch = 64;
-__device__ __forceinline__ float tile_sum(InstRef I, uint64_t q, int r, const SegEnds &ends) {
-    return sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, r, ends);
+__device__ __forceinline__ float tile_sum(InstRef I, uint64_t q, int r, const SegEnds &ends,
+                                          RowOps &o) {
+    return sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, r, ends, [&] {
+        row_ops_early(I, q, r, o);
+        row_ops_joined(I, q, r, o);
+        return true;
+    });
 }
 
-// Commands of tile t for frame q, then of every following frame whose join
-// this completes.  Returns the number of frames done.
-__device__ int finish_chain(InstRef I, uint64_t q, int t, int lane) {
+// Commands of tile t for frame q from its sum y, then of every following frame
+// whose join this completes.  Returns the number of frames done.
+__device__ __forceinline__ int finish_chain(InstRef I, ArgsRef A, uint64_t q, int t, int lane,
+                                            const Trace &tr, float y, const RowOps &o0,
+                                            const SegEnds &ends) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int r = t * kTileRows + lane;
-    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
+    const int rc = t * kTileRows + (lane < nr ? lane : 0);
+    tile_commands(I, A, q, t, r, lane < nr, y, o0, lane, tr);
     for (int done = 1;; ++done) {
-        const float y = tile_sum(I, q, t * kTileRows + (lane < nr ? lane : 0), ends);
-        tile_commands(I, q, t, r, lane < nr, y, lane);
         ++q;
         if (q >= I.q_end || !join(I, q, t, lane)) return done;
+        RowOps o;
+        y = tile_sum(I, q, rc, ends, o);
+        tile_commands(I, A, q, t, r, lane < nr, y, o, lane, tr);
     }
 }
 
-// The accumulation a completed join starts, timed into the frame's record.
-__device__ __forceinline__ void accumulate(InstRef I, uint64_t q, int t, int lane, Trace &tr) {
-    const uint64_t t0 = tr.rec != nullptr ? wall_clock64() : 0;
-    const int n = finish_chain(I, q, t, lane);
-    if (tr.rec != nullptr) {
-        tr.chain_ticks += wall_clock64() - t0;
-        tr.chain_blocks += (uint64_t)n;
+// The accumulation a completed join starts, stamped into the frame's record.
+__device__ __forceinline__ void accumulate(InstRef I, ArgsRef A, uint64_t q, int t, int lane,
+                                           Trace &tr) {
+    const int nr = min(kTileRows, I.n_act - t * kTileRows);
+    const int rc = t * kTileRows + (lane < nr ? lane : 0);
+    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
+    RowOps o;
+    const float y = tile_sum(I, q, rc, ends, o);
+    (void)finish_chain(I, A, q, t, lane, tr, y, o, ends);
+    tr.stamp(RTC_TRACE_ACCUM, lane);
+}
+
+// The (E) party of (q, t), whose partials are all stored (its arrival saw
+// every partial's count): the first batch of the sum and the early row
+// operands are issued with the join's atomic, so those round trips overlap;
+// the sum is abandoned when the join is not complete (its last party does
+// the work), else the operands the other parties wrote follow.
+__device__ __forceinline__ void tile_ready(InstRef I, ArgsRef A, uint64_t q, int t, int lane,
+                                           Trace &tr) {
+    const int nr = min(kTileRows, I.n_act - t * kTileRows);
+    const int rc = t * kTileRows + (lane < nr ? lane : 0);
+    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
+    RowOps o;
+    bool joined = false;
+    const float y = sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, rc, ends, [&] {
+        row_ops_early(I, q, rc, o);
+        joined = join(I, q, t, lane);
+        if (joined) row_ops_joined(I, q, rc, o);
+        return joined;
+    });
+    if (!joined) return;
+    tr.stamp(RTC_TRACE_SUMMED, lane);
+    (void)finish_chain(I, A, q, t, lane, tr, y, o, ends);
+    tr.stamp(RTC_TRACE_ACCUM, lane);
+}
+
+// Spin until tiles [t0, t1] (fewer than kWave of them) and tile tr have
+// written their commands of frame q: lane i < kWave - 1 polls tile t0 + i,
+// the last lane tile tr, so the pollers of a frame's POLC tasks spread over
+// the tiles' flags instead of one counter that the tiles' own arrivals update.
+static_assert(kMaxSegVectors * 4 / kTileRows + 1 < kWave, "a POLC segment spans few tiles");
+__device__ __forceinline__ bool wait_tiles(InstRef I, ArgsRef A, uint64_t q, int t0, int t1,
+                                           int tr, int lane) {
+    const int t = lane == kWave - 1 ? tr : t0 + lane;
+    bool ok = (lane < kWave - 1 && t > t1) || ld_agent64(slot(I.tile_pub, t)) >= q + 1;
+    if (__all(ok)) return true;
+    const uint64_t c0 = wall_clock64();
+    for (uint32_t it = 1;; ++it) {
+        __builtin_amdgcn_s_sleep(2);
+        ok = ok || ld_agent64(slot(I.tile_pub, t)) >= q + 1;
+        if (__all(ok)) return true;
+        if ((it & 31) == 0) {
+            if (stopping(A)) return false;
+            if (wall_clock64() - c0 > A.dep_watchdog) {
+                watchdog_expired(A);
+                return false;
+            }
+        }
     }
 }
 
@@ -512,19 +617,26 @@ __device__ __forceinline__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int
     const int n_tasks = I.n_segm * I.n_tiles;
     int j = first_task(rank, nw, rot(q, n_tasks, nw));
     if (j >= n_tasks) return true;
-    if (!wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q, I.n_tiles), A,
-                  A.dep_watchdog))
-        return false;
     const float *aq = a_buf(I, q);
     float *part = I.p_part[dslot(q)];
-    // the POLC matrix of frame q's slot: the product completes frame q
-    const int ms = mat_slot(I, q);
     for (; j < n_tasks; j += nw) {
         const int sg = j / I.n_tiles;
         const int t = j - sg * I.n_tiles;
         const Segment S = ldc(I.segm + sg);
         const KBlock K = ldc(I.kbm + S.kb);
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
+        // the segment's commands of frame q (its tiles published), and tile
+        // t's own: its commands of frame q have read p, which this task's
+        // reduction may overwrite with the next frame's term
+        const int c0 = K.k0 + S.v0 * 4;
+        if (!wait_tiles(I, A, q, c0 / kTileRows, (min(c0 + S.nv * 4, I.n_act) - 1) / kTileRows, t,
+                        lane))
+            return false;
+        // the POLC matrix of frame q's slot (the product completes frame q),
+        // read once frame q has published commands: a worker with no task of
+        // the frame may reach this before the frame's chunks, and a matrix
+        // swap, have arrived
+        const int ms = mat_slot(I, q);
         const float v = loop_task<RTC_CM_F32, false>(I.M[ms], K, S, t, nr, lane,
                                                      aq + K.spad + S.v0 * 4, lds);
         // p_part copy of frame q is free once frame q - kDepth's term of the tile
@@ -535,12 +647,15 @@ __device__ __forceinline__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int
         if (lane < nr) st_agent(part + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
         uint64_t old = 0;
-        if (lane == 0) old = add_agent64(slot(I.pol_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
+        if (lane == 0) {
+            add_agent64(slot(I.pol_seg, (size_t)dslot(q) * I.n_segm + sg), 1);   // a_q read
+            old = add_agent64(slot(I.pol_cnt, (size_t)dslot(q) * I.n_tiles + t), 1);
+        }
         old = __shfl(old, 0, kWave);
         if (old + 1 != par_target(I, q, (uint64_t)I.n_segm)) continue;
         const SegEnds ends = load_seg_ends(I.segm_ends, I.n_segm, lane);
         const int r = t * kTileRows + (lane < nr ? lane : 0);
-        const float y = sum_partials<kSumBatch>(part, I.n_segm, I.n_act, r, ends);
+        const float y = sum_partials<kSumBatch>(part, I.n_segm, I.n_act, r, ends, [] { return true; });
         if (lane < nr) st_agent(I.p + r, y);
         drain();
         if (lane == 0) st_agent64(slot(I.p_done, t), q + 1);
@@ -549,7 +664,7 @@ __device__ __forceinline__ bool polc_tasks(InstRef I, ArgsRef A, uint64_t q, int
         if (all && I.serving && lane == 0)
             __hip_atomic_store(gbl(I.pol_seq), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         // (P) party of frame q + 1 on this tile
-        if (q + 1 < I.q_end && join(I, q + 1, t, lane)) accumulate(I, q + 1, t, lane, tr);
+        if (q + 1 < I.q_end && join(I, q + 1, t, lane)) accumulate(I, A, q + 1, t, lane, tr);
     }
     return true;
 }
@@ -624,8 +739,9 @@ __device__ __forceinline__ void centroid_tasks(InstRef I, uint64_t q, const KbWo
 // the block's slopes must be complete.  Each task counts on its tile's
 // counter; the arrival completing the tile's partials of the frame (every
 // segment of every block) is the tile's (E) party.
-__device__ __forceinline__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W, int kb, int nw, int lane,
-                          RTC_LDS float *lds, int &m, Trace &tr, int budget = 1 << 30) {
+__device__ __forceinline__ void mvm_tasks(InstRef I, ArgsRef A, uint64_t q, const KbWork &W, int kb,
+                                          int nw, int lane, RTC_LDS float *lds, int &m, Trace &tr,
+                                          int budget = 1 << 30) {
     const int n_tiles = I.n_tiles;
     const int end = W.mvm_base + W.nseg * n_tiles;
     if (m >= end) return;
@@ -650,7 +766,8 @@ __device__ __forceinline__ void mvm_tasks(InstRef I, uint64_t q, const KbWork &W
         old = __shfl(old, 0, kWave);
         if (old + 1 != par_target(I, q, (uint64_t)I.n_seg)) continue;
         // (E) party: the tile's reconstruction sum is ready
-        if (join(I, q, t, lane)) accumulate(I, q, t, lane, tr);
+        tr.stamp(RTC_TRACE_TILE_READY, lane);
+        tile_ready(I, A, q, t, lane, tr);
     }
     tr.stamp(RTC_TRACE_MVM_LAST, lane);
 }
@@ -664,16 +781,13 @@ __device__ __forceinline__ Trace trace_of(InstRef I, ArgsRef A, uint64_t q, int 
     return tr;
 }
 __device__ __forceinline__ void trace_end(Trace &tr, int lane) {
-    tr.put(RTC_TRACE_CHAIN_TICKS, tr.chain_ticks, lane);
-    tr.put(RTC_TRACE_CHAIN_BLOCKS, tr.chain_blocks, lane);
     tr.stamp(RTC_TRACE_FRAME_END, lane);
 }
 
 // Frame gate: frame q reuses the buffers and counters of frame q - kDepth.
 __device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
     return q < I.q_begin + kDepth ||
-           wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q - kDepth, I.n_tiles),
-                    A, A.dep_watchdog);
+           wait_geq(tiles_out(I, q), tiles_target(I, q - kDepth), A, A.dep_watchdog);
 }
 
 // Serving ingest: copy this worker's pieces of readout step `st` (frame q)
@@ -683,34 +797,35 @@ __device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
 // not the bytes); stores are 16-byte agent-coherent, so wavefronts on any XCD
 // read the new frame.  Buffer accesses are range-checked against each ring.
 constexpr int kIngestPerLane = kIngestUnits / kWave;
-__device__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int nw, int lane,
+static_assert(kIngestPerLane * kWave == kIngestUnits, "a piece is whole loads of the wavefront");
+static_assert(kTelUnits % (4 * kWave) == 0, "a telemetry task is whole rounds of four loads");
+__device__ __forceinline__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int nw, int lane,
                              int &j) {
     const int end = S.ing0 + S.ing_n;
     if (j >= end) return;
     const int w = S.wfs;
-    const uint32_t nrec = (uint32_t)I.ring_bytes[w];
-    __amdgpu_buffer_rsrc_t hsrc =
-        __builtin_amdgcn_make_buffer_rsrc((void *)I.ring_host[w], (short)0, (int)nrec, 0x00020000);
-    __amdgpu_buffer_rsrc_t ddst =
-        __builtin_amdgcn_make_buffer_rsrc((void *)I.src[w], (short)0, (int)nrec, 0x00020000);
-    const uint32_t base =
-        (uint32_t)((q % (uint64_t)I.ring_depth) * (uint64_t)I.src_stride[w] / 8) + (uint32_t)S.u0;
+    // both buffers span exactly the step's units of this frame's ring slot:
+    // every access is issued without a condition (no branch, so the loads stay
+    // in flight together and each store waits for its own load only), and the
+    // range check drops a last piece's units past the step
+    const uint64_t off =
+        ((q % (uint64_t)I.ring_depth) * (uint64_t)I.src_stride[w] / 8 + (uint64_t)S.u0) * 16;
+    const int nbytes = S.n16 * 16;
+    __amdgpu_buffer_rsrc_t hsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((const uint8_t *)I.ring_host[w] + off), (short)0, nbytes, 0x00020000);
+    __amdgpu_buffer_rsrc_t ddst = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((const uint8_t *)I.src[w] + off), (short)0, nbytes, 0x00020000);
     constexpr int kSys = 1 | 16, kAgent = 16;   // cache policy: sc0 sc1, sc1
     uint64_t cnt = 0;
     for (; j < end; j += nw, ++cnt) {
         const int u0 = (j - S.ing0) * kIngestUnits;
-        const int u1 = min(S.n16, u0 + kIngestUnits);
         vec16_t v[kIngestPerLane];
 #pragma unroll
-        for (int k = 0; k < kIngestPerLane; ++k) {
-            const int u = u0 + k * kWave + lane;
-            if (u < u1) v[k] = __builtin_amdgcn_raw_buffer_load_b128(hsrc, (base + u) * 16, 0, kSys);
-        }
+        for (int k = 0; k < kIngestPerLane; ++k)
+            v[k] = __builtin_amdgcn_raw_buffer_load_b128(hsrc, (u0 + k * kWave + lane) * 16, 0, kSys);
 #pragma unroll
-        for (int k = 0; k < kIngestPerLane; ++k) {
-            const int u = u0 + k * kWave + lane;
-            if (u < u1) __builtin_amdgcn_raw_buffer_store_b128(v[k], ddst, (base + u) * 16, 0, kAgent);
-        }
+        for (int k = 0; k < kIngestPerLane; ++k)
+            __builtin_amdgcn_raw_buffer_store_b128(v[k], ddst, (u0 + k * kWave + lane) * 16, 0, kAgent);
     }
     drain();
     if (lane == 0) add_agent64(slot(I.ing_cnt, (size_t)dslot(q) * I.n_steps + st), cnt);
@@ -720,13 +835,12 @@ __device__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int n
 // copies 16-byte units [j kTelUnits, (j + 1) kTelUnits) of its record from the
 // device ring to the pinned host ring (agent-coherent loads, system-coherent
 // stores), then sets its flag.  Off the frame's latency path.
-__device__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane) {
+__device__ __forceinline__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q, int rank, int nw, int lane) {
     const int n16 = I.tel_rec / 4;
     const int n_tasks = (n16 + kTelUnits - 1) / kTelUnits;
     int j = first_task(rank, nw, rot(q, n_tasks, nw));
     if (j >= n_tasks) return true;
-    if (!wait_geq(fan_top(fan_grp(I.tile_fan, q, 1, 0)), fan_target(I, q, I.n_tiles), A,
-                  A.dep_watchdog))
+    if (!wait_geq(tiles_out(I, q), tiles_target(I, q), A, A.dep_watchdog))
         return false;
     const uint64_t ts = (q >> I.tel_dshift) & (uint64_t)I.tel_smask;
     const int bytes = n16 * 16;
@@ -737,18 +851,18 @@ __device__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q, int rank, int n
     constexpr int kSys = 1 | 16, kAgent = 16;   // cache policy: sc0 sc1, sc1
     for (; j < n_tasks; j += nw) {
         const int u1 = min(n16, (j + 1) * kTelUnits);
+        // a unit past u1 lies past the record (tasks cover whole multiples of
+        // 4 kWave units), so the buffers' range checks drop it
         for (int u0 = j * kTelUnits; u0 < u1; u0 += 4 * kWave) {
             vec16_t v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int u = u0 + k * kWave + lane;
-                if (u < u1) v[k] = __builtin_amdgcn_raw_buffer_load_b128(src, u * 16, 0, kAgent);
-            }
+            for (int k = 0; k < 4; ++k)
+                v[k] = __builtin_amdgcn_raw_buffer_load_b128(src, (u0 + k * kWave + lane) * 16, 0,
+                                                             kAgent);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int u = u0 + k * kWave + lane;
-                if (u < u1) __builtin_amdgcn_raw_buffer_store_b128(v[k], dst, u * 16, 0, kSys);
-            }
+            for (int k = 0; k < 4; ++k)
+                __builtin_amdgcn_raw_buffer_store_b128(v[k], dst, (u0 + k * kWave + lane) * 16, 0,
+                                                       kSys);
         }
         drain();
         if (lane == 0)
@@ -791,6 +905,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
         const int n_steps = I.n_steps, n_tiles = I.n_tiles;
         int is = 0, ic = 0, cs = 0, ms = 0;   // next step to ingest, known ingested, slopes, MVM
         uint32_t idle = 0;
+        bool last_seen = false;   // an MVM task of the frame's last block started
         while (is < n_steps || cs < n_steps || ms < n_steps) {
             bool progressed = false;
             // ingest of every delivered chunk
@@ -799,7 +914,9 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                 if (ing < S.ing0 + S.ing_n) {
                     if (!db_reached(ld_agent64(I.db_mirror + S.wfs), q, (uint64_t)S.chunk + 1))
                         break;
+                    tr.stamp(RTC_TRACE_INGEST_START, lane);
                     ingest_tasks(I, q, S, is, nw, lane, ing);
+                    tr.stamp(RTC_TRACE_INGEST, lane);
                     progressed = true;
                 }
                 ++is;
@@ -822,6 +939,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     }
                     if (ic <= cs) break;
                     uint32_t cnt = 0;
+                    tr.stamp(RTC_TRACE_CEN_START, lane);
                     centroid_tasks(I, q, W, nw, lane, so, false, ft.cen, cnt);
                     drain();
                     (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt,
@@ -845,7 +963,11 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     continue;
                 }
                 if (block_ready(I, q, W, S.kb)) {
-                    mvm_tasks(I, q, W, S.kb, nw, lane, lds, ft.mvm, tr, 1);
+                    if (S.kb == I.n_kb - 1 && !last_seen) {
+                        tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
+                        last_seen = true;
+                    }
+                    mvm_tasks(I, A, q, W, S.kb, nw, lane, lds, ft.mvm, tr, 1);
                     if (ft.mvm >= end) ++ms;
                     progressed = true;
                 }
@@ -916,7 +1038,7 @@ __device__ __forceinline__ void batch_worker(InstRef I, ArgsRef A, int wid, int 
         int m = frame_tasks(I, q, rank, nw).mvm;
         const int n_kb = I.n_kb, n_all = I.n_seg * I.n_tiles;
         for (int kb = 0; kb < n_kb && m < n_all; ++kb)
-            mvm_tasks(I, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr);
+            mvm_tasks(I, A, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr);
         if (I.polc && q > q0 && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
         trace_end(tr, lane);
     }
@@ -956,8 +1078,9 @@ k_frame_loop_serve(PersistArgs args) {
 }
 
 // Batch form: a finite launch over frames already in device memory, at the
-// whole occupancy.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+// whole occupancy (three workgroups per CU: the most that fit without
+// spilling).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_frame_loop_batch(PersistArgs args) {
     RTC_FRAME_LOOP_BODY(false)
 }

@@ -103,6 +103,8 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.join = P.join;
     d.pol_cnt = P.pol_cnt;
     d.p_done = P.p_done;
+    d.tile_pub = P.tile_pub;
+    d.pol_seg = P.pol_seg;
     d.db_mirror = P.db_mirror;
     d.drop_mirror = P.drop_mirror;
     d.ring_depth = e->ring_depth;
@@ -288,9 +290,11 @@ rtc_status persist_alloc(rtc_engine *e) {
         }
         // counters, each in a slot of its own; arrival counters kDepth times:
         // fan-in barriers cen [D][nkb], tile [D], pol [D]; tile_cnt, join and
-        // pol_cnt [D][nt]; p_done [nt] once; ing_cnt [D][n_steps]
-        const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size();
-        const size_t n_slots = D * nkb * fan + 2 * D * fan + 3 * D * nt + nt + D * nst;
+        // pol_cnt [D][nt]; p_done and tile_pub [nt] once; ing_cnt [D][n_steps];
+        // pol_seg [D][n_segm]
+        const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size(), nsm = I->segm.size();
+        const size_t n_slots =
+            D * nkb * fan + 2 * D * fan + 3 * D * nt + 2 * nt + D * nst + D * nsm;
         P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_fan = P.ctr;
@@ -300,7 +304,9 @@ rtc_status persist_alloc(rtc_engine *e) {
         P.join = P.tile_cnt + D * nt * kCtrSlot;
         P.pol_cnt = P.join + D * nt * kCtrSlot;
         P.p_done = P.pol_cnt + D * nt * kCtrSlot;
-        P.ing_cnt = P.p_done + nt * kCtrSlot;
+        P.tile_pub = P.p_done + nt * kCtrSlot;
+        P.ing_cnt = P.tile_pub + nt * kCtrSlot;
+        P.pol_seg = P.ing_cnt + D * nst * kCtrSlot;
         // serving ingest: each readout step's rows as 16-byte units of a ring
         // slot, in pieces, numbered in readout order; the buffer accesses take
         // 32-bit byte offsets

@@ -34,8 +34,9 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_acquire_chunk", "rtc_commit_chunk", "rtc_stage_matrices",
            "rtc_swap_matrices", "rtc_telemetry_enable", "rtc_telemetry_next",
            "rtc_process_frames_noalloc", "rtc_pacer_run")
-TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "chain_ticks",
-                "chain_blocks", "frame_end")
+TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "ingest",
+                "accum", "frame_end", "cen_start", "last_block", "tile_ready", "cmds",
+                "ingest_start", "summed")
 
 
 class RtcError(RuntimeError):

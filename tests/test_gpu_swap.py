@@ -136,6 +136,11 @@ def test_swap_paths_identical(rtc):
         assert eng.swap_matrices(0) == K2
         parts.append(run_stream(eng, 0, case, n=N_FRAMES - K2, first_frame=K2)[0])
         c = np.concatenate(parts)
+    for name, x in (("persistent batch", b), ("serving", c)):
+        bad = np.nonzero(np.any(x != a, axis=1))[0]
+        if bad.size:
+            log(f"  {name}: frames differing from the per-launch path: {bad[:20].tolist()}"
+                f" (of {bad.size}); first max |diff| {np.abs(x[bad[0]] - a[bad[0]]).max():.3e}")
     assert np.array_equal(a, b)
     assert np.array_equal(a, c)
     ref = oracle_switched(case, sets, (K1, K2), N_FRAMES)
