@@ -374,7 +374,7 @@ rtc_status rtc_mvm_timing_read(rtc_engine *e, int32_t inst, int32_t *n, double *
  * frames of that launch, overwriting the previous launch's record; 0 turns the
  * record off (its cost is then one test per frame).  Synchronises the engine;
  * the loop must not be running (RTC_E_STATE otherwise). */
-#define RTC_TRACE_EVENTS 14
+#define RTC_TRACE_EVENTS 15
 enum {
     RTC_TRACE_FRAME_START = 0,   /* the wavefront reached the frame */
     RTC_TRACE_GATE = 1,          /* frame q - 2 published: the frame may start */
@@ -389,7 +389,8 @@ enum {
     RTC_TRACE_TILE_READY = 10,   /* it completed a tile's partials (the sum starts) */
     RTC_TRACE_CMDS = 11,         /* its last tile's commands written (before counting) */
     RTC_TRACE_INGEST_START = 12, /* serving: its last ingest pieces start (doorbell seen) */
-    RTC_TRACE_SUMMED = 13        /* its last tile sum (and command operands) in registers */
+    RTC_TRACE_SUMMED = 13,       /* its last tile sum (and command operands) in registers */
+    RTC_TRACE_JOINED = 14        /* its last join atomic returned (first partials loaded) */
 };
 rtc_status rtc_trace_enable(rtc_engine *e, int32_t n_frames);
 /* Copies the record of the last launch into out (host): value

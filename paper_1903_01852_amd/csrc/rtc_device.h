@@ -569,11 +569,14 @@ __device__ __forceinline__ uint32_t seg_end_word(const SegEnds &m, int wi) {
 // to memory covers a batch.  The first batch is peeled: after its loads are
 // issued, after_first() issues whatever else the caller needs from memory
 // (those round trips then overlap) and returns false to abandon the sum
-// (the result is then 0).  r must be below n_rows.
+// (the result is then 0).  With use_y0, the fold continues from the state y0
+// (read after after_first()) that earlier blocks, ending at a block end, left:
+// the sum of those blocks.  r must be below n_rows.
 constexpr int kBufAgent = 16;
 template <int BATCH, class After>
 __device__ __forceinline__ float sum_partials(const float *part, int n, int n_rows, int r,
-                                              const SegEnds &ends, After &&after_first) {
+                                              const SegEnds &ends, After &&after_first,
+                                              bool use_y0 = false, const float &y0 = 0.0f) {
     static_assert(BATCH % 32 == 0, "batches cover whole mask words");
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)part, (short)0, n * n_rows * (int)sizeof(float), 0x00020000);
@@ -606,6 +609,10 @@ __device__ __forceinline__ float sum_partials(const float *part, int n, int n_ro
     };
     load(0);
     if (!after_first()) return 0.0f;
+    if (use_y0) {
+        y = y0;
+        first = false;
+    }
     fold(0);
     for (int s0 = BATCH; s0 < n; s0 += BATCH) {
         load(s0);

@@ -281,8 +281,8 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
     // (segments x tiles) cover the device's wavefronts (two workgroups of four
     // per CU), down to kMinLastSegVectors vectors a segment.
     std::vector<int> n_min(I->kb.size(), 1);
+    std::vector<int> last(I->wfs.size(), -1);
     {
-        std::vector<int> last(I->wfs.size(), -1);
         for (size_t b = 0; b < I->kb.size(); ++b) last[I->kb[b].wfs] = (int)b;
         int n_last = 0;
         for (int b : last) n_last += b >= 0 ? 1 : 0;
@@ -308,6 +308,19 @@ rtc_status build_instance(rtc_engine *e, Instance *I) {
     }
     if (I->seg.size() > (size_t)kMaxSegments) return RTC_E_INVAL;
     I->seg_ends = segment_ends(I->seg);
+    // Head and tail of the reconstruction sum (frame loop): the tail runs from
+    // the earliest of the sensors' last blocks to the end, the head is every
+    // block before it.  During serving the head's blocks are complete long
+    // before the frame's last chunk, so their part of the sum (the fold's
+    // state after them) is formed off the latency path.
+    {
+        int tail_kb = (int)I->kb.size() - 1;
+        for (int b : last)
+            if (b >= 0) tail_kb = std::min(tail_kb, b);
+        I->n_head_seg = I->kb_seg0[tail_kb];
+        I->tail_ends =
+            segment_ends(std::vector<Segment>(I->seg.begin() + I->n_head_seg, I->seg.end()));
+    }
     // POLC column blocks of kPolcBlock commands, F32
     if (I->d.polc) {
         const int nb = (I->n_act + kPolcBlock - 1) / kPolcBlock;
@@ -344,6 +357,7 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     TRY(dev_alloc(e, &I->d_kbm, std::max<size_t>(I->kbm.size(), 1)));
     TRY(dev_alloc(e, &I->d_seg, I->seg.size()));
     TRY(dev_alloc(e, &I->d_seg_ends, I->seg_ends.size()));
+    TRY(dev_alloc(e, &I->d_tail_ends, I->tail_ends.size()));
     TRY(dev_alloc(e, &I->d_segm_ends, std::max<size_t>(I->segm_ends.size(), 1)));
     TRY(dev_alloc(e, &I->d_segm, std::max<size_t>(I->segm.size(), 1)));
     TRY(dev_alloc(e, &I->d_run, I->seg.size()));
@@ -392,6 +406,7 @@ rtc_status alloc_instance(rtc_engine *e, Instance *I) {
     };
     HIP_TRY(up(I->d_seg, I->seg.data(), I->seg.size() * sizeof(Segment)));
     HIP_TRY(up(I->d_seg_ends, I->seg_ends.data(), I->seg_ends.size() * 4));
+    HIP_TRY(up(I->d_tail_ends, I->tail_ends.data(), I->tail_ends.size() * 4));
     HIP_TRY(up(I->d_segm_ends, I->segm_ends.data(), I->segm_ends.size() * 4));
     HIP_TRY(up(I->d_segm, I->segm.data(), I->segm.size() * sizeof(Segment)));
     const std::vector<SegRun> run = seg_runs(I->kb, I->seg, elems_per_vec(I->d.cm_dtype));

@@ -68,7 +68,8 @@ struct PersistInstState {
     size_t n_ctr = 0;
     uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
     uint64_t *tile_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
-    uint64_t *tile_pub = nullptr, *pol_seg = nullptr;
+    uint64_t *tile_pub = nullptr, *pol_seg = nullptr, *head_cnt = nullptr;
+    float *pre = nullptr;          // [kDepth][n_act] prefixes of the reconstruction sum
     int n_cen_all = 0;             // centroid tasks of a frame
     int n_ing_all = 0;             // ingest pieces of a frame (serving)
     uint64_t *ing_cnt = nullptr;   // [kDepth][n_steps] ingest counters
@@ -128,6 +129,8 @@ struct Instance {
     std::vector<Segment> seg, segm;            // segments: reconstruction, POLC
     std::vector<int> kb_seg0, kb_nseg;         // segments of each column block
     std::vector<uint32_t> seg_ends, segm_ends; // bit j: segment j ends its block (recon / POLC)
+    int n_head_seg = 0;                        // segments before the reconstruction sum's tail
+    std::vector<uint32_t> tail_ends;           // seg_ends of the tail's segments, from bit 0
     int spad_len = 0;
     int64_t cm_bytes = 0, m_bytes = 0;
     bool stream_nt = false;        // non-temporal matrix loads (the engine's matrices exceed the cache)
@@ -139,7 +142,7 @@ struct Instance {
     KBlock *d_kb = nullptr, *d_kbm = nullptr;
     Segment *d_seg = nullptr, *d_segm = nullptr;
     rtc::SegRun *d_run = nullptr, *d_runm = nullptr;   // the segments, block fields folded in
-    uint32_t *d_seg_ends = nullptr, *d_segm_ends = nullptr;
+    uint32_t *d_seg_ends = nullptr, *d_segm_ends = nullptr, *d_tail_ends = nullptr;
     float *d_sh_dark = nullptr, *d_sh_flat = nullptr, *d_sh_bg = nullptr, *d_sh_thr = nullptr;
     float *d_py_dark = nullptr, *d_py_flat = nullptr, *d_py_bg = nullptr, *d_py_thr = nullptr;
     float *d_ref = nullptr;

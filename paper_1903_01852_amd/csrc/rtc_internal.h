@@ -186,6 +186,8 @@ struct PersistInst {
     const KbWork *kbw;
     const Segment *segs;
     const uint32_t *seg_ends;      // bit j: segment j ends its column block
+    const uint32_t *tail_ends;     // the same for the sum's tail, segment n_head at bit 0
+    int32_t n_head, r9;            // segments before the sum's tail (their prefix is formed apart)
     const Step *steps;
     int32_t n_kb, n_seg, n_steps, n_wfs;
     int32_t n_cen_all, r5;         // centroid tasks of a frame (every block)
@@ -217,7 +219,9 @@ struct PersistInst {
     uint64_t *cen_fan;             // [kDepth][n_kb] fan-in: centroid tasks of a block
     uint64_t *tile_fan;            // [kDepth] fan-in: tiles whose commands are out
     uint64_t *pol_fan;             // [kDepth] fan-in: tiles whose POLC term is formed
-    uint64_t *tile_cnt;            // [kDepth][n_tiles] segment partials of a tile formed
+    uint64_t *tile_cnt;            // [kDepth][n_tiles] tail partials (and the prefix) of a tile formed
+    uint64_t *head_cnt;            // [kDepth][n_tiles] head partials of a tile formed
+    float *pre;                    // [kDepth][n_act] the sum's prefix over the head blocks
     uint64_t *join;                // [kDepth][n_tiles] accumulation joins
     uint64_t *pol_cnt;             // [kDepth][n_tiles] POLC partials of a tile
     uint64_t *p_done;              // [n_tiles] q + 1 of the last POLC term reduced

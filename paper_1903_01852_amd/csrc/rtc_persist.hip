@@ -292,31 +292,12 @@ __device__ __forceinline__ float *tel_rec(InstRef I, uint64_t q) {
     return I.tel_ring + ((q >> I.tel_dshift) & (uint64_t)I.tel_smask) * (uint64_t)I.tel_rec;
 }
 
-// Frame coefficients for frame q.
+// Frame coefficients for frame q of a batch launch (serving reads them from
+// the device mirror of the parameter block, with the row's other operands).
 __device__ __forceinline__ void frame_coef(InstRef I, uint64_t q, float &c1, float &g) {
-    if (I.serving) {
-        // device mirror, refreshed by the sentinel before it mirrors any
-        // doorbell that follows a host parameter change
-        // (both slots are read with the word, not after it: a slot a frame
-        // selects was mirrored before the doorbells of that frame, which this
-        // wavefront has already seen)
-        const ParamBlock *pb = I.param_mirror;
-        const uint64_t word = ld_agent64(&pb->word);
-        float c1s[2], gs[2];
-        for (int k = 0; k < 2; ++k) {
-            c1s[k] = __hip_atomic_load(gbl(&pb->c1[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            gs[k] = __hip_atomic_load(gbl(&pb->g[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        const uint64_t qs = word >> 1;
-        const int staged = (int)(word & 1);
-        const int s = q >= qs ? staged : 1 - staged;
-        c1 = s ? c1s[1] : c1s[0];
-        g = s ? gs[1] : gs[0];
-    } else {
-        const int s = q >= I.coef.q_switch ? 1 : 0;
-        c1 = I.coef.c1[s];
-        g = I.coef.g[s];
-    }
+    const int s = q >= I.coef.q_switch ? 1 : 0;
+    c1 = I.coef.c1[s];
+    g = I.coef.g[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -457,11 +438,17 @@ __device__ __forceinline__ bool join(InstRef I, uint64_t q, int t, int lane) {
 // The frame's coefficients, FP8 row scale and drop mark are settled before
 // any wavefront starts the frame, so they may be loaded early (beside the
 // sum); the previous commands and the POLC term come from the join's other
-// parties and are loaded only once the join is complete.
+// parties and are loaded only once the join is complete.  Every load of a
+// group is issued before any of its values is used, so a group costs one
+// round trip to memory.
 struct RowOps {
     float c1, g, scale, p, aprev;
     bool dropped;
     uint64_t a_free;   // POLC: tasks of frame q - 2 done reading the tile's columns
+};
+struct RowRaw {
+    uint64_t word, mword, drop, a_free;
+    float c1s[2], gs[2], scs[2];
 };
 // With POLC, the tile's commands of frame q overwrite those of frame q - 2,
 // which the POLC tasks of frame q - 2 on the tile's columns (one segment: a
@@ -471,13 +458,58 @@ static_assert(kPolcBlock / 4 <= kMaxSegVectors && kPolcBlock % kTileRows == 0,
 __device__ __forceinline__ uint64_t *a_free_ctr(InstRef I, uint64_t q, int t) {
     return slot(I.pol_seg, (size_t)dslot(q) * I.n_segm + t * kTileRows / kPolcBlock);
 }
-__device__ __forceinline__ void row_ops_early(InstRef I, uint64_t q, int r, RowOps &o) {
-    o.a_free = I.polc && q >= I.q_begin + 2 ? ld_agent64(a_free_ctr(I, q - 2, r / kTileRows))
-                                             : ~0ull;
-    frame_coef(I, q, o.c1, o.g);
-    const float *scale = I.dtype == RTC_CM_FP8 ? I.scale[mat_slot(I, q)] : nullptr;
-    o.scale = scale != nullptr ? gbl(scale)[r] : 1.0f;
-    o.dropped = I.serving && ld_agent64(I.drop_mirror + (q % (uint64_t)I.ring_depth)) == q + 1;
+__device__ __forceinline__ void row_ops_issue(InstRef I, uint64_t q, int r, RowRaw &w) {
+    // descriptor fields first (scalar loads), then the vector loads
+    const bool serving = I.serving != 0, polc = I.polc != 0, fp8 = I.dtype == RTC_CM_FP8;
+    const ParamBlock *pb = I.param_mirror;
+    const uint64_t *dm = I.drop_mirror + (q % (uint64_t)I.ring_depth);
+    const float *sc0 = I.scale[0], *sc1 = I.scale[1];
+    w = RowRaw{};
+    w.a_free = ~0ull;
+    if (polc && q >= I.q_begin + 2) w.a_free = ld_agent64(a_free_ctr(I, q - 2, r / kTileRows));
+    if (serving) {
+        w.word = ld_agent64(&pb->word);
+        w.mword = ld_agent64(&pb->mword);
+        for (int k = 0; k < 2; ++k) {
+            w.c1s[k] = __hip_atomic_load(gbl(&pb->c1[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            w.gs[k] = __hip_atomic_load(gbl(&pb->g[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        w.drop = ld_agent64(dm);
+    }
+    if (fp8) {
+        w.scs[0] = gbl(sc0)[r];
+        w.scs[1] = gbl(sc1)[r];
+    }
+}
+// Ties the loaded values to this point of the program: the compiler would
+// otherwise move cheap uses (a comparison) up to the loads, and the wait for
+// them ahead of the group's later memory operations.
+__device__ __forceinline__ void pin_raw(RowRaw &w) {
+    asm volatile("" : "+v"(w.word), "+v"(w.mword), "+v"(w.drop), "+v"(w.a_free));
+    asm volatile("" : "+v"(w.c1s[0]), "+v"(w.c1s[1]), "+v"(w.gs[0]), "+v"(w.gs[1]),
+                 "+v"(w.scs[0]), "+v"(w.scs[1]));
+}
+// The early operands from their loaded values (the word of a parameter or
+// matrix switch: frames from q_switch = word >> 1 on use slot word & 1).
+__device__ __forceinline__ void row_ops_early(InstRef I, uint64_t q, const RowRaw &w, RowOps &o) {
+    o.a_free = w.a_free;
+    o.scale = 1.0f;
+    if (I.serving) {
+        // the device mirror of the parameter block: the sentinel refreshes it
+        // before it mirrors any doorbell that follows a host change, and this
+        // frame's doorbells have been seen (so both slots may be read with the
+        // word rather than after it)
+        const int s = q >= (w.word >> 1) ? (int)(w.word & 1) : 1 - (int)(w.word & 1);
+        o.c1 = s ? w.c1s[1] : w.c1s[0];
+        o.g = s ? w.gs[1] : w.gs[0];
+        o.dropped = w.drop == q + 1;
+        const int ms = q >= (w.mword >> 1) ? (int)(w.mword & 1) : 1 - (int)(w.mword & 1);
+        if (I.dtype == RTC_CM_FP8) o.scale = ms ? w.scs[1] : w.scs[0];
+    } else {
+        frame_coef(I, q, o.c1, o.g);
+        o.dropped = false;
+        if (I.dtype == RTC_CM_FP8) o.scale = mat_slot(I, q) ? w.scs[1] : w.scs[0];
+    }
 }
 __device__ __forceinline__ void row_ops_joined(InstRef I, uint64_t q, int r, RowOps &o) {
     o.p = I.polc ? load_agent(I.p + r) : 0.0f;
@@ -519,16 +551,46 @@ __device__ __forceinline__ void tile_commands(InstRef I, ArgsRef A, uint64_t q, 
 
 // The tile's reconstruction sum for row r: its segment partials of the frame,
 // block by block in readout order, the block ends from the mask (every lane
-// holds its words; r of lanes past a short tile is clamped); the row's other
-// operands are loaded with the first partials.
+// holds its words; r of lanes past a short tile is clamped).  The head blocks'
+// part is the prefix formed once they were complete (fold_head); the tail's
+// partials continue the fold from it.  The row's other operands are loaded
+// with the first partials.
 constexpr int kSumBatch = 64;
+__device__ __forceinline__ const float *tail_part(InstRef I, uint64_t q) {
+    return I.y_part[dslot(q)] + (size_t)I.n_head * I.n_act;
+}
+__device__ __forceinline__ const float *pre_of(InstRef I, uint64_t q, int r) {
+    return I.pre + (size_t)dslot(q) * I.n_act + r;
+}
+// Tail partials and the prefix of a tile's count (the prefix is one arrival).
+__device__ __forceinline__ uint64_t tile_need(InstRef I) {
+    return (uint64_t)(I.n_seg - I.n_head + (I.n_head > 0 ? 1 : 0));
+}
 __device__ __forceinline__ float tile_sum(InstRef I, uint64_t q, int r, const SegEnds &ends,
                                           RowOps &o) {
-    return sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, r, ends, [&] {
-        row_ops_early(I, q, r, o);
+    const bool has_pre = I.n_head > 0;
+    float pre = 0.0f;
+    return sum_partials<kSumBatch>(tail_part(I, q), I.n_seg - I.n_head, I.n_act, r, ends, [&] {
+        RowRaw w;
+        row_ops_issue(I, q, r, w);
+        if (has_pre) pre = load_agent(pre_of(I, q, r));
         row_ops_joined(I, q, r, o);
+        pin_raw(w);
+        row_ops_early(I, q, w, o);
         return true;
-    });
+    }, has_pre, pre);
+}
+
+// The head's part of tile t's sum for frame q, once all its partials are
+// stored: the fold's state after the head blocks, for the tail to continue.
+__device__ __forceinline__ void fold_head(InstRef I, uint64_t q, int t, int lane) {
+    const int nr = min(kTileRows, I.n_act - t * kTileRows);
+    const int rc = t * kTileRows + (lane < nr ? lane : 0);
+    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_head, lane);
+    const float y = sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_head, I.n_act, rc, ends,
+                                            [] { return true; });
+    if (lane < nr) st_agent(I.pre + (size_t)dslot(q) * I.n_act + rc, y);
+    drain();
 }
 
 // Commands of tile t for frame q from its sum y, then of every following frame
@@ -554,7 +616,7 @@ __device__ __forceinline__ void accumulate(InstRef I, ArgsRef A, uint64_t q, int
                                            Trace &tr) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int rc = t * kTileRows + (lane < nr ? lane : 0);
-    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
+    const SegEnds ends = load_seg_ends(I.tail_ends, I.n_seg - I.n_head, lane);
     RowOps o;
     const float y = tile_sum(I, q, rc, ends, o);
     (void)finish_chain(I, A, q, t, lane, tr, y, o, ends);
@@ -570,15 +632,23 @@ __device__ __forceinline__ void tile_ready(InstRef I, ArgsRef A, uint64_t q, int
                                            Trace &tr) {
     const int nr = min(kTileRows, I.n_act - t * kTileRows);
     const int rc = t * kTileRows + (lane < nr ? lane : 0);
-    const SegEnds ends = load_seg_ends(I.seg_ends, I.n_seg, lane);
+    const SegEnds ends = load_seg_ends(I.tail_ends, I.n_seg - I.n_head, lane);
+    const bool has_pre = I.n_head > 0;
+    float pre = 0.0f;
     RowOps o;
     bool joined = false;
-    const float y = sum_partials<kSumBatch>(I.y_part[dslot(q)], I.n_seg, I.n_act, rc, ends, [&] {
-        row_ops_early(I, q, rc, o);
-        joined = join(I, q, t, lane);
-        if (joined) row_ops_joined(I, q, rc, o);
-        return joined;
-    });
+    const float y = sum_partials<kSumBatch>(tail_part(I, q), I.n_seg - I.n_head, I.n_act, rc, ends, [&] {
+        RowRaw w;
+        row_ops_issue(I, q, rc, w);
+        if (has_pre) pre = load_agent(pre_of(I, q, rc));
+        joined = join(I, q, t, lane);   // waits for the group
+        tr.stamp(RTC_TRACE_JOINED, lane);
+        pin_raw(w);
+        if (!joined) return false;
+        row_ops_joined(I, q, rc, o);
+        row_ops_early(I, q, w, o);
+        return true;
+    }, has_pre, pre);
     if (!joined) return;
     tr.stamp(RTC_TRACE_SUMMED, lane);
     (void)finish_chain(I, A, q, t, lane, tr, y, o, ends);
@@ -762,9 +832,16 @@ __device__ __forceinline__ void mvm_tasks(InstRef I, ArgsRef A, uint64_t q, cons
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
         uint64_t old = 0;
+        if (sg < I.n_head) {
+            // a head partial: the arrival completing the tile's head folds it
+            if (lane == 0) old = add_agent64(slot(I.head_cnt, (size_t)dslot(q) * n_tiles + t), 1);
+            old = __shfl(old, 0, kWave);
+            if (old + 1 != par_target(I, q, (uint64_t)I.n_head)) continue;
+            fold_head(I, q, t, lane);
+        }
         if (lane == 0) old = add_agent64(slot(I.tile_cnt, (size_t)dslot(q) * n_tiles + t), 1);
         old = __shfl(old, 0, kWave);
-        if (old + 1 != par_target(I, q, (uint64_t)I.n_seg)) continue;
+        if (old + 1 != par_target(I, q, tile_need(I))) continue;
         // (E) party: the tile's reconstruction sum is ready
         tr.stamp(RTC_TRACE_TILE_READY, lane);
         tile_ready(I, A, q, t, lane, tr);

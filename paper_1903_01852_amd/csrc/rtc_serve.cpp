@@ -52,6 +52,8 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.kbw = P.kbw;
     d.segs = I->d_seg;
     d.seg_ends = I->d_seg_ends;
+    d.tail_ends = I->d_tail_ends;
+    d.n_head = I->n_head_seg;
     d.steps = nullptr;
     d.n_kb = (int)I->kb.size();
     d.n_cen_all = P.n_cen_all;
@@ -100,6 +102,8 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     d.tile_fan = P.tile_fan;
     d.pol_fan = P.pol_fan;
     d.tile_cnt = P.tile_cnt;
+    d.head_cnt = P.head_cnt;
+    d.pre = P.pre;
     d.join = P.join;
     d.pol_cnt = P.pol_cnt;
     d.p_done = P.p_done;
@@ -291,10 +295,10 @@ rtc_status persist_alloc(rtc_engine *e) {
         // counters, each in a slot of its own; arrival counters kDepth times:
         // fan-in barriers cen [D][nkb], tile [D], pol [D]; tile_cnt, join and
         // pol_cnt [D][nt]; p_done and tile_pub [nt] once; ing_cnt [D][n_steps];
-        // pol_seg [D][n_segm]
+        // pol_seg [D][n_segm]; head_cnt [D][nt]
         const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size(), nsm = I->segm.size();
         const size_t n_slots =
-            D * nkb * fan + 2 * D * fan + 3 * D * nt + 2 * nt + D * nst + D * nsm;
+            D * nkb * fan + 2 * D * fan + 4 * D * nt + 2 * nt + D * nst + D * nsm;
         P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_fan = P.ctr;
@@ -307,6 +311,8 @@ rtc_status persist_alloc(rtc_engine *e) {
         P.tile_pub = P.p_done + nt * kCtrSlot;
         P.ing_cnt = P.tile_pub + nt * kCtrSlot;
         P.pol_seg = P.ing_cnt + D * nst * kCtrSlot;
+        P.head_cnt = P.pol_seg + D * nsm * kCtrSlot;
+        TRY(dev_alloc(e, &P.pre, (size_t)kDepth * I->n_act));
         // serving ingest: each readout step's rows as 16-byte units of a ring
         // slot, in pieces, numbered in readout order; the buffer accesses take
         // 32-bit byte offsets

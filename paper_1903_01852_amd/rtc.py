@@ -36,7 +36,7 @@ EXPORTS = ("rtc_create", "rtc_destroy", "rtc_strerror", "rtc_get_info", "rtc_chu
            "rtc_process_frames_noalloc", "rtc_pacer_run")
 TRACE_EVENTS = ("frame_start", "gate", "centroids", "mvm_first", "mvm_last", "ingest",
                 "accum", "frame_end", "cen_start", "last_block", "tile_ready", "cmds",
-                "ingest_start", "summed")
+                "ingest_start", "summed", "joined")
 
 
 class RtcError(RuntimeError):
