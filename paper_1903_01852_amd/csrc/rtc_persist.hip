@@ -959,12 +959,22 @@ __device__ __forceinline__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q,
 // earlier-stage work is available, so no worker holds up a block that others
 // wait on, and the steps of a frame (about a hundred for six laser guide
 // stars) pipeline instead of queueing behind each other.
+constexpr int kFrontMinWorkers = 1024;
 __device__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb) {
     return ld_agent64(fan_top(fan_grp(I.cen_fan, q, I.n_kb, kb))) >= fan_target(I, q, W.n_cen);
 }
 
 __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                                RTC_LDS float *lds) {
+    // With many workers, two groups: the front quarter takes the pixel work
+    // (ingest and slopes), the rest the products.  A front worker is never
+    // inside an MVM task when a chunk's pixels land, so the frame's last slopes
+    // start as soon as their chunk is in device memory.  A smaller instance
+    // keeps one group (its last block's products need every worker).  POLC
+    // and telemetry copies (after publication) go to every worker.
+    const int n_front = nw >= kFrontMinWorkers ? nw / 4 : 0;
+    const bool front = rank < n_front, both = n_front == 0;
+    const int grank = front ? rank : rank - n_front, gn = both ? nw : front ? n_front : nw - n_front;
     for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
         if (stopping(A)) return;
         Trace tr = trace_of(I, A, q, wid);
@@ -977,10 +987,12 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
             so.counts = reinterpret_cast<int32_t *>(so.s_out + I.n_slopes);
             so.masks = reinterpret_cast<uint64_t *>(so.s_out + I.tel_mask_off);
         }
-        FrameTasks ft = frame_tasks(I, q, rank, nw);
-        int ing = first_task(rank, nw, rot(q, I.n_ing_all, nw));
+        FrameTasks ft = frame_tasks(I, q, grank, gn);
+        int ing = first_task(grank, gn, rot(q, I.n_ing_all, gn));
         const int n_steps = I.n_steps, n_tiles = I.n_tiles;
-        int is = 0, ic = 0, cs = 0, ms = 0;   // next step to ingest, known ingested, slopes, MVM
+        // next step to ingest, known ingested, slopes, MVM (a group skips the other's)
+        int is = front || both ? 0 : n_steps, ic = 0, cs = front || both ? 0 : n_steps,
+            ms = front ? n_steps : 0;
         uint32_t idle = 0;
         bool last_seen = false;   // an MVM task of the frame's last block started
         while (is < n_steps || cs < n_steps || ms < n_steps) {
@@ -992,7 +1004,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     if (!db_reached(ld_agent64(I.db_mirror + S.wfs), q, (uint64_t)S.chunk + 1))
                         break;
                     tr.stamp(RTC_TRACE_INGEST_START, lane);
-                    ingest_tasks(I, q, S, is, nw, lane, ing);
+                    ingest_tasks(I, q, S, is, gn, lane, ing);
                     tr.stamp(RTC_TRACE_INGEST, lane);
                     progressed = true;
                 }
@@ -1017,7 +1029,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     if (ic <= cs) break;
                     uint32_t cnt = 0;
                     tr.stamp(RTC_TRACE_CEN_START, lane);
-                    centroid_tasks(I, q, W, nw, lane, so, false, ft.cen, cnt);
+                    centroid_tasks(I, q, W, gn, lane, so, false, ft.cen, cnt);
                     drain();
                     (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt,
                                      lane);
@@ -1044,7 +1056,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                         tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
                         last_seen = true;
                     }
-                    mvm_tasks(I, A, q, W, S.kb, nw, lane, lds, ft.mvm, tr, 1);
+                    mvm_tasks(I, A, q, W, S.kb, gn, lane, lds, ft.mvm, tr, 1);
                     if (ft.mvm >= end) ++ms;
                     progressed = true;
                 }
