@@ -207,6 +207,61 @@ def serve(eng, data, n_frames, warmup, first=0, switch=None, zero_copy=False, in
     return [latency_stats(s[k]) for k in range(len(insts))]
 
 
+# Milestones of a served frame from the frame loop's timeline record (event,
+# and whether the first or the last wavefront to reach it matters), in
+# microseconds after the sentinel saw the frame's last chunk.
+TIMELINE = (("last ingest starts", "ingest_start", "last"),
+            ("last ingest done", "ingest", "last"),
+            ("last slopes start", "cen_start", "last"),
+            ("last slopes counted", "centroids", "last"),
+            ("last block's first MVM task", "last_block", "first"),
+            ("first tile's partials complete", "tile_ready", "first"),
+            ("last tile's partials complete", "tile_ready", "last"),
+            ("last join answered", "joined", "last"),
+            ("last sum formed", "summed", "last"),
+            ("last commands written", "cmds", "last"))
+
+
+def timeline(torch, rtc, name, dtype, n_rec=150, warmup=50):
+    """Where a served frame's latency goes: the paced serving run with the
+    library's per-wavefront timeline record, per instance the median over
+    frames of each milestone (device clock, 100 MHz)."""
+    import numpy as np
+    wl, data = build_inputs(name, 16)
+    eng = load_engine(rtc, wl, data, dtype, "persistent")
+    eng.trace_enable(n_rec + warmup)
+    s = eng.pace([(k, d["frames"]) for k, d in enumerate(data)], n_rec + warmup,
+                 warmup=warmup, period_s=PERIOD_S, readout_s=READOUT_S)
+    tr = eng.trace_read().astype(np.int64)       # (frames, waves, events)
+    eng.close()
+    ev = {e: i for i, e in enumerate(rtc.TRACE_EVENTS)}
+    out = {}
+    for k, inst in enumerate(wl.instances):
+        per = {m[0]: [] for m in TIMELINE}
+        per["published"] = []
+        for i in range(n_rec):
+            t_seen, t_pub = int(s[k][i]["dev_ticks_start"]), int(s[k][i]["dev_ticks_cmd"])
+            if t_seen == 0:
+                continue
+            rec = tr[warmup + i]
+            # an instance's wavefronts run from its sentinel (which records
+            # nothing) to the next instance's sentinel
+            sentinels = np.flatnonzero(rec[:, ev["frame_start"]] == 0)
+            w0 = sentinels[k] if k < len(sentinels) else 0
+            w1 = sentinels[k + 1] if k + 1 < len(sentinels) else rec.shape[0]
+            mine = rec[w0:w1]
+            mine = mine[mine[:, ev["frame_start"]] > 0]
+            for label, e, which in TIMELINE:
+                v = mine[:, ev[e]]
+                v = v[v > 0]
+                if v.size:
+                    per[label].append(((v.min() if which == "first" else v.max()) - t_seen) / 100.0)
+            per["published"].append((t_pub - t_seen) / 100.0)
+        out[inst.name] = {lab: round(float(np.median(v)), 2) for lab, v in per.items() if v}
+        out[inst.name]["host_p50"] = round(float(np.median(s[k]["host_us"])), 2)
+    return out
+
+
 def mvm_timing(torch, eng, n_iter=200, cold=False, inst=0):
     """Average MVM kernel duration (s) from HIP events on the launch stream.
 
@@ -579,6 +634,13 @@ def main():
                     help="only the standalone MVM on the matrices beyond the cache (profiling)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline's cold MVM launches (hardware-counter runs)")
+    ap.add_argument("--frame-loop-only", action="store_true",
+                    help="only the frame loop's batch form on the 74x74 SCAO FP32 case, 4 "
+                         "launches of 64 device-resident frames after one warm-up launch "
+                         "(hardware-counter runs)")
+    ap.add_argument("--timeline", metavar="WORKLOAD",
+                    help="only the serving timeline of WORKLOAD (with --dtype): where a "
+                         "frame's latency goes, from the loop's per-wavefront record")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -609,6 +671,30 @@ def main():
     if args.mvm_large_only:
         print(json.dumps({"box_reference": ref, "mvm_large": mvm_large(torch, rtc, log, {})}),
               flush=True)
+        return
+
+    if args.timeline:
+        print(json.dumps({"timeline": {"workload": args.timeline, "dtype": args.dtype,
+                                       "us_after_last_chunk_seen": timeline(
+                                           torch, rtc, args.timeline, args.dtype)}}),
+              flush=True)
+        return
+
+    if args.frame_loop_only:
+        wl_s, data_s = build_inputs("scao_sh_74", 64)
+        inst_s = wl_s.instances[0]
+        eng = load_engine(rtc, wl_s, data_s, "f32", "persistent")
+        dfr = [torch.from_numpy(f).cuda() for f in data_s[0]["frames"]]
+        r = batch_throughput(torch, eng, dfr, 256, 64)
+        n_s = eng.infos[0]["n_slopes"]
+        eng.close()
+        # per frame: the matrix and command bytes of the MVM, and 2 B of raw pixel
+        # plus 12 B of calibration per processed pixel
+        px = (n_s // 2) * inst_s.wfs[0].px ** 2
+        alg = mvm_alg_bytes(inst_s, n_s, "f32") + 14 * px
+        print(json.dumps({"frame_loop_only": {"frames_per_s": round(r["frames_per_s"], 1),
+                                              "frames_per_launch": 64,
+                                              "alg_bytes_per_frame": alg}}), flush=True)
         return
 
     # ---------------------------------------------------------------- headline
