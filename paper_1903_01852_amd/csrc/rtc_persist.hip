@@ -555,7 +555,7 @@ __device__ __forceinline__ void tile_commands(InstRef I, ArgsRef A, uint64_t q, 
 // part is the prefix formed once they were complete (fold_head); the tail's
 // partials continue the fold from it.  The row's other operands are loaded
 // with the first partials.
-constexpr int kSumBatch = 64;
+constexpr int kSumBatch = 32;
 __device__ __forceinline__ const float *tail_part(InstRef I, uint64_t q) {
     return I.y_part[dslot(q)] + (size_t)I.n_head * I.n_act;
 }
