@@ -959,22 +959,41 @@ __device__ __forceinline__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q,
 // earlier-stage work is available, so no worker holds up a block that others
 // wait on, and the steps of a frame (about a hundred for six laser guide
 // stars) pipeline instead of queueing behind each other.
-constexpr int kFrontMinWorkers = 1024;
+// Serving worker roles: which kinds of work a worker takes, and its rank
+// among the workers of each kind (its tasks of a kind are every n-th of the
+// frame's, starting at its rank).
+struct Roles {
+    bool ing, cen, mvm;
+    int ing_rank, ing_n, cen_rank, cen_n, mvm_rank, mvm_n;
+};
+constexpr int kSplitMinWorkers = 1024;   // smaller instances keep one group
+constexpr int kIngestWorkers = 32;       // ingest-only workers of a split instance
+constexpr int kSlopeShare = 4;           // 1 / kSlopeShare of the rest take the slopes
 __device__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb) {
     return ld_agent64(fan_top(fan_grp(I.cen_fan, q, I.n_kb, kb))) >= fan_target(I, q, W.n_cen);
 }
 
 __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
                                RTC_LDS float *lds) {
-    // With many workers, two groups: the front quarter takes the pixel work
-    // (ingest and slopes), the rest the products.  A front worker is never
-    // inside an MVM task when a chunk's pixels land, so the frame's last slopes
-    // start as soon as their chunk is in device memory.  A smaller instance
-    // keeps one group (its last block's products need every worker).  POLC
-    // and telemetry copies (after publication) go to every worker.
-    const int n_front = nw >= kFrontMinWorkers ? nw / 4 : 0;
-    const bool front = rank < n_front, both = n_front == 0;
-    const int grank = front ? rank : rank - n_front, gn = both ? nw : front ? n_front : nw - n_front;
+    // With many workers, three groups: a few take only the ingest, a quarter of
+    // the rest the slopes, the others the products.  No ingest or slope worker
+    // is then inside a longer task when a chunk's pixels land, so the frame's
+    // last chunk is copied and its slopes start as soon as their turn comes.
+    // A smaller instance keeps one group (its last block's products need
+    // every worker).  POLC and telemetry copies (after publication) go to
+    // every worker.
+    Roles ro;
+    if (nw < kSplitMinWorkers) {
+        ro = Roles{true, true, true, rank, nw, rank, nw, rank, nw};
+    } else {
+        const int ni = kIngestWorkers, nc = (nw - ni) / kSlopeShare;
+        if (rank < ni)
+            ro = Roles{true, false, false, rank, ni, 0, 1, 0, 1};
+        else if (rank < ni + nc)   // with no ingest-only workers, the slope group ingests
+            ro = Roles{ni == 0, true, false, rank - ni, nc, rank - ni, nc, 0, 1};
+        else
+            ro = Roles{false, false, true, 0, 1, 0, 1, rank - ni - nc, nw - ni - nc};
+    }
     for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
         if (stopping(A)) return;
         Trace tr = trace_of(I, A, q, wid);
@@ -987,12 +1006,14 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
             so.counts = reinterpret_cast<int32_t *>(so.s_out + I.n_slopes);
             so.masks = reinterpret_cast<uint64_t *>(so.s_out + I.tel_mask_off);
         }
-        FrameTasks ft = frame_tasks(I, q, grank, gn);
-        int ing = first_task(grank, gn, rot(q, I.n_ing_all, gn));
+        FrameTasks ft;
+        ft.cen = first_task(ro.cen_rank, ro.cen_n, rot(q, I.n_cen_all, ro.cen_n));
+        ft.mvm = first_task(ro.mvm_rank, ro.mvm_n, rot(q, I.n_seg * I.n_tiles, ro.mvm_n));
+        int ing = first_task(ro.ing_rank, ro.ing_n, rot(q, I.n_ing_all, ro.ing_n));
         const int n_steps = I.n_steps, n_tiles = I.n_tiles;
-        // next step to ingest, known ingested, slopes, MVM (a group skips the other's)
-        int is = front || both ? 0 : n_steps, ic = 0, cs = front || both ? 0 : n_steps,
-            ms = front ? n_steps : 0;
+        // next step to ingest, known ingested, slopes, MVM (a group skips the others')
+        int is = ro.ing ? 0 : n_steps, ic = 0, cs = ro.cen ? 0 : n_steps,
+            ms = ro.mvm ? 0 : n_steps;
         uint32_t idle = 0;
         bool last_seen = false;   // an MVM task of the frame's last block started
         while (is < n_steps || cs < n_steps || ms < n_steps) {
@@ -1004,7 +1025,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     if (!db_reached(ld_agent64(I.db_mirror + S.wfs), q, (uint64_t)S.chunk + 1))
                         break;
                     tr.stamp(RTC_TRACE_INGEST_START, lane);
-                    ingest_tasks(I, q, S, is, gn, lane, ing);
+                    ingest_tasks(I, q, S, is, ro.ing_n, lane, ing);
                     tr.stamp(RTC_TRACE_INGEST, lane);
                     progressed = true;
                 }
@@ -1029,7 +1050,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     if (ic <= cs) break;
                     uint32_t cnt = 0;
                     tr.stamp(RTC_TRACE_CEN_START, lane);
-                    centroid_tasks(I, q, W, gn, lane, so, false, ft.cen, cnt);
+                    centroid_tasks(I, q, W, ro.cen_n, lane, so, false, ft.cen, cnt);
                     drain();
                     (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt,
                                      lane);
@@ -1056,7 +1077,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                         tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
                         last_seen = true;
                     }
-                    mvm_tasks(I, A, q, W, S.kb, gn, lane, lds, ft.mvm, tr, 1);
+                    mvm_tasks(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm, tr, 1);
                     if (ft.mvm >= end) ++ms;
                     progressed = true;
                 }
