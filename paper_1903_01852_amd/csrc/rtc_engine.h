@@ -69,6 +69,7 @@ struct PersistInstState {
     uint64_t *cen_fan = nullptr, *tile_fan = nullptr, *pol_fan = nullptr;
     uint64_t *tile_cnt = nullptr, *join = nullptr, *pol_cnt = nullptr, *p_done = nullptr;
     uint64_t *tile_pub = nullptr, *pol_seg = nullptr, *head_cnt = nullptr;
+    uint64_t *tile_host = nullptr; // pinned [n_tiles]: q + 1 of a tile's last commands in the mailbox
     float *pre = nullptr;          // [kDepth][n_act] prefixes of the reconstruction sum
     int n_cen_all = 0;             // centroid tasks of a frame
     int n_ing_all = 0;             // ingest pieces of a frame (serving)
@@ -91,6 +92,7 @@ struct PersistInstState {
     std::vector<uint64_t> slot_frame;   // frame id of the frame in each slot
     std::vector<int64_t> slot_t_last;   // host clock at its last chunk
     std::vector<uint64_t> slot_tlc0;    // the slot's last-chunk stamp before the frame (stale)
+    std::vector<uint64_t> slot_tpub0;   // the slot's publication stamp before the frame (stale)
     std::vector<uint8_t> slot_dropped;
     uint64_t param_word = 0;       // (q_switch << 1) | staged slot, as last written
     uint64_t mword = 0;            // (q_mswitch << 1) | slot, as last written

@@ -260,6 +260,8 @@ struct PersistInst {
     // outputs
     float *mail;                           // pinned, ring_depth x n_act (serving)
     uint64_t *cmd_seq;                     // pinned: q + 1 of the last published frame
+    uint64_t *tile_host;                   // pinned, per tile: q + 1 of the last frame whose
+                                           // commands of the tile are in the mailbox
     uint64_t *pol_seq;                     // pinned: q + 1 of the last frame whose POLC term is done
     FrameTel *tel;                         // pinned, per slot
     float *cmds_out;                       // batch, n_frames x n_act (nullable)

@@ -540,6 +540,8 @@ __device__ __forceinline__ void tile_commands(InstRef I, ArgsRef A, uint64_t q, 
     }
     drain();
     tr.stamp(RTC_TRACE_CMDS, lane);
+    if (lane == 0 && I.serving)   // the tile's commands are in the mailbox
+        __hip_atomic_store(gbl(I.tile_host + t), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (lane == 0) st_agent64(slot(I.tile_pub, t), q + 1);
     if (lane == 0 && add_agent64(tiles_out(I, q), 1) + 1 == tiles_target(I, q) && I.serving) {
         FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);

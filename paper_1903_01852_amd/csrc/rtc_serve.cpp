@@ -127,6 +127,7 @@ PersistInst describe(rtc_engine *e, Instance *I) {
     }
     d.mail = I->h_mail;
     d.cmd_seq = P.cmd_seq;
+    d.tile_host = P.tile_host;
     d.pol_seq = P.pol_seq;
     d.tel = P.tel;
     d.n_slopes = I->n_slopes;
@@ -337,11 +338,13 @@ rtc_status persist_alloc(rtc_engine *e) {
         TRY(host_pinned(e, &P.drop_host, e->ring_depth));
         TRY(host_pinned(e, &P.params, 1));
         TRY(host_pinned(e, &P.cmd_seq, 1));
+        TRY(host_pinned(e, &P.tile_host, (size_t)I->n_tiles));
         TRY(host_pinned(e, &P.pol_seq, 1));
         TRY(host_pinned(e, &P.tel, e->ring_depth));
         P.slot_frame.assign(e->ring_depth, ~0ull);
         P.slot_t_last.assign(e->ring_depth, 0);
         P.slot_tlc0.assign(e->ring_depth, 0);
+        P.slot_tpub0.assign(e->ring_depth, 0);
         P.slot_dropped.assign(e->ring_depth, 0);
         // work of each column block; task 0 of each list goes to the worker
         // after the previous list's last task so that the load spreads evenly
@@ -472,6 +475,7 @@ void persist_reset(Instance *I) {
     for (size_t k = 0; k < P.slot_frame.size(); ++k) *vol(P.drop_host + k) = 0;
     *vol(P.cmd_seq) = 0;
     *vol(P.pol_seq) = 0;
+    for (int t = 0; t < I->n_tiles; ++t) *vol(P.tile_host + t) = 0;
     P.seq = 0;
     P.q_cur = 0;
     std::fill(P.slot_frame.begin(), P.slot_frame.end(), ~0ull);
@@ -703,6 +707,7 @@ rtc_status begin_chunk(rtc_engine *e, Instance *I, int w, uint64_t frame, int ch
         P.slot_dropped[slot] = 0;
         P.slot_t_last[slot] = 0;
         P.slot_tlc0[slot] = reinterpret_cast<volatile FrameTel *>(P.tel + slot)->ticks_last_chunk;
+        P.slot_tpub0[slot] = reinterpret_cast<volatile FrameTel *>(P.tel + slot)->ticks_publish;
         I->cur_frame = frame;
         I->cur_started = false;
         for (auto &W : I->wfs) W.next_chunk = 0;
@@ -804,8 +809,15 @@ rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
         std::this_thread::yield();
     }
     const size_t slot = q % depth;
+    // every tile flags its commands once they are in the mailbox (a tile's
+    // frames are integrated in order, so its flag only grows): the frame is
+    // ready when every flag has reached it, or when the publication count has
+    // (the loop counts the tiles on the device before it publishes)
+    const int nt = I->n_tiles;
+    int tk = 0;      // tiles before tk are known ready
     for (;;) {
-        if (load_acquire(P.cmd_seq) >= q + 1) break;
+        while (tk < nt && load_acquire(P.tile_host + tk) >= q + 1) ++tk;
+        if (tk == nt || load_acquire(P.cmd_seq) >= q + 1) break;
         if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
         if (e->pe.running && stream_done(e->pe.stream)) return fail(e, RTC_E_DEVICE);
     }
@@ -844,7 +856,14 @@ rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
             }
         }
         info->dev_ticks_start = start == P.slot_tlc0[slot] ? 0 : start;
-        info->dev_ticks_cmd = tel->ticks_publish;
+        // the tiles' flags can reach the host before the loop has counted the
+        // tiles and stamped the publication: wait briefly for that stamp
+        uint64_t pub = tel->ticks_publish;
+        while (pub == P.slot_tpub0[slot] && now_ns() - t_ready < kStampWaitNs) {
+            std::this_thread::yield();
+            pub = tel->ticks_publish;
+        }
+        info->dev_ticks_cmd = pub;
         info->drops = I->drops;
     }
     return RTC_OK;
