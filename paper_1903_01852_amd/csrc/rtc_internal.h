@@ -302,7 +302,7 @@ constexpr int kCtrSlot = 32;                      // uint64 per counter slot
 // arrival completing a stripe's quota counts on the top slot, and waiters
 // poll only the top slot.
 constexpr int kFanStripes = 32;
-constexpr int kFanSlots = kFanStripes + 1;        // stripes, then the top
+constexpr int kFanSlots = kFanStripes + 2;        // stripes, the top, the done flag
 
 // serving: the indefinitely running form (2 waves per SIMD, so up to 256
 // VGPRs a lane); otherwise the batch form (4 waves per SIMD)

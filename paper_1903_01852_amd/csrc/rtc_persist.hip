@@ -106,6 +106,22 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
     return dq > q || (dq == q && (db & kDbChunkMask) >= chunks);
 }
 
+// Bounded spin of a worker with nothing else to do: up to kSpinPolls loads of
+// one word, each tested with ok(value).  The pointer and the test are set
+// before the spin, so a poll costs one round trip to memory, where a pass of
+// the worker's main loop (which re-reads its tables to find the next piece of
+// work) costs several.  False when the bound is reached (the caller's main
+// loop then checks for a stop request before it spins again).
+constexpr int kSpinPolls = 64;
+template <class Ok>
+__device__ __forceinline__ bool spin_until(const uint64_t *p, Ok ok) {
+    for (int k = 0; k < kSpinPolls; ++k) {
+        __builtin_amdgcn_s_sleep(1);
+        if (ok(ld_agent64(p))) return true;
+    }
+    return false;
+}
+
 
 // Timeline record (rtc_trace_enable): this wavefront's events of one frame.
 struct Trace {
@@ -131,12 +147,23 @@ __device__ __forceinline__ uint64_t *slot(uint64_t *base, size_t i) {
 }
 
 // Fan-in barrier `key` (of n_keys) used by frame q: kFanStripes stripe slots,
-// then the top slot.
+// the top slot, then the done flag.
 __device__ __forceinline__ uint64_t *fan_grp(uint64_t *base, uint64_t q, int n_keys, int key) {
     return slot(base, ((size_t)dslot(q) * n_keys + key) * kFanSlots);
 }
 __device__ __forceinline__ uint64_t *fan_top(uint64_t *grp) {
     return slot(grp, kFanStripes);
+}
+// Waiters poll a word that no arrival updates: loads of a counter that atomics
+// are updating at the same time delay those atomics (measured: the last of 32
+// stripe arrivals at the top took 3 us with some 300 wavefronts polling it,
+// against 0.2 us for 512 contending atomics with no poller).  The arrival that
+// completes the barrier stores q + 1 here once its atomic has returned.
+__device__ __forceinline__ uint64_t *fan_flag(uint64_t *grp) {
+    return slot(grp, kFanStripes + 1);
+}
+__device__ __forceinline__ bool fan_done(uint64_t *grp, uint64_t q) {
+    return ld_agent64(fan_flag(grp)) >= q + 1;
 }
 // Top count once frame q has passed a barrier of n tasks.
 __device__ __forceinline__ uint64_t fan_target(InstRef I, uint64_t q, int n) {
@@ -152,8 +179,10 @@ __device__ __forceinline__ bool fan_arrive(InstRef I, uint64_t *grp, uint64_t q,
     if (cnt != 0) {
         const uint64_t quota = (uint64_t)((n - lane + kFanStripes - 1) / kFanStripes);
         const uint64_t old = add_agent64(slot(grp, lane), cnt);
-        if (old + cnt == par_target(I, q, quota))
+        if (old + cnt == par_target(I, q, quota)) {
             done = add_agent64(fan_top(grp), 1) + 1 == fan_target(I, q, n);
+            if (done) st_agent64(fan_flag(grp), q + 1);
+        }
     }
     return __any(done);
 }
@@ -878,6 +907,13 @@ __device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
 constexpr int kIngestPerLane = kIngestUnits / kWave;
 static_assert(kIngestPerLane * kWave == kIngestUnits, "a piece is whole loads of the wavefront");
 static_assert(kTelUnits % (4 * kWave) == 0, "a telemetry task is whole rounds of four loads");
+// Ingest count of readout step st of frame q, and its done flag.
+__device__ __forceinline__ uint64_t *ing_ctr(InstRef I, uint64_t q, int st) {
+    return slot(I.ing_cnt, (size_t)dslot(q) * I.n_steps + st);
+}
+__device__ __forceinline__ uint64_t *ing_flag(InstRef I, uint64_t q, int st) {
+    return slot(I.ing_cnt, ((size_t)kDepth + dslot(q)) * I.n_steps + st);
+}
 __device__ __forceinline__ void ingest_tasks(InstRef I, uint64_t q, const Step &S, int st, int nw, int lane,
                              int &j) {
     const int end = S.ing0 + S.ing_n;
@@ -907,7 +943,11 @@ __device__ __forceinline__ void ingest_tasks(InstRef I, uint64_t q, const Step &
             __builtin_amdgcn_raw_buffer_store_b128(v[k], ddst, (u0 + k * kWave + lane) * 16, 0, kAgent);
     }
     drain();
-    if (lane == 0) add_agent64(slot(I.ing_cnt, (size_t)dslot(q) * I.n_steps + st), cnt);
+    // the arrival completing the step's count raises its flag (the slope
+    // workers poll the flag, not the counter)
+    if (lane == 0 &&
+        add_agent64(ing_ctr(I, q, st), cnt) + cnt == par_target(I, q, (uint64_t)S.ing_n))
+        st_agent64(ing_flag(I, q, st), q + 1);
 }
 
 // Telemetry copy of recorded frame q: once the frame is published, task j
@@ -971,8 +1011,13 @@ struct Roles {
 constexpr int kSplitMinWorkers = 1024;   // smaller instances keep one group
 constexpr int kIngestWorkers = 32;       // ingest-only workers of a split instance
 constexpr int kSlopeShare = 4;           // 1 / kSlopeShare of the rest take the slopes
-__device__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb) {
-    return ld_agent64(fan_top(fan_grp(I.cen_fan, q, I.n_kb, kb))) >= fan_target(I, q, W.n_cen);
+// The slopes of column block kb of frame q are all stored; a worker with only
+// products to form (spin) waits for them in a bounded spin.
+__device__ __forceinline__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb,
+                                            bool spin) {
+    uint64_t *grp = fan_grp(I.cen_fan, q, I.n_kb, kb);
+    if (W.n_cen == 0 || fan_done(grp, q)) return true;   // (no arrival without slope tasks)
+    return spin && spin_until(fan_flag(grp), [&](uint64_t v) { return v >= q + 1; });
 }
 
 __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
@@ -996,6 +1041,10 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
         else
             ro = Roles{false, false, true, 0, 1, 0, 1, rank - ni - nc, nw - ni - nc};
     }
+    // a worker of a single kind waits for its next piece of work in a spin
+    const bool ingest_only = ro.ing && !ro.cen && !ro.mvm;
+    const bool slopes_only = ro.cen && !ro.ing && !ro.mvm;
+    const bool mvm_only = ro.mvm && !ro.ing && !ro.cen;
     for (uint64_t q = I.q_begin; q < I.q_end; ++q) {
         if (stopping(A)) return;
         Trace tr = trace_of(I, A, q, wid);
@@ -1024,7 +1073,11 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
             while (is < n_steps) {
                 const Step S = ldc(I.steps + is);
                 if (ing < S.ing0 + S.ing_n) {
-                    if (!db_reached(ld_agent64(I.db_mirror + S.wfs), q, (uint64_t)S.chunk + 1))
+                    const uint64_t *db = I.db_mirror + S.wfs;
+                    const uint64_t want = (uint64_t)S.chunk + 1;
+                    if (!db_reached(ld_agent64(db), q, want) &&
+                        !(ingest_only &&
+                          spin_until(db, [&](uint64_t v) { return db_reached(v, q, want); })))
                         break;
                     tr.stamp(RTC_TRACE_INGEST_START, lane);
                     ingest_tasks(I, q, S, is, ro.ing_n, lane, ing);
@@ -1043,9 +1096,11 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                 const KbWork W = ldc(I.kbw + S.kb);
                 if (ft.cen < W.cen_base + W.n_cen) {
                     while (ic <= cs) {
-                        const Step T = ldc(I.steps + ic);
-                        if (ld_agent64(slot(I.ing_cnt, (size_t)dslot(q) * n_steps + ic)) <
-                            par_target(I, q, (uint64_t)T.ing_n))
+                        // (a step with no pixel units has nothing to count)
+                        const uint64_t *flag = ing_flag(I, q, ic);
+                        if (ldc(I.steps + ic).ing_n > 0 && ld_agent64(flag) < q + 1 &&
+                            !(slopes_only &&
+                              spin_until(flag, [&](uint64_t v) { return v >= q + 1; })))
                             break;
                         ++ic;
                     }
@@ -1074,7 +1129,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     ++ms;
                     continue;
                 }
-                if (block_ready(I, q, W, S.kb)) {
+                if (block_ready(I, q, W, S.kb, mvm_only)) {
                     if (S.kb == I.n_kb - 1 && !last_seen) {
                         tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
                         last_seen = true;
@@ -1144,7 +1199,7 @@ __device__ __forceinline__ void batch_worker(InstRef I, ArgsRef A, int wid, int 
             Trace tn = trace_of(I, A, q + kAhead, wid);
             if (!batch_centroids(I, A, q + kAhead, rank, nw, lane, tn)) return;
         }
-        if (!wait_geq(fan_top(fan_grp(I.cen_fan, q, I.n_kb, 0)), fan_target(I, q, I.n_cen_all), A,
+        if (!wait_geq(fan_flag(fan_grp(I.cen_fan, q, I.n_kb, 0)), q + 1, A,
                       A.dep_watchdog))
             return;
         int m = frame_tasks(I, q, rank, nw).mvm;

@@ -295,11 +295,11 @@ rtc_status persist_alloc(rtc_engine *e) {
         }
         // counters, each in a slot of its own; arrival counters kDepth times:
         // fan-in barriers cen [D][nkb], tile [D], pol [D]; tile_cnt, join and
-        // pol_cnt [D][nt]; p_done and tile_pub [nt] once; ing_cnt [D][n_steps];
-        // pol_seg [D][n_segm]; head_cnt [D][nt]
+        // pol_cnt [D][nt]; p_done and tile_pub [nt] once; ing_cnt [D][n_steps]
+        // then its done flags [D][n_steps]; pol_seg [D][n_segm]; head_cnt [D][nt]
         const size_t fan = kFanSlots, D = kDepth, nst = I->steps.size(), nsm = I->segm.size();
         const size_t n_slots =
-            D * nkb * fan + 2 * D * fan + 4 * D * nt + 2 * nt + D * nst + D * nsm;
+            D * nkb * fan + 2 * D * fan + 4 * D * nt + 2 * nt + 2 * D * nst + D * nsm;
         P.n_ctr = n_slots * kCtrSlot;
         TRY(dev_alloc(e, &P.ctr, P.n_ctr));
         P.cen_fan = P.ctr;
@@ -311,7 +311,7 @@ rtc_status persist_alloc(rtc_engine *e) {
         P.p_done = P.pol_cnt + D * nt * kCtrSlot;
         P.tile_pub = P.p_done + nt * kCtrSlot;
         P.ing_cnt = P.tile_pub + nt * kCtrSlot;
-        P.pol_seg = P.ing_cnt + D * nst * kCtrSlot;
+        P.pol_seg = P.ing_cnt + 2 * D * nst * kCtrSlot;
         P.head_cnt = P.pol_seg + D * nsm * kCtrSlot;
         TRY(dev_alloc(e, &P.pre, (size_t)kDepth * I->n_act));
         // serving ingest: each readout step's rows as 16-byte units of a ring
