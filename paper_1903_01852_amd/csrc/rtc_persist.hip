@@ -788,13 +788,33 @@ __device__ __forceinline__ FrameTasks frame_tasks(InstRef I, uint64_t q, int ran
 // index j (into the frame's task list) advances past the block.  Lane s
 // accumulates in cnt this worker's tasks on stripe s, counting tasks by their
 // frame index (global_idx: one barrier for the frame) or their block index.
-__device__ __forceinline__ void centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw, int lane,
-                               const SlopeOut &so, bool global_idx, int &j, uint32_t &cnt) {
+// ready() is asked, once the sensor's parameters and the first Shack-Hartmann
+// task's descriptor are in registers, whether the block's pixels have arrived
+// (a serving worker may wait for them there); false returns false with no task
+// done.
+template <class Ready>
+__device__ __forceinline__ bool centroid_tasks(InstRef I, uint64_t q, const KbWork &W, int nw,
+                                               int lane, const SlopeOut &so, bool global_idx,
+                                               int &j, uint32_t &cnt, Ready ready) {
     const int end = W.cen_base + W.n_cen;
-    if (j >= end) return;
+    if (j >= end) return true;
     const uint16_t *fr = frame_src(I, W.wfs, q);
     WfsParam P = ldc(I.wp + W.wfs);
     P.W = I.src_pitch[W.wfs];            // row pitch of the frame source
+    const int j0 = j;
+    ShUnit d0{};
+    float thr0 = 0.0f;
+    if (W.kind == RTC_WFS_SH) {
+        const int u = W.cu0 + (j0 - W.cen_base);
+        d0 = ldc(I.sh + u);
+        thr0 = gbl(I.sh_thr)[u];
+    }
+    // the scalar reads above complete before the wait (the pixel addresses
+    // depend on them anyway): a worker that waited then finds them in hand
+    // rather than in a cache its neighbours have since refilled
+    asm volatile("" ::"s"(fr), "s"(P.p), "s"(P.W), "s"(P.thr_mode), "s"(P.half), "s"(d0.row0),
+                 "s"(d0.col0), "s"(d0.cal), "s"(d0.pad));
+    if (!ready()) return false;
     // global normalisation: the sensor's one block waits for its whole frame,
     // and each wavefront forms the pupil sum itself (no cross-wavefront
     // dependency), in the per-launch path's order
@@ -812,13 +832,15 @@ __device__ __forceinline__ void centroid_tasks(InstRef I, uint64_t q, const KbWo
         if (stripe_lane(global_idx ? j : jc, lane)) ++cnt;
         if (W.kind == RTC_WFS_SH) {
             const int u = W.cu0 + jc;
-            const ShUnit d = ldc(I.sh + u);
+            const bool first = j == j0;
+            const ShUnit d = first ? d0 : ldc(I.sh + u);
+            const float thr = first ? thr0 : gbl(I.sh_thr)[u];
             if (I.serving)
-                sh_unit<STORE_AGENT, LOAD_AGENT>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
-                                                  I.sh_bg, I.ref, so, lane);
+                sh_unit<STORE_AGENT, LOAD_AGENT>(d, thr, fr, P, I.sh_dark, I.sh_flat, I.sh_bg,
+                                                  I.ref, so, lane);
             else
-                sh_unit<STORE_AGENT, LOAD_PLAIN>(d, gbl(I.sh_thr)[u], fr, P, I.sh_dark, I.sh_flat,
-                                                 I.sh_bg, I.ref, so, lane);
+                sh_unit<STORE_AGENT, LOAD_PLAIN>(d, thr, fr, P, I.sh_dark, I.sh_flat, I.sh_bg,
+                                                 I.ref, so, lane);
         } else {
             const int k = W.cu0 + jc * kWave + lane;
             if (k < W.cu1) {
@@ -834,6 +856,7 @@ __device__ __forceinline__ void centroid_tasks(InstRef I, uint64_t q, const KbWo
             }
         }
     }
+    return true;
 }
 
 // MVM tasks (segment x tile) of this worker in column block kb of frame q;
@@ -1095,19 +1118,23 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                 }
                 const KbWork W = ldc(I.kbw + S.kb);
                 if (ft.cen < W.cen_base + W.n_cen) {
-                    while (ic <= cs) {
-                        // (a step with no pixel units has nothing to count)
-                        const uint64_t *flag = ing_flag(I, q, ic);
-                        if (ldc(I.steps + ic).ing_n > 0 && ld_agent64(flag) < q + 1 &&
-                            !(slopes_only &&
-                              spin_until(flag, [&](uint64_t v) { return v >= q + 1; })))
-                            break;
-                        ++ic;
-                    }
-                    if (ic <= cs) break;
+                    // every step up to this one copied into device memory
+                    const auto ingested = [&] {
+                        while (ic <= cs) {
+                            // (a step with no pixel units has nothing to count)
+                            const uint64_t *flag = ing_flag(I, q, ic);
+                            if (ldc(I.steps + ic).ing_n > 0 && ld_agent64(flag) < q + 1 &&
+                                !(slopes_only &&
+                                  spin_until(flag, [&](uint64_t v) { return v >= q + 1; })))
+                                return false;
+                            ++ic;
+                        }
+                        tr.stamp(RTC_TRACE_CEN_START, lane);
+                        return true;
+                    };
                     uint32_t cnt = 0;
-                    tr.stamp(RTC_TRACE_CEN_START, lane);
-                    centroid_tasks(I, q, W, ro.cen_n, lane, so, false, ft.cen, cnt);
+                    if (!centroid_tasks(I, q, W, ro.cen_n, lane, so, false, ft.cen, cnt, ingested))
+                        break;
                     drain();
                     (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, S.kb), q, W.n_cen, cnt,
                                      lane);
@@ -1167,7 +1194,8 @@ __device__ __forceinline__ bool batch_centroids(InstRef I, ArgsRef A, uint64_t q
     int j = frame_tasks(I, q, rank, nw).cen;
     const int n_kb = I.n_kb, n_all = I.n_cen_all;
     for (int kb = 0; kb < n_kb && j < n_all; ++kb)
-        centroid_tasks(I, q, ldc(I.kbw + kb), nw, lane, so, true, j, cnt);
+        (void)centroid_tasks(I, q, ldc(I.kbw + kb), nw, lane, so, true, j, cnt,
+                             [] { return true; });
     drain();
     (void)fan_arrive(I, fan_grp(I.cen_fan, q, I.n_kb, 0), q, I.n_cen_all, cnt, lane);
     tr.stamp(RTC_TRACE_CENTROIDS, lane);
