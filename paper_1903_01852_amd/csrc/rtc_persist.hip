@@ -859,28 +859,37 @@ __device__ __forceinline__ bool centroid_tasks(InstRef I, uint64_t q, const KbWo
     return true;
 }
 
-// MVM tasks (segment x tile) of this worker in column block kb of frame q;
-// the block's slopes must be complete.  Each task counts on its tile's
-// counter; the arrival completing the tile's partials of the frame (every
-// segment of every block) is the tile's (E) party.
-__device__ __forceinline__ void mvm_tasks(InstRef I, ArgsRef A, uint64_t q, const KbWork &W, int kb,
+// MVM tasks (segment x tile) of this worker in column block kb of frame q.
+// Each task counts on its tile's counter; the arrival completing the tile's
+// partials of the frame (every segment of every block) is the tile's (E)
+// party.  ready() is asked, once the block's and the first task's segment
+// descriptors are in registers, whether the block's slopes are complete (a
+// serving worker may wait for them there); false returns false with no task
+// done.  The matrix slot is read after it: the swap word of a frame that has
+// not yet arrived may not be settled.
+template <class Ready>
+__device__ __forceinline__ bool mvm_tasks(InstRef I, ArgsRef A, uint64_t q, const KbWork &W, int kb,
                                           int nw, int lane, RTC_LDS float *lds, int &m, Trace &tr,
-                                          int budget = 1 << 30) {
+                                          int budget, Ready ready) {
     const int n_tiles = I.n_tiles;
     const int end = W.mvm_base + W.nseg * n_tiles;
-    if (m >= end) return;
+    if (m >= end) return true;
+    const KBlock K = ldc(I.kbs + kb);
+    const int m0 = m;
+    const Segment S0 = ldc(I.segs + W.seg0 + (m0 - W.mvm_base) / n_tiles);
+    asm volatile("" ::"s"(K.base), "s"(K.kv), "s"(K.spad), "s"(S0.v0), "s"(S0.nv));
+    if (!ready()) return false;
     if (tr.rec != nullptr && lane == 0 && gbl(tr.rec)[RTC_TRACE_MVM_FIRST] == 0)
         gbl(tr.rec)[RTC_TRACE_MVM_FIRST] = wall_clock64();
     const float *spad = I.s_pad[dslot(q)];
     const int E = vec_elems(I.dtype);
-    const KBlock K = ldc(I.kbs + kb);
     const int ms = mat_slot(I, q);
     for (; m < end && budget > 0; m += nw, --budget) {
         const int jm = m - W.mvm_base;
         const int sl = jm / n_tiles;
         const int t = jm - sl * n_tiles;
         const int sg = W.seg0 + sl;
-        const Segment Sg = ldc(I.segs + sg);
+        const Segment Sg = m == m0 ? S0 : ldc(I.segs + sg);
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
         const float v = seg_partial(I, ms, q, K, Sg, t, nr, lane, spad + K.spad + Sg.v0 * E, lds);
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
@@ -901,6 +910,7 @@ __device__ __forceinline__ void mvm_tasks(InstRef I, ArgsRef A, uint64_t q, cons
         tile_ready(I, A, q, t, lane, tr);
     }
     tr.stamp(RTC_TRACE_MVM_LAST, lane);
+    return true;
 }
 
 // This wavefront's timeline record of frame q, if recorded.
@@ -1156,12 +1166,15 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     ++ms;
                     continue;
                 }
-                if (block_ready(I, q, W, S.kb, mvm_only)) {
+                const auto slopes_in = [&] {
+                    if (!block_ready(I, q, W, S.kb, mvm_only)) return false;
                     if (S.kb == I.n_kb - 1 && !last_seen) {
                         tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
                         last_seen = true;
                     }
-                    mvm_tasks(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm, tr, 1);
+                    return true;
+                };
+                if (mvm_tasks(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm, tr, 1, slopes_in)) {
                     if (ft.mvm >= end) ++ms;
                     progressed = true;
                 }
@@ -1233,7 +1246,8 @@ __device__ __forceinline__ void batch_worker(InstRef I, ArgsRef A, int wid, int 
         int m = frame_tasks(I, q, rank, nw).mvm;
         const int n_kb = I.n_kb, n_all = I.n_seg * I.n_tiles;
         for (int kb = 0; kb < n_kb && m < n_all; ++kb)
-            mvm_tasks(I, A, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr);
+            (void)mvm_tasks(I, A, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr, 1 << 30,
+                            [] { return true; });
         if (I.polc && q > q0 && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
         trace_end(tr, lane);
     }
