@@ -106,20 +106,23 @@ __device__ __forceinline__ bool db_reached(uint64_t db, uint64_t q, uint64_t chu
     return dq > q || (dq == q && (db & kDbChunkMask) >= chunks);
 }
 
-// Bounded spin of a worker with nothing else to do: up to kSpinPolls loads of
-// one word, each tested with ok(value).  The pointer and the test are set
-// before the spin, so a poll costs one round trip to memory, where a pass of
-// the worker's main loop (which re-reads its tables to find the next piece of
-// work) costs several.  False when the bound is reached (the caller's main
-// loop then checks for a stop request before it spins again).
+// Spin of a worker with nothing else to do until ok(*p) holds, checking for a
+// stop request every kSpinPolls loads (false then).  The pointer and the test
+// are set before the spin, so a poll costs one round trip to memory, where a
+// pass of the worker's main loop (which re-reads its tables to find the next
+// piece of work) costs several; and the worker does not leave the spin, so
+// whatever it prepared before it (a matrix batch in flight) is still in hand
+// when the word changes.
 constexpr int kSpinPolls = 64;
 template <class Ok>
-__device__ __forceinline__ bool spin_until(const uint64_t *p, Ok ok) {
-    for (int k = 0; k < kSpinPolls; ++k) {
-        __builtin_amdgcn_s_sleep(1);
-        if (ok(ld_agent64(p))) return true;
+__device__ __forceinline__ bool spin_until(const uint64_t *p, Ok ok, ArgsRef A) {
+    for (;;) {
+        for (int k = 0; k < kSpinPolls; ++k) {
+            __builtin_amdgcn_s_sleep(1);
+            if (ok(ld_agent64(p))) return true;
+        }
+        if (stopping(A)) return false;
     }
-    return false;
 }
 
 
@@ -309,6 +312,79 @@ __device__ __forceinline__ int mat_slot(InstRef I, uint64_t q) {
         return q >= (w >> 1) ? s : 1 - s;
     }
     return q >= I.coef.q_mswitch ? I.coef.mslot[1] : I.coef.mslot[0];
+}
+
+// A serving worker's MVM task that may wait for its block's slopes: the first
+// matrix batch is in flight before the wait (its matrix slot read then is
+// right unless a swap settles during the wait: the slot is read again after
+// it and the batch reissued if it changed), so the wait ends into the slope
+// copy alone.  ok is false, with nothing computed, when ready() is; ms is the
+// frame's matrix slot.
+template <int DT, bool REV, class Ready>
+__device__ __forceinline__ float loop_task_early(InstRef I, uint64_t q, const KBlock &K,
+                                                 const Segment &S, int t, int nr, int lane,
+                                                 const float *xs, RTC_LDS float *lds, Ready ready,
+                                                 bool &ok, int &ms) {
+    constexpr int EL = Elem<DT>::E, U = kLoopBatch;
+    constexpr int kPer = (kLoopLdsFloats / 4 + kWave - 1) / kWave;
+    const int nb = (S.nv + U - 1) / U;
+    const int n4 = (nb + 1) * U * EL / 4;
+    const int64_t off = K.base + ((int64_t)t * kTileRows * K.kv + (int64_t)S.v0 * nr) * 16;
+    const int ms0 = mat_slot(I, q);
+    SegStream<U, false> ss;
+    ss.rs = __builtin_amdgcn_make_buffer_rsrc((void *)(I.cm[ms0] + off), (short)0,
+                                              S.nv * nr * 16, 0x00020000);
+    ss.nb = nb;
+    ss.voff = lane * 16;
+    ss.vstride = nr * 16;
+    vec16_t qa[U];
+    ss.load(qa, REV ? nb - 1 : 0);
+    if (!ready()) {
+        ok = false;
+        return 0.0f;
+    }
+    ms = mat_slot(I, q);
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void *)xs, (short)0, S.nv * EL * 4, 0x00020000);
+    lds4_t sv[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kWave + lane;
+        const vec16_t w = __builtin_amdgcn_raw_buffer_load_b128(rx, i * 16, 0, kBufAgent);
+        sv[j] = lds4_t{__uint_as_float(w.x), __uint_as_float(w.y), __uint_as_float(w.z),
+                       __uint_as_float(w.w)};
+    }
+    if (ms != ms0) {   // a matrix swap took effect with this frame
+        ss.rs = __builtin_amdgcn_make_buffer_rsrc((void *)(I.cm[ms] + off), (short)0,
+                                                  S.nv * nr * 16, 0x00020000);
+        ss.load(qa, REV ? nb - 1 : 0);
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int i = j * kWave + lane;
+        if (i < n4) ((RTC_LDS lds4_t *)lds)[i] = sv[j];
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): this wavefront's LDS writes done
+    __builtin_amdgcn_wave_barrier();
+    return seg_stream<DT, U, false, REV>(ss, qa, (const RTC_LDS lds4_t *)lds);
+}
+template <class Ready>
+__device__ __forceinline__ float seg_partial_early(InstRef I, uint64_t q, const KBlock &K,
+                                                   const Segment &S, int t, int nr, int lane,
+                                                   const float *xs, RTC_LDS float *lds,
+                                                   Ready ready, bool &ok, int &ms) {
+    const bool rev = (q & 1) != 0;
+    switch (I.dtype) {
+    case RTC_CM_F32:
+        return rev ? loop_task_early<RTC_CM_F32, true>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms)
+                   : loop_task_early<RTC_CM_F32, false>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms);
+    case RTC_CM_BF16:
+        return rev ? loop_task_early<RTC_CM_BF16, true>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms)
+                   : loop_task_early<RTC_CM_BF16, false>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms);
+    default:
+        return rev ? loop_task_early<RTC_CM_FP8, true>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms)
+                   : loop_task_early<RTC_CM_FP8, false>(I, q, K, S, t, nr, lane, xs, lds, ready, ok, ms);
+    }
 }
 
 // Telemetry: frame q is recorded when q is a multiple of the decimation, in
@@ -863,11 +939,12 @@ __device__ __forceinline__ bool centroid_tasks(InstRef I, uint64_t q, const KbWo
 // Each task counts on its tile's counter; the arrival completing the tile's
 // partials of the frame (every segment of every block) is the tile's (E)
 // party.  ready() is asked, once the block's and the first task's segment
-// descriptors are in registers, whether the block's slopes are complete (a
-// serving worker may wait for them there); false returns false with no task
-// done.  The matrix slot is read after it: the swap word of a frame that has
-// not yet arrived may not be settled.
-template <class Ready>
+// descriptors are in registers (EARLY: and the first task's first matrix
+// batch is in flight), whether the block's slopes are complete (a serving
+// worker may wait for them there); false returns false with no task done.
+// The matrix slot is settled only after it: the swap word of a frame that has
+// not yet arrived may be stale.
+template <bool EARLY, class Ready>
 __device__ __forceinline__ bool mvm_tasks(InstRef I, ArgsRef A, uint64_t q, const KbWork &W, int kb,
                                           int nw, int lane, RTC_LDS float *lds, int &m, Trace &tr,
                                           int budget, Ready ready) {
@@ -876,14 +953,30 @@ __device__ __forceinline__ bool mvm_tasks(InstRef I, ArgsRef A, uint64_t q, cons
     if (m >= end) return true;
     const KBlock K = ldc(I.kbs + kb);
     const int m0 = m;
-    const Segment S0 = ldc(I.segs + W.seg0 + (m0 - W.mvm_base) / n_tiles);
+    const int sg0 = W.seg0 + (m0 - W.mvm_base) / n_tiles;
+    const Segment S0 = ldc(I.segs + sg0);
     asm volatile("" ::"s"(K.base), "s"(K.kv), "s"(K.spad), "s"(S0.v0), "s"(S0.nv));
-    if (!ready()) return false;
-    if (tr.rec != nullptr && lane == 0 && gbl(tr.rec)[RTC_TRACE_MVM_FIRST] == 0)
-        gbl(tr.rec)[RTC_TRACE_MVM_FIRST] = wall_clock64();
+    const auto rdy = [&] {
+        if (!ready()) return false;
+        if (tr.rec != nullptr && lane == 0 && gbl(tr.rec)[RTC_TRACE_MVM_FIRST] == 0)
+            gbl(tr.rec)[RTC_TRACE_MVM_FIRST] = wall_clock64();
+        return true;
+    };
     const float *spad = I.s_pad[dslot(q)];
     const int E = vec_elems(I.dtype);
-    const int ms = mat_slot(I, q);
+    int ms = 0;
+    float v0 = 0.0f;                     // EARLY: the first task's partial
+    if constexpr (EARLY) {
+        const int t0 = (m0 - W.mvm_base) - (sg0 - W.seg0) * n_tiles;
+        const int nr0 = min(kTileRows, I.n_act - t0 * kTileRows);
+        bool ok = true;
+        v0 = seg_partial_early(I, q, K, S0, t0, nr0, lane, spad + K.spad + S0.v0 * E, lds, rdy,
+                               ok, ms);
+        if (!ok) return false;
+    } else {
+        if (!rdy()) return false;
+        ms = mat_slot(I, q);
+    }
     for (; m < end && budget > 0; m += nw, --budget) {
         const int jm = m - W.mvm_base;
         const int sl = jm / n_tiles;
@@ -891,7 +984,9 @@ __device__ __forceinline__ bool mvm_tasks(InstRef I, ArgsRef A, uint64_t q, cons
         const int sg = W.seg0 + sl;
         const Segment Sg = m == m0 ? S0 : ldc(I.segs + sg);
         const int nr = min(kTileRows, I.n_act - t * kTileRows);
-        const float v = seg_partial(I, ms, q, K, Sg, t, nr, lane, spad + K.spad + Sg.v0 * E, lds);
+        const float v = (EARLY && m == m0)
+                            ? v0
+                            : seg_partial(I, ms, q, K, Sg, t, nr, lane, spad + K.spad + Sg.v0 * E, lds);
         if (lane < nr) st_agent(I.y_part[dslot(q)] + (size_t)sg * I.n_act + t * kTileRows + lane, v);
         drain();
         uint64_t old = 0;
@@ -1046,11 +1141,11 @@ constexpr int kIngestWorkers = 32;       // ingest-only workers of a split insta
 constexpr int kSlopeShare = 4;           // 1 / kSlopeShare of the rest take the slopes
 // The slopes of column block kb of frame q are all stored; a worker with only
 // products to form (spin) waits for them in a bounded spin.
-__device__ __forceinline__ bool block_ready(InstRef I, uint64_t q, const KbWork &W, int kb,
-                                            bool spin) {
+__device__ __forceinline__ bool block_ready(InstRef I, ArgsRef A, uint64_t q, const KbWork &W,
+                                            int kb, bool spin) {
     uint64_t *grp = fan_grp(I.cen_fan, q, I.n_kb, kb);
     if (W.n_cen == 0 || fan_done(grp, q)) return true;   // (no arrival without slope tasks)
-    return spin && spin_until(fan_flag(grp), [&](uint64_t v) { return v >= q + 1; });
+    return spin && spin_until(fan_flag(grp), [&](uint64_t v) { return v >= q + 1; }, A);
 }
 
 __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, int rank, int nw, int lane,
@@ -1110,7 +1205,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     const uint64_t want = (uint64_t)S.chunk + 1;
                     if (!db_reached(ld_agent64(db), q, want) &&
                         !(ingest_only &&
-                          spin_until(db, [&](uint64_t v) { return db_reached(v, q, want); })))
+                          spin_until(db, [&](uint64_t v) { return db_reached(v, q, want); }, A)))
                         break;
                     tr.stamp(RTC_TRACE_INGEST_START, lane);
                     ingest_tasks(I, q, S, is, ro.ing_n, lane, ing);
@@ -1135,7 +1230,7 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                             const uint64_t *flag = ing_flag(I, q, ic);
                             if (ldc(I.steps + ic).ing_n > 0 && ld_agent64(flag) < q + 1 &&
                                 !(slopes_only &&
-                                  spin_until(flag, [&](uint64_t v) { return v >= q + 1; })))
+                                  spin_until(flag, [&](uint64_t v) { return v >= q + 1; }, A)))
                                 return false;
                             ++ic;
                         }
@@ -1167,14 +1262,20 @@ __device__ __forceinline__ void serving_worker(InstRef I, ArgsRef A, int wid, in
                     continue;
                 }
                 const auto slopes_in = [&] {
-                    if (!block_ready(I, q, W, S.kb, mvm_only)) return false;
+                    if (!block_ready(I, A, q, W, S.kb, mvm_only)) return false;
                     if (S.kb == I.n_kb - 1 && !last_seen) {
                         tr.stamp(RTC_TRACE_LAST_BLOCK, lane);
                         last_seen = true;
                     }
                     return true;
                 };
-                if (mvm_tasks(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm, tr, 1, slopes_in)) {
+                // a worker with only products to form issues its task's first
+                // matrix batch before it waits (the others ask first, so that a
+                // block that is not ready costs them no matrix traffic)
+                if (mvm_only ? mvm_tasks<true>(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm, tr,
+                                               1, slopes_in)
+                             : mvm_tasks<false>(I, A, q, W, S.kb, ro.mvm_n, lane, lds, ft.mvm,
+                                                tr, 1, slopes_in)) {
                     if (ft.mvm >= end) ++ms;
                     progressed = true;
                 }
@@ -1246,8 +1347,8 @@ __device__ __forceinline__ void batch_worker(InstRef I, ArgsRef A, int wid, int 
         int m = frame_tasks(I, q, rank, nw).mvm;
         const int n_kb = I.n_kb, n_all = I.n_seg * I.n_tiles;
         for (int kb = 0; kb < n_kb && m < n_all; ++kb)
-            (void)mvm_tasks(I, A, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr, 1 << 30,
-                            [] { return true; });
+            (void)mvm_tasks<false>(I, A, q, ldc(I.kbw + kb), kb, nw, lane, lds, m, tr, 1 << 30,
+                                   [] { return true; });
         if (I.polc && q > q0 && !polc_tasks(I, A, q - 1, rank, nw, lane, lds, tr)) return;
         trace_end(tr, lane);
     }
