@@ -203,6 +203,10 @@ __device__ __forceinline__ uint64_t *tiles_out(InstRef I, uint64_t q) {
 __device__ __forceinline__ uint64_t tiles_target(InstRef I, uint64_t q) {
     return par_target(I, q, (uint64_t)I.n_tiles);
 }
+// Raised by the last tile of frame q: waiters poll it, not the count.
+__device__ __forceinline__ uint64_t *tiles_flag(InstRef I, uint64_t q) {
+    return fan_flag(fan_grp(I.tile_fan, q, 1, 0));
+}
 
 // First task index of this worker among n tasks whose task 0 goes to `base`.
 __device__ __forceinline__ int first_task(int rank, int nw, int base) {
@@ -648,11 +652,15 @@ __device__ __forceinline__ void tile_commands(InstRef I, ArgsRef A, uint64_t q, 
     if (lane == 0 && I.serving)   // the tile's commands are in the mailbox
         __hip_atomic_store(gbl(I.tile_host + t), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     if (lane == 0) st_agent64(slot(I.tile_pub, t), q + 1);
-    if (lane == 0 && add_agent64(tiles_out(I, q), 1) + 1 == tiles_target(I, q) && I.serving) {
-        FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
-        __hip_atomic_store(gbl(&tel->ticks_publish), wall_clock64(), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(gbl(I.cmd_seq), q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (lane == 0 && add_agent64(tiles_out(I, q), 1) + 1 == tiles_target(I, q)) {
+        st_agent64(tiles_flag(I, q), q + 1);
+        if (I.serving) {
+            FrameTel *tel = I.tel + (q % (uint64_t)I.ring_depth);
+            __hip_atomic_store(gbl(&tel->ticks_publish), wall_clock64(), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(gbl(I.cmd_seq), q + 1, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
@@ -1023,7 +1031,7 @@ __device__ __forceinline__ void trace_end(Trace &tr, int lane) {
 // Frame gate: frame q reuses the buffers and counters of frame q - kDepth.
 __device__ __forceinline__ bool gate(InstRef I, ArgsRef A, uint64_t q) {
     return q < I.q_begin + kDepth ||
-           wait_geq(tiles_out(I, q), tiles_target(I, q - kDepth), A, A.dep_watchdog);
+           wait_geq(tiles_flag(I, q), q - kDepth + 1, A, A.dep_watchdog);
 }
 
 // Serving ingest: copy this worker's pieces of readout step `st` (frame q)
@@ -1087,7 +1095,7 @@ __device__ __forceinline__ bool tel_copy_tasks(InstRef I, ArgsRef A, uint64_t q,
     const int n_tasks = (n16 + kTelUnits - 1) / kTelUnits;
     int j = first_task(rank, nw, rot(q, n_tasks, nw));
     if (j >= n_tasks) return true;
-    if (!wait_geq(tiles_out(I, q), tiles_target(I, q), A, A.dep_watchdog))
+    if (!wait_geq(tiles_flag(I, q), q + 1, A, A.dep_watchdog))
         return false;
     const uint64_t ts = (q >> I.tel_dshift) & (uint64_t)I.tel_smask;
     const int bytes = n16 * 16;
