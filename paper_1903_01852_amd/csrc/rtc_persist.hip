@@ -425,13 +425,24 @@ __device__ __forceinline__ void sentinel(InstRef I, ArgsRef A, int lane) {
     uint64_t last_drop = ~0ull;
     uint64_t seen_q = I.q_begin;   // next frame whose last chunk has not been stamped
     uint64_t t_change = wall_clock64();
+    // One poll of the host words, the doorbells first: parameters are read
+    // after the doorbells and mirrored before them, so a doorbell seen here
+    // was rung after any parameter change it follows; drop marks likewise (the
+    // host writes a frame's mark before the doorbells that complete it).
+    uint64_t db_n = 0, word_n = 0, mword_n = 0, dm_n = 0;
+    const auto poll = [&] {
+        if (lane < nw) db_n = ld_sys64(I.doorbell + lane);
+        word_n = ld_sys64(&I.params->word);
+        mword_n = ld_sys64(&I.params->mword);
+        if (lane < I.ring_depth) dm_n = ld_sys64(I.drop_host + lane);
+    };
+    poll();
     for (uint32_t it = 0;; ++it) {
-        uint64_t db = 0;
-        if (lane < nw) db = ld_sys64(I.doorbell + lane);
-        // parameters are read after the doorbells and mirrored before them:
-        // a doorbell seen here was rung after any parameter change it follows
-        const uint64_t word = ld_sys64(&I.params->word);
-        const uint64_t mword = ld_sys64(&I.params->mword);
+        // the next poll is in flight while this one is processed: a read
+        // across PCIe takes about a microsecond, and two in flight halve the
+        // time from a doorbell's store to its being seen
+        const uint64_t db = db_n, word = word_n, mword = mword_n, dm = dm_n;
+        poll();
         if (word != last_word || mword != last_mword) {
             if (lane < 2) {
                 const float c1 = __hip_atomic_load(gbl(&I.params->c1[lane]), __ATOMIC_RELAXED,
@@ -451,10 +462,6 @@ __device__ __forceinline__ void sentinel(InstRef I, ArgsRef A, int lane) {
             last_word = word;
             last_mword = mword;
         }
-        // drop marks likewise: the host writes a frame's mark before the
-        // doorbells that complete it
-        uint64_t dm = 0;
-        if (lane < I.ring_depth) dm = ld_sys64(I.drop_host + lane);
         if (lane < I.ring_depth && dm != last_drop) {
             st_agent64(I.drop_mirror + lane, dm);
             last_drop = dm;
