@@ -443,6 +443,10 @@ __device__ __forceinline__ void sentinel(InstRef I, ArgsRef A, int lane) {
         // time from a doorbell's store to its being seen
         const uint64_t db = db_n, word = word_n, mword = mword_n, dm = dm_n;
         poll();
+        // mirror stores of this pass that a doorbell mirrored after them must
+        // follow (the wait for them also waits for the poll in flight, so it
+        // is taken only when there are any)
+        bool mirrored = false;
         if (word != last_word || mword != last_mword) {
             if (lane < 2) {
                 const float c1 = __hip_atomic_load(gbl(&I.params->c1[lane]), __ATOMIC_RELAXED,
@@ -461,14 +465,17 @@ __device__ __forceinline__ void sentinel(InstRef I, ArgsRef A, int lane) {
             }
             last_word = word;
             last_mword = mword;
+            mirrored = true;
         }
-        if (lane < I.ring_depth && dm != last_drop) {
+        const bool drop_changed = lane < I.ring_depth && dm != last_drop;
+        if (drop_changed) {
             st_agent64(I.drop_mirror + lane, dm);
             last_drop = dm;
         }
+        mirrored = mirrored || __any(drop_changed);
         const bool changed = lane < nw && db != last;
         if (__any(changed)) {
-            drain();
+            if (mirrored) drain();
             if (changed) st_agent64(I.db_mirror + lane, db);
             last = db;
             t_change = wall_clock64();
