@@ -16,4 +16,16 @@ inline bool mailbox_copy_whole(uint64_t seq_after_copy, uint64_t q, uint64_t dep
     return seq_after_copy <= q + depth;
 }
 
+// Each of n tiles raises its flag to q + 1 once its commands of frame q are in
+// the mailbox, and a tile's frames are integrated in order, so its flag only
+// grows: frame q is out when every flag has reached q + 1.  Scanning from
+// tile `from` (the tiles before it known to have), returns the first tile
+// whose flag (flag(t), an acquire load) has not, or n.
+template <class Flag>
+inline int tiles_ready_from(Flag flag, int n, uint64_t q, int from) {
+    int t = from;
+    while (t < n && flag(t) >= q + 1) ++t;
+    return t;
+}
+
 }  // namespace rtc

@@ -816,7 +816,7 @@ rtc_status persist_wait(rtc_engine *e, Instance *I, uint64_t frame, float *cmds,
     const int nt = I->n_tiles;
     int tk = 0;      // tiles before tk are known ready
     for (;;) {
-        while (tk < nt && load_acquire(P.tile_host + tk) >= q + 1) ++tk;
+        tk = tiles_ready_from([&](int t) { return load_acquire(P.tile_host + t); }, nt, q, tk);
         if (tk == nt || load_acquire(P.cmd_seq) >= q + 1) break;
         if (now_ns() - t0 > timeout_ns) return RTC_E_TIMEOUT;
         if (e->pe.running && stream_done(e->pe.stream)) return fail(e, RTC_E_DEVICE);

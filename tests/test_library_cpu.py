@@ -146,3 +146,75 @@ int main() {
         [str(exe)], check=True, capture_output=True, text=True, timeout=120).stdout.split())
     assert torn == 0
     assert accepted > 100
+
+
+def test_tile_flags_mark_a_frame_out_only_when_every_tile_is(tmp_path):
+    """The waiter's readiness test on the per-tile flags: fixed cases (a flag
+    short of the frame stops the scan, a tile already on a later frame counts,
+    the scan resumes where it stopped), then writer threads that each own some
+    tiles and, frame by frame in order, store a tile's value and then raise its
+    flag (release) in a shuffled tile order, against a reader that waits for
+    each frame with the scan (acquire loads) and checks every tile's value."""
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    src = tmp_path / "flags.cpp"
+    src.write_text(r'''
+#include <algorithm>
+#include <atomic>
+#include <cstdio>
+#include <random>
+#include <thread>
+#include <vector>
+#include "rtc_seq.h"
+int main() {
+    int bad = 0;
+    {
+        const uint64_t f[5] = {5, 5, 5, 4, 7};
+        auto at = [&](int t) { return f[t]; };
+        bad += rtc::tiles_ready_from(at, 5, 4, 0) != 3;     // tile 3 still on frame 3
+        bad += rtc::tiles_ready_from(at, 5, 3, 0) != 5;     // every tile past frame 3
+        bad += rtc::tiles_ready_from(at, 5, 4, 4) != 5;     // resumed after tile 3
+        bad += rtc::tiles_ready_from(at, 0, 9, 0) != 0;     // no tiles: out
+    }
+    const int n = 96, n_writers = 4;
+    const uint64_t n_frames = 20000;
+    std::vector<std::atomic<uint64_t>> flag(n), val(n);
+    for (int t = 0; t < n; ++t) { flag[t].store(0); val[t].store(~0ull); }
+    std::vector<std::thread> writers;
+    for (int w = 0; w < n_writers; ++w)
+        writers.emplace_back([&, w] {
+            std::mt19937 rng(w);
+            std::vector<int> mine;
+            for (int t = w; t < n; t += n_writers) mine.push_back(t);
+            for (uint64_t q = 0; q < n_frames; ++q) {
+                std::shuffle(mine.begin(), mine.end(), rng);
+                for (int t : mine) {
+                    val[t].store(q, std::memory_order_relaxed);
+                    flag[t].store(q + 1, std::memory_order_release);
+                }
+            }
+        });
+    uint64_t torn = 0;
+    for (uint64_t q = 0; q < n_frames; q += 7) {
+        int tk = 0;
+        while (tk < n)
+            tk = rtc::tiles_ready_from(
+                [&](int t) { return flag[t].load(std::memory_order_acquire); }, n, q, tk);
+        for (int t = 0; t < n; ++t) torn += val[t].load(std::memory_order_relaxed) < q;
+    }
+    for (auto &w : writers) w.join();
+    std::printf("%d %llu\n", bad, (unsigned long long)torn);
+    return 0;
+}
+''')
+    exe = tmp_path / "flags"
+    csrc = os.path.join(ROOT, "paper_1903_01852_amd", "csrc")
+    subprocess.run([cxx, "-O2", "-std=c++17", f"-I{csrc}", str(src), "-o", str(exe), "-lpthread"],
+                   check=True)
+    bad, torn = map(int, subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True, timeout=120).stdout.split())
+    assert bad == 0
+    assert torn == 0
